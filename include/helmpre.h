@@ -1,0 +1,173 @@
+/*
+ * helmpre — C ABI of the MI355X (gfx950) implementation of the interpolated
+ * pseudodifferential preconditioner for the variable-media Helmholtz equation
+ *     c^2 Lap u + omega^2 u + i omega a u = f            (Eqn. 001)
+ * of Acosta, Khajah and Palacios (arXiv 2409.16172), together with the
+ * finite-difference operator P_N it preconditions and a restarted GMRES solver.
+ *
+ * Conventions shared by every entry point
+ *   - Grids: d = 2 or 3 dimensions, n[j] points per axis, each a power of two in
+ *     [8, 2048] (FP64 plans) or [8, 4096] (mixed plans); side len[j]; spacing
+ *     h_j = len[j]/n[j]; periodic boundary conditions (Section 5).
+ *   - Fields: row-major with the last axis contiguous, complex interleaved
+ *     (re, im); several right-hand sides are stored one after another
+ *     ("batch outermost": [nrhs][n0][n1]([n2])).
+ *   - Host arrays (media, options) are read during the call and copied; the
+ *     library never keeps a host pointer.  Device arrays are HIP device memory
+ *     owned by the caller.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  apply and matvec
+ *     only enqueue work; they allocate nothing and return before it completes.
+ *   - Errors are status codes; argument and media errors are detected before
+ *     anything is enqueued.  No C++ exception crosses this interface.
+ *   - A plan is not re-entrant: calls on one plan must not overlap (they share
+ *     the plan's workspace).  Distinct plans are independent.
+ */
+#ifndef HELMPRE_H
+#define HELMPRE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp_plan_s* hp_plan;
+
+typedef enum {
+  HP_OK = 0,
+  HP_E_INVALID = 1,        /* bad argument or option                                 */
+  HP_E_SHAPE = 2,          /* grid size not supported                                 */
+  HP_E_MEDIA = 3,          /* media not finite / not positive, or a zero symbol denominator */
+  HP_E_LAYER = 4,          /* c differs from the background c0 where zeta > 0        */
+  HP_E_NONFINITE = 5,      /* non-finite right-hand side                              */
+  HP_E_DEVICE = 6,         /* a HIP call failed                                       */
+  HP_E_NOMEM = 7,          /* device allocation failed                                */
+  HP_E_NOT_CONVERGED = 8   /* solve stopped at max_cycles above the tolerance         */
+} hp_status;
+
+typedef enum { HP_FP64 = 0, HP_MIXED = 1 } hp_precision;
+typedef enum { HP_SYMBOL_CONTINUOUS = 0, HP_SYMBOL_DISCRETE = 1 } hp_symbol;
+
+typedef struct {
+  int dim;          /* 2 or 3                                        */
+  int n[3];         /* points per axis (n[2] ignored when dim = 2)  */
+  double len[3];    /* side lengths                                  */
+} hp_grid;
+
+/* Absorbing layer by a complex wave speed gamma = c (1 - i zeta)
+ * (Eqn. Complex_wave_speed).  The medium must satisfy c = c0 wherever
+ * zeta > 0 (Section 4.3); zeta >= 0 on the host, n[0]*...*n[d-1] values. */
+typedef struct {
+  const double* zeta;   /* host, may be NULL (no layer)        */
+  double c0;            /* background speed c_o (> 0)          */
+} hp_layer;
+
+/* Preconditioner options.
+ *   m_real     M: real-axis interpolation nodes (Section 4.1).  1 gives the
+ *              one-node preconditioner Q_1 of Eqn. OneInterpPoint (node c0,
+ *              no layer nodes).  With a layer c0 is always a node and M >= 3.
+ *   m_layer    M~: layer nodes zeta_1..zeta_M~ (Section 4.3), >= 1 when a layer is given.
+ *   nodes_real optional explicit increasing real nodes (host, m_real values)
+ *   nodes_zeta optional explicit increasing layer nodes (host, m_layer values > 0)
+ *   a_nodes    optional damping a(c_m) at the real nodes (host, m_real values)
+ *   a_floor    lower bound applied to the symbol damping of real nodes (the
+ *              operator P_N keeps the true a); 0 disables it
+ *   symbol     HP_SYMBOL_CONTINUOUS: |xi|^2 as in Eqn. 021;
+ *              HP_SYMBOL_DISCRETE: the 5/7-point stencil's own symbol
+ *   precision  HP_FP64, or HP_MIXED (FFTs, symbol multiply, combine and the
+ *              Arnoldi stencil in FP32; orthogonalisation, least squares, true
+ *              residual and set-up in FP64)
+ *   max_nrhs   largest batch one apply/matvec call processes at once (>= 1);
+ *              larger batches are processed in chunks                          */
+typedef struct {
+  int m_real;
+  int m_layer;
+  const double* nodes_real;
+  const double* nodes_zeta;
+  const double* a_nodes;
+  double a_floor;
+  int symbol;
+  int precision;
+  int max_nrhs;
+} hp_plan_opts;
+
+/* Right-preconditioned restarted GMRES(restart): solves P_N Q y = f, x = Q y,
+ * starting from the x passed in.  Stops when the FP64 true residual
+ * ||f - P_N x||_2 <= rtol ||f||_2 at a restart, or after max_cycles cycles. */
+typedef struct {
+  int restart;       /* 1..64                 */
+  int max_cycles;    /* >= 1                  */
+  double rtol;       /* > 0                   */
+} hp_solve_opts;
+
+typedef struct {
+  int iters;                 /* Arnoldi steps taken                    */
+  int cycles;                /* restart cycles run                     */
+  double rel_true_residual;  /* ||f - P_N x|| / ||f|| at return (FP64) */
+  int status;                /* HP_OK or HP_E_NOT_CONVERGED            */
+} hp_solve_info;
+
+/* Read-only description of a plan (for tests and reports). */
+typedef struct {
+  int dim, n[3];
+  int K, M, Mt, mo;          /* node fields, real nodes, layer nodes, index of c0 */
+  double cmin, cmax, zeta_max;
+  double cnode[64];          /* real nodes                  */
+  double znode[65];          /* zeta_0 = 0, zeta_1..zeta_Mt */
+  double ahat[64];           /* symbol damping per node     */
+  double gamma_re[64], gamma_im[64];  /* node speeds gamma_n (K) */
+  size_t workspace_bytes;    /* device bytes held by the plan for apply/matvec */
+  int precision;
+} hp_plan_info;
+
+/* Build a plan: validate the media, place the nodes, and compute in FP64 on the
+ * host the per-point interpolation records, the stencil coefficients and the
+ * symbol tables, then upload them (Section 4, Eqn. 021, 403/405; Section 5).
+ *   c      host, wave speed > 0 at every point
+ *   a      host damping >= 0 at every point, or NULL (a = 0)
+ *   layer  NULL: no absorbing layer
+ * Errors: HP_E_INVALID, HP_E_SHAPE, HP_E_MEDIA (non-finite or non-positive
+ * media, or a symbol denominator that vanishes on the grid), HP_E_LAYER,
+ * HP_E_NOMEM, HP_E_DEVICE.  On error *out is NULL. */
+hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const double* c,
+                         const double* a, const hp_layer* layer, const hp_plan_opts* opts,
+                         void* stream);
+
+/* Device bytes a plan with these options holds for apply/matvec (excluding the
+ * solver's Krylov storage), and the solver's extra bytes for nrhs and restart. */
+size_t hp_plan_workspace_bytes(const hp_grid* grid, const hp_plan_opts* opts, int K);
+size_t hp_solve_workspace_bytes(const hp_grid* grid, int restart, int nrhs);
+
+hp_status hp_plan_query(hp_plan p, hp_plan_info* info);
+
+/* u = Q_M v (Eqn. 403): one forward FFT of each field, K symbol multiplies and
+ * inverse FFTs, and the pointwise combine with the piecewise-linear weights of
+ * the local complex speed.  v, u: device, nrhs fields, complex128 for FP64
+ * plans and complex64 for mixed plans.  u == v is allowed. */
+hp_status hp_apply_precond(hp_plan p, const void* v, void* u, int nrhs, void* stream);
+
+/* y = P_N u: second-order centred differences of Eqn. 003 with periodic
+ * boundaries, gamma^2 in place of c^2 (Section 4.3, Section 5).  Same dtypes as
+ * apply.  y must not alias u. */
+hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
+
+/* Restarted GMRES on P_N x = f with right preconditioner Q_M (the left form of
+ * Eqn. MainDiscretePrecond rearranged so that the residual GMRES minimises is
+ * the true one).  f, x: device complex128 [nrhs][N^d] whatever the plan
+ * precision; x holds the initial guess on entry and the solution on return.
+ * info: host array of nrhs entries.  Blocks until every right-hand side has
+ * converged or max_cycles is reached.  Krylov storage is allocated on first
+ * use and kept by the plan.  Returns HP_E_NOT_CONVERGED if any right-hand side
+ * stopped above rtol (x and info are filled in any case). */
+hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts,
+                   hp_solve_info* info, void* stream);
+
+hp_status hp_plan_destroy(hp_plan p);
+
+const char* hp_status_str(hp_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELMPRE_H */

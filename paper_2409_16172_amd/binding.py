@@ -1,0 +1,263 @@
+"""Thin ctypes binding of libhelmpre.so (the C ABI declared in include/helmpre.h).
+
+Only argument marshalling happens here: every step of the preconditioner, the
+stencil and the solver runs in the HIP library.  PyTorch provides the device
+memory (tensors on the GPU) and the stream.  If the library is not built, or no
+GPU is present, the calls raise: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelmpre.so")
+
+HP_OK, HP_E_INVALID, HP_E_SHAPE, HP_E_MEDIA, HP_E_LAYER = 0, 1, 2, 3, 4
+HP_E_NONFINITE, HP_E_DEVICE, HP_E_NOMEM, HP_E_NOT_CONVERGED = 5, 6, 7, 8
+HP_FP64, HP_MIXED = 0, 1
+SYMBOLS = {"continuous": 0, "discrete": 1}
+PRECISIONS = {"fp64": HP_FP64, "mixed": HP_MIXED}
+
+EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_bytes", "hp_plan_query",
+            "hp_apply_precond", "hp_matvec", "hp_solve", "hp_plan_destroy", "hp_status_str"]
+
+
+class HpGrid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("len", C.c_double * 3)]
+
+
+class HpLayer(C.Structure):
+    _fields_ = [("zeta", C.c_void_p), ("c0", C.c_double)]
+
+
+class HpPlanOpts(C.Structure):
+    _fields_ = [("m_real", C.c_int), ("m_layer", C.c_int), ("nodes_real", C.c_void_p),
+                ("nodes_zeta", C.c_void_p), ("a_nodes", C.c_void_p), ("a_floor", C.c_double),
+                ("symbol", C.c_int), ("precision", C.c_int), ("max_nrhs", C.c_int)]
+
+
+class HpSolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double)]
+
+
+class HpSolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_true_residual", C.c_double),
+                ("status", C.c_int)]
+
+
+class HpPlanInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("K", C.c_int), ("M", C.c_int), ("Mt", C.c_int),
+                ("mo", C.c_int), ("cmin", C.c_double), ("cmax", C.c_double), ("zeta_max", C.c_double),
+                ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
+                ("gamma_re", C.c_double * 64), ("gamma_im", C.c_double * 64),
+                ("workspace_bytes", C.c_size_t), ("precision", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhelmpre.so (raises OSError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is not built; run __graft_entry__.build() or "
+                      "python paper_2409_16172_amd/build.py")
+    lib = C.CDLL(path)
+    vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    lib.hp_plan_create.argtypes = [C.POINTER(vp), C.POINTER(HpGrid), d, vp, vp, C.POINTER(HpLayer),
+                                   C.POINTER(HpPlanOpts), vp]
+    lib.hp_plan_create.restype = i
+    lib.hp_plan_workspace_bytes.argtypes = [C.POINTER(HpGrid), C.POINTER(HpPlanOpts), i]
+    lib.hp_plan_workspace_bytes.restype = sz
+    lib.hp_solve_workspace_bytes.argtypes = [C.POINTER(HpGrid), i, i]
+    lib.hp_solve_workspace_bytes.restype = sz
+    lib.hp_plan_query.argtypes = [vp, C.POINTER(HpPlanInfo)]
+    lib.hp_plan_query.restype = i
+    lib.hp_apply_precond.argtypes = [vp, vp, vp, i, vp]
+    lib.hp_apply_precond.restype = i
+    lib.hp_matvec.argtypes = [vp, vp, vp, i, vp]
+    lib.hp_matvec.restype = i
+    lib.hp_solve.argtypes = [vp, vp, vp, i, C.POINTER(HpSolveOpts), C.POINTER(HpSolveInfo), vp]
+    lib.hp_solve.restype = i
+    lib.hp_plan_destroy.argtypes = [vp]
+    lib.hp_plan_destroy.restype = i
+    lib.hp_status_str.argtypes = [i]
+    lib.hp_status_str.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class HelmpreError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = load_library().hp_status_str(code).decode()
+        super().__init__(f"{where}: {msg} (status {code})")
+        self.code = code
+
+
+def _check(code: int, where: str):
+    if code != HP_OK:
+        raise HelmpreError(code, where)
+
+
+def _host(a, shape):
+    if a is None:
+        return None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if arr.size != int(np.prod(shape)):
+        raise ValueError(f"expected {int(np.prod(shape))} values, got {arr.size}")
+    return arr
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    cycles: int
+    rel_true_residual: float
+    status: int
+
+
+class Plan:
+    """Preconditioner plan: media, nodes, tables and workspace on the GPU.
+
+    shape: grid points per axis (2 or 3 axes, powers of two); length: side L.
+    c, a, zeta: host arrays of that shape (a and zeta optional).
+    precision: "fp64" (complex128 apply/matvec) or "mixed" (complex64 apply/matvec,
+    FP64 orthogonalisation and residuals in solve).
+    """
+
+    def __init__(self, shape, omega, c, a=None, zeta=None, *, length=1.0, c0=1.0, m_real=8,
+                 m_layer=3, symbol="continuous", precision="fp64", a_floor=0.0, max_nrhs=1,
+                 nodes_real=None, nodes_zeta=None, a_nodes=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("helmpre needs a ROCm GPU (torch.cuda.is_available() is False)")
+        lib = load_library()
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        self.precision = precision
+        self.npts = int(np.prod(self.shape))
+        g = HpGrid()
+        g.dim = self.dim
+        for k, n in enumerate(self.shape):
+            g.n[k] = n
+            g.len[k] = float(length)
+        self._grid = g
+        keep = [_host(c, self.shape), _host(a, self.shape), _host(zeta, self.shape)]
+        nr = None if nodes_real is None else np.ascontiguousarray(nodes_real, dtype=np.float64)
+        nz = None if nodes_zeta is None else np.ascontiguousarray(nodes_zeta, dtype=np.float64)
+        an = None if a_nodes is None else np.ascontiguousarray(a_nodes, dtype=np.float64)
+        o = HpPlanOpts()
+        o.m_real = int(m_real if nr is None else nr.size)
+        o.m_layer = int(m_layer if nz is None else nz.size)
+        o.nodes_real = None if nr is None else nr.ctypes.data
+        o.nodes_zeta = None if nz is None else nz.ctypes.data
+        o.a_nodes = None if an is None else an.ctypes.data
+        o.a_floor = float(a_floor)
+        o.symbol = SYMBOLS[symbol]
+        o.precision = PRECISIONS[precision]
+        o.max_nrhs = int(max_nrhs)
+        self._opts = o
+        lay = HpLayer()
+        lay.zeta = None if keep[2] is None else keep[2].ctypes.data
+        lay.c0 = float(c0)
+        h = C.c_void_p()
+        code = lib.hp_plan_create(C.byref(h), C.byref(g), float(omega), keep[0].ctypes.data,
+                                  None if keep[1] is None else keep[1].ctypes.data, C.byref(lay),
+                                  C.byref(o), _stream(stream))
+        _check(code, "hp_plan_create")
+        self._h = h
+        self.omega = float(omega)
+
+    # dtype of apply / matvec fields
+    @property
+    def field_dtype(self):
+        import torch
+        return torch.complex128 if self.precision == "fp64" else torch.complex64
+
+    def info(self) -> dict:
+        pi = HpPlanInfo()
+        _check(load_library().hp_plan_query(self._h, C.byref(pi)), "hp_plan_query")
+        K = pi.K
+        return {"K": K, "M": pi.M, "Mt": pi.Mt, "mo": pi.mo, "cmin": pi.cmin, "cmax": pi.cmax,
+                "zeta_max": pi.zeta_max, "cnode": np.array(pi.cnode[:pi.M]),
+                "znode": np.array(pi.znode[:pi.Mt + 1]), "ahat": np.array(pi.ahat[:K]),
+                "gamma": np.array(pi.gamma_re[:K]) + 1j * np.array(pi.gamma_im[:K]),
+                "workspace_bytes": int(pi.workspace_bytes)}
+
+    def _fields(self, x, dtype, name):
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError(f"{name} must be a CUDA/HIP tensor")
+        if x.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if tuple(x.shape[-self.dim:]) != self.shape:
+            raise ValueError(f"{name} has shape {tuple(x.shape)}, grid is {self.shape}")
+        return x.numel() // self.npts
+
+    def apply(self, v, out=None, stream=None):
+        """u = Q_M v for one field or a batch [nrhs, *shape]."""
+        import torch
+        nr = self._fields(v, self.field_dtype, "v")
+        u = torch.empty_like(v) if out is None else out
+        self._fields(u, self.field_dtype, "out")
+        _check(load_library().hp_apply_precond(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()),
+                                               nr, _stream(stream)), "hp_apply_precond")
+        return u
+
+    def matvec(self, u, out=None, stream=None):
+        """y = P_N u for one field or a batch."""
+        import torch
+        nr = self._fields(u, self.field_dtype, "u")
+        y = torch.empty_like(u) if out is None else out
+        self._fields(y, self.field_dtype, "out")
+        _check(load_library().hp_matvec(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(y.data_ptr()), nr,
+                                        _stream(stream)), "hp_matvec")
+        return y
+
+    def solve(self, f, x=None, *, restart=30, max_cycles=200, rtol=1e-8, stream=None, raise_on_fail=False):
+        """Right-preconditioned restarted GMRES.  f (and x) complex128; returns (x, [SolveInfo])."""
+        import torch
+        nr = self._fields(f, torch.complex128, "f")
+        if x is None:
+            x = torch.zeros_like(f)
+        self._fields(x, torch.complex128, "x")
+        o = HpSolveOpts(int(restart), int(max_cycles), float(rtol))
+        infos = (HpSolveInfo * nr)()
+        code = load_library().hp_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()), nr,
+                                       C.byref(o), infos, _stream(stream))
+        if code not in (HP_OK, HP_E_NOT_CONVERGED) or (raise_on_fail and code != HP_OK):
+            raise HelmpreError(code, "hp_solve")
+        return x, [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status) for i in infos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().hp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_from_workload(w, **over):
+    """Plan for a synthetic workload from paper_2409_16172_amd.inputs."""
+    kw = dict(length=w.length, c0=w.c0, m_real=w.m_real, m_layer=w.m_layer, a_floor=w.a_floor,
+              precision=w.precision, max_nrhs=w.f.shape[0])
+    kw.update(over)
+    return Plan(w.shape, w.omega, w.c, w.a, w.zeta, **kw)

@@ -1,0 +1,680 @@
+// Host side of the library: plan set-up in FP64 (node placement, per-point
+// interpolation records, stencil coefficients, symbol and twiddle tables), the
+// enqueue sequences of apply and matvec, and the restarted-GMRES driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/helmpre.h"
+#include "hp_internal.h"
+
+using hp::cpx;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t alloc(size_t b) {
+    release();
+    if (b == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    bytes = b;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+struct hp_plan_s {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  double len[3] = {1, 1, 1};
+  size_t npts = 0;
+  double omega = 0;
+  int prec = HP_FP64;
+  int symbol = HP_SYMBOL_CONTINUOUS;
+  int max_nrhs = 1;
+  // nodes
+  int K = 1, M = 1, Mt = 0, mo = 0;
+  double cmin = 0, cmax = 0, zmax = 0;
+  double cnode[64] = {0}, znode[65] = {0}, ahat[64] = {0}, gre[64] = {0}, gim[64] = {0};
+  // device data
+  DevBuf nodes, pos, grpmask, coef64, coef32, lam_ax, lam_in, tw64[3], tw32[3];
+  DevBuf t, fields;                  // apply workspace
+  // solver workspace
+  DevBuf V, z, tvec, state, part, flags;
+  int ws_restart = 0, ws_nrhs = 0;
+  void* pinned = nullptr;
+
+  int real_kind() const { return prec == HP_FP64 ? 0 : 1; }
+  size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
+  const void* tw(int axis) const { return prec == HP_FP64 ? tw64[axis].p : tw32[axis].p; }
+  void release_all() {
+    for (DevBuf* b : {&nodes, &pos, &grpmask, &coef64, &coef32, &lam_ax, &lam_in, &t, &fields, &V, &z, &tvec,
+                      &state, &part, &flags})
+      b->release();
+    for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+  }
+};
+
+namespace {
+
+hp_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return HP_OK;
+  if (e == hipErrorOutOfMemory) return HP_E_NOMEM;
+  return HP_E_DEVICE;
+}
+
+#define HP_TRY(expr)                         \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
+// Real interpolation nodes (Section 4.1); with an absorbing layer the
+// background speed c0 must be one of them (Section 4.3).  Reading: two
+// equidistant runs on [cmin, c0] and [c0, cmax]; the number of intervals below
+// c0 is the nearest integer (ties downwards) to (c0-cmin)/(cmax-cmin)*(M-1),
+// kept in [1, M-2] when c0 is strictly inside (M raised to 3 if smaller).
+hp_status place_real_nodes(hp_plan_s& P, const hp_plan_opts& o, double c0, bool layer) {
+  int M = o.m_real;
+  if (M < 1 || M > hp::kMaxNodes) return HP_E_INVALID;
+  if (o.nodes_real) {
+    for (int i = 0; i < M; ++i) {
+      double v = o.nodes_real[i];
+      if (!(v > 0) || !std::isfinite(v) || (i && !(v > o.nodes_real[i - 1]))) return HP_E_INVALID;
+      P.cnode[i] = v;
+    }
+    P.M = M;
+    P.mo = -1;
+    for (int i = 0; i < M; ++i)
+      if (P.cnode[i] == c0) P.mo = i;
+    if (layer && P.mo < 0) return HP_E_LAYER;
+    if (P.mo < 0) P.mo = 0;
+    return HP_OK;
+  }
+  if (M == 1) {                        // one-node preconditioner Q_1 at c0
+    P.M = 1;
+    P.cnode[0] = c0;
+    P.mo = 0;
+    return HP_OK;
+  }
+  const double lo = P.cmin, hi = P.cmax;
+  if (!(hi > lo)) {                    // homogeneous medium: a single node
+    if (layer && lo != c0) return HP_E_LAYER;
+    P.M = 1;
+    P.cnode[0] = lo;
+    P.mo = 0;
+    return HP_OK;
+  }
+  if (!layer) {
+    const double step = (hi - lo) / (M - 1);
+    for (int i = 0; i < M; ++i) P.cnode[i] = lo + step * i;
+    P.cnode[M - 1] = hi;
+    P.M = M;
+    P.mo = 0;
+    return HP_OK;
+  }
+  if (c0 < lo || c0 > hi) return HP_E_LAYER;
+  int below;
+  if (c0 == lo) {
+    below = 0;
+  } else if (c0 == hi) {
+    below = M - 1;
+  } else {
+    M = std::max(M, 3);
+    const double r = (c0 - lo) / (hi - lo) * (M - 1);
+    below = (int)std::ceil(r - 0.5);
+    below = std::min(std::max(below, 1), M - 2);
+  }
+  for (int i = 0; i < M; ++i) {
+    if (i < below) P.cnode[i] = lo + (c0 - lo) * ((double)i / below);
+    else if (i == below) P.cnode[i] = c0;
+    else P.cnode[i] = c0 + (hi - c0) * ((double)(i - below) / (M - 1 - below));
+  }
+  if (below != M - 1) P.cnode[M - 1] = hi;
+  P.M = M;
+  P.mo = below;
+  return HP_OK;
+}
+
+// Interpolation record of a point (see decode_pos in the kernels).
+double encode_point(const hp_plan_s& P, double c, double z) {
+  if (P.Mt > 0 && z > 0.0) {
+    double zz = std::min(z, P.znode[P.Mt]);
+    int j = (int)(std::upper_bound(P.znode, P.znode + P.Mt + 1, zz) - P.znode) - 1;
+    j = std::min(std::max(j, 0), P.Mt - 1);
+    const double t = (zz - P.znode[j]) / (P.znode[j + 1] - P.znode[j]);
+    return -(1.0 + j + t);
+  }
+  if (P.M == 1) return 0.0;
+  double cc = std::min(std::max(c, P.cnode[0]), P.cnode[P.M - 1]);
+  int s = (int)(std::upper_bound(P.cnode, P.cnode + P.M, cc) - P.cnode) - 1;
+  s = std::min(std::max(s, 0), P.M - 2);
+  const double t = (cc - P.cnode[s]) / (P.cnode[s + 1] - P.cnode[s]);
+  return s + t;
+}
+
+void point_nodes(const hp_plan_s& P, double pos, int& A, int& B, double& t) {
+  if (pos >= 0) {
+    if (P.M == 1) { A = B = 0; t = 0; return; }
+    int s = std::min((int)pos, P.M - 2);
+    A = s; B = s + 1; t = pos - s;
+  } else {
+    double q = -pos - 1.0;
+    int s = std::min((int)q, P.Mt - 1);
+    A = s == 0 ? P.mo : P.M + s - 1; B = P.M + s; t = q - s;
+  }
+}
+
+double lambda_1d(int k, int n, double len, int symbol) {
+  if (symbol == HP_SYMBOL_CONTINUOUS) {
+    const int ks = k < n / 2 ? k : k - n;
+    const double xi = 2.0 * M_PI * ks / len;
+    return xi * xi;
+  }
+  const double h = len / n;
+  const double s = std::sin(M_PI * k / n);
+  return 4.0 / (h * h) * s * s;
+}
+
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v) {
+  hipError_t e = b.alloc(v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+hp_status check_grid(const hp_grid* g, int prec) {
+  if (!g || (g->dim != 2 && g->dim != 3)) return HP_E_SHAPE;
+  const int hi = prec == HP_FP64 ? 2048 : 4096;
+  for (int d = 0; d < g->dim; ++d) {
+    if (!pow2_in(g->n[d], 8, hi)) return HP_E_SHAPE;
+    if (!(g->len[d] > 0) || !std::isfinite(g->len[d])) return HP_E_INVALID;
+  }
+  return HP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hp_status_str(hp_status st) {
+  switch (st) {
+    case HP_OK: return "ok";
+    case HP_E_INVALID: return "invalid argument";
+    case HP_E_SHAPE: return "unsupported grid shape";
+    case HP_E_MEDIA: return "invalid media or vanishing symbol denominator";
+    case HP_E_LAYER: return "wave speed differs from c0 inside the absorbing layer";
+    case HP_E_NONFINITE: return "non-finite input";
+    case HP_E_DEVICE: return "HIP device error";
+    case HP_E_NOMEM: return "out of device memory";
+    case HP_E_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}
+
+size_t hp_plan_workspace_bytes(const hp_grid* g, const hp_plan_opts* o, int K) {
+  if (!g || !o) return 0;
+  size_t npts = 1;
+  for (int d = 0; d < g->dim; ++d) npts *= (size_t)g->n[d];
+  const size_t fs = o->precision == HP_FP64 ? 16 : 8;
+  const size_t nr = (size_t)std::max(1, o->max_nrhs);
+  size_t b = nr * npts * fs * (size_t)(K + 1);      // t and the K node fields
+  b += npts * (8 + 32 + (o->precision == HP_FP64 ? 0 : 16));   // pos, coef64, coef32
+  return b;
+}
+
+size_t hp_solve_workspace_bytes(const hp_grid* g, int restart, int nrhs) {
+  if (!g) return 0;
+  size_t npts = 1;
+  for (int d = 0; d < g->dim; ++d) npts *= (size_t)g->n[d];
+  const size_t nr = (size_t)std::max(1, nrhs);
+  return nr * (npts * 16 * (size_t)(restart + 3) + sizeof(hp::KState) +
+               (size_t)hp::kRedBlocks * hp::kPartSlots * 16 + 16);
+}
+
+hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const double* c, const double* a,
+                         const hp_layer* layer, const hp_plan_opts* opts, void* stream) {
+  if (!out) return HP_E_INVALID;
+  *out = nullptr;
+  if (!opts || !c) return HP_E_INVALID;
+  if (opts->precision != HP_FP64 && opts->precision != HP_MIXED) return HP_E_INVALID;
+  if (opts->symbol != HP_SYMBOL_CONTINUOUS && opts->symbol != HP_SYMBOL_DISCRETE) return HP_E_INVALID;
+  if (opts->max_nrhs < 1 || opts->max_nrhs > 4096) return HP_E_INVALID;
+  if (!(omega > 0) || !std::isfinite(omega)) return HP_E_INVALID;
+  if (!(opts->a_floor >= 0) || !std::isfinite(opts->a_floor)) return HP_E_INVALID;
+  hp_status st = check_grid(grid, opts->precision);
+  if (st) return st;
+  const double c0 = layer ? layer->c0 : 1.0;
+  if (!(c0 > 0) || !std::isfinite(c0)) return HP_E_INVALID;
+
+  hp_plan_s* P = new (std::nothrow) hp_plan_s();
+  if (!P) return HP_E_NOMEM;
+  auto fail = [&](hp_status s) {
+    P->release_all();
+    delete P;
+    return s;
+  };
+  P->dim = grid->dim;
+  P->npts = 1;
+  for (int d = 0; d < grid->dim; ++d) {
+    P->n[d] = grid->n[d];
+    P->len[d] = grid->len[d];
+    P->npts *= (size_t)grid->n[d];
+  }
+  P->omega = omega;
+  P->prec = opts->precision;
+  P->symbol = opts->symbol;
+  P->max_nrhs = opts->max_nrhs;
+  const size_t np = P->npts;
+  const double* zeta = layer ? layer->zeta : nullptr;
+
+  // media checks and ranges
+  P->cmin = INFINITY;
+  P->cmax = -INFINITY;
+  P->zmax = 0;
+  for (size_t i = 0; i < np; ++i) {
+    const double cv = c[i];
+    if (!std::isfinite(cv) || !(cv > 0)) return fail(HP_E_MEDIA);
+    P->cmin = std::min(P->cmin, cv);
+    P->cmax = std::max(P->cmax, cv);
+    if (a && (!std::isfinite(a[i]) || a[i] < 0)) return fail(HP_E_MEDIA);
+    if (zeta) {
+      if (!std::isfinite(zeta[i]) || zeta[i] < 0) return fail(HP_E_MEDIA);
+      P->zmax = std::max(P->zmax, zeta[i]);
+    }
+  }
+  const bool q1 = opts->m_real == 1 && !opts->nodes_real;
+  const bool has_layer = P->zmax > 0 && !q1;
+  st = place_real_nodes(*P, *opts, c0, has_layer);
+  if (st) return fail(st);
+  P->Mt = 0;
+  if (has_layer) {
+    const int Mt = opts->m_layer;
+    if (Mt < 1 || P->M + Mt > hp::kMaxNodes) return fail(HP_E_INVALID);
+    P->znode[0] = 0;
+    for (int j = 1; j <= Mt; ++j) {
+      if (opts->nodes_zeta) {
+        P->znode[j] = opts->nodes_zeta[j - 1];
+        if (!(P->znode[j] > P->znode[j - 1]) || !std::isfinite(P->znode[j])) return fail(HP_E_INVALID);
+      } else {
+        P->znode[j] = (j == Mt) ? P->zmax : P->zmax * ((double)j / Mt);
+      }
+    }
+    P->Mt = Mt;
+    for (size_t i = 0; i < np; ++i)
+      if (zeta[i] > 0 && std::fabs(c[i] - c0) > 1e-12 * c0) return fail(HP_E_LAYER);
+  }
+  P->K = P->M + P->Mt;
+
+  // per-point records
+  std::vector<double> pos(np);
+  for (size_t i = 0; i < np; ++i) pos[i] = encode_point(*P, c[i], has_layer ? zeta[i] : 0.0);
+
+  // symbol damping per node: uniform a as is, a(c_m) if given, otherwise the
+  // weight-averaged a over the points each real node serves; floored.
+  bool uniform = true;
+  const double a0 = a ? a[0] : 0.0;
+  if (a)
+    for (size_t i = 1; i < np && uniform; ++i) uniform = a[i] == a0;
+  for (int m = 0; m < P->M; ++m) P->ahat[m] = a0;
+  if (opts->a_nodes) {
+    for (int m = 0; m < P->M; ++m) {
+      if (!(opts->a_nodes[m] >= 0) || !std::isfinite(opts->a_nodes[m])) return fail(HP_E_INVALID);
+      P->ahat[m] = opts->a_nodes[m];
+    }
+  } else if (!uniform) {
+    std::vector<double> num(P->K, 0.0), den(P->K, 0.0);
+    double mean = 0;
+    for (size_t i = 0; i < np; ++i) {
+      int A, B;
+      double t;
+      point_nodes(*P, pos[i], A, B, t);
+      auto add = [&](int n, double w) {
+        if (n < P->M) { num[n] += w * a[i]; den[n] += w; }
+      };
+      if (A == B) add(A, 1.0);
+      else { add(A, 1.0 - t); add(B, t); }
+      mean += a[i];
+    }
+    mean /= (double)np;
+    for (int m = 0; m < P->M; ++m) P->ahat[m] = den[m] > 0 ? num[m] / den[m] : mean;
+  }
+  for (int m = 0; m < P->M; ++m) P->ahat[m] = std::max(P->ahat[m], opts->a_floor);
+  for (int m = 0; m < P->M; ++m) { P->gre[m] = P->cnode[m]; P->gim[m] = 0; }
+  for (int j = 1; j <= P->Mt; ++j) {
+    P->ahat[P->M + j - 1] = P->ahat[P->mo];
+    P->gre[P->M + j - 1] = c0;
+    P->gim[P->M + j - 1] = -c0 * P->znode[j];
+  }
+
+  // symbol constants and tables
+  std::vector<hp::NodeConst> nc(P->K);
+  for (int k = 0; k < P->K; ++k) {
+    const double gr = P->gre[k], gi = P->gim[k];
+    nc[k] = {omega * omega, omega * P->ahat[k], gr * gr - gi * gi, 2 * gr * gi};
+  }
+  std::vector<double> lam0(P->n[0]);
+  for (int k = 0; k < P->n[0]; ++k) lam0[k] = lambda_1d(k, P->n[0], P->len[0], P->symbol);
+  size_t S = np / P->n[0];
+  std::vector<double> lamin(S);
+  if (P->dim == 2) {
+    for (int k = 0; k < P->n[1]; ++k) lamin[k] = lambda_1d(k, P->n[1], P->len[1], P->symbol);
+  } else {
+    std::vector<double> l1(P->n[1]), l2(P->n[2]);
+    for (int k = 0; k < P->n[1]; ++k) l1[k] = lambda_1d(k, P->n[1], P->len[1], P->symbol);
+    for (int k = 0; k < P->n[2]; ++k) l2[k] = lambda_1d(k, P->n[2], P->len[2], P->symbol);
+    for (int k1 = 0; k1 < P->n[1]; ++k1)
+      for (int k2 = 0; k2 < P->n[2]; ++k2) lamin[(size_t)k1 * P->n[2] + k2] = l1[k1] + l2[k2];
+  }
+  // a vanishing denominator is only possible for a real node without damping
+  for (int k = 0; k < P->K; ++k) {
+    if (nc[k].aim != 0.0 || nc[k].gim != 0.0) continue;
+    for (int k0 = 0; k0 < P->n[0]; ++k0)
+      for (size_t ci = 0; ci < S; ++ci)
+        if (nc[k].are - nc[k].gre * (lam0[k0] + lamin[ci]) == 0.0) return fail(HP_E_MEDIA);
+  }
+
+  // pass-C group masks: which nodes any point of a workgroup's rows uses
+  const int nl = P->n[P->dim - 1];
+  const size_t rows = np / nl;
+  const int G = hp::combine_group_rows(P->real_kind(), nl);
+  std::vector<uint64_t> gm((rows + G - 1) / G, 0);
+  for (size_t r = 0; r < rows; ++r) {
+    uint64_t m = 0;
+    for (int i = 0; i < nl; ++i) {
+      int A, B;
+      double t;
+      point_nodes(*P, pos[r * nl + i], A, B, t);
+      m |= (1ull << A) | (1ull << B);
+    }
+    gm[r / G] |= m;
+  }
+
+  // stencil coefficients {gamma^2, beta} (Section 5 with gamma of Section 4.3)
+  double sih2 = 0, ih2[3] = {0, 0, 0};
+  for (int d = 0; d < P->dim; ++d) {
+    const double h = P->len[d] / P->n[d];
+    ih2[d] = 1.0 / (h * h);
+    sih2 += ih2[d];
+  }
+  std::vector<cpx<double>> cf(2 * np);
+  for (size_t i = 0; i < np; ++i) {
+    const double cv = c[i], zv = zeta ? zeta[i] : 0.0, av = a ? a[i] : 0.0;
+    const double gr = cv * cv * (1 - zv * zv), gi = -2 * cv * cv * zv;   // (c (1 - i zeta))^2
+    cf[2 * i] = {gr, gi};
+    cf[2 * i + 1] = {omega * omega - 2 * gr * sih2, omega * av - 2 * gi * sih2};
+  }
+
+  hipError_t e;
+  if ((e = upload(P->nodes, nc)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->pos, pos)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->grpmask, gm)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->coef64, cf)) != hipSuccess) return fail(from_hip(e));
+  if (P->prec == HP_MIXED) {
+    std::vector<cpx<float>> cf32(2 * np);
+    for (size_t i = 0; i < 2 * np; ++i) cf32[i] = {(float)cf[i].re, (float)cf[i].im};
+    if ((e = upload(P->coef32, cf32)) != hipSuccess) return fail(from_hip(e));
+  }
+  if ((e = upload(P->lam_ax, lam0)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->lam_in, lamin)) != hipSuccess) return fail(from_hip(e));
+  for (int d = 0; d < P->dim; ++d) {
+    const int n = P->n[d];
+    std::vector<cpx<double>> w(n);
+    std::vector<cpx<float>> wf(n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = 2.0 * M_PI * (double)m / (double)n;
+      w[m] = {std::cos(ang), -std::sin(ang)};
+      wf[m] = {(float)w[m].re, (float)w[m].im};
+    }
+    if (P->prec == HP_FP64) {
+      if ((e = upload(P->tw64[d], w)) != hipSuccess) return fail(from_hip(e));
+    } else {
+      if ((e = upload(P->tw32[d], wf)) != hipSuccess) return fail(from_hip(e));
+    }
+  }
+  const size_t fb = (size_t)P->max_nrhs * np * P->fsize();
+  if ((e = P->t.alloc(fb)) != hipSuccess) return fail(from_hip(e));
+  if ((e = P->fields.alloc(fb * P->K)) != hipSuccess) return fail(from_hip(e));
+  (void)stream;
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(from_hip(e));
+  *out = P;
+  return HP_OK;
+}
+
+hp_status hp_plan_query(hp_plan p, hp_plan_info* info) {
+  if (!p || !info) return HP_E_INVALID;
+  std::memset(info, 0, sizeof(*info));
+  info->dim = p->dim;
+  for (int d = 0; d < 3; ++d) info->n[d] = p->n[d];
+  info->K = p->K;
+  info->M = p->M;
+  info->Mt = p->Mt;
+  info->mo = p->mo;
+  info->cmin = p->cmin;
+  info->cmax = p->cmax;
+  info->zeta_max = p->zmax;
+  for (int i = 0; i < 64; ++i) {
+    info->cnode[i] = p->cnode[i];
+    info->ahat[i] = p->ahat[i];
+    info->gamma_re[i] = p->gre[i];
+    info->gamma_im[i] = p->gim[i];
+  }
+  for (int i = 0; i < 65; ++i) info->znode[i] = p->znode[i];
+  info->workspace_bytes = p->t.bytes + p->fields.bytes + p->pos.bytes + p->coef64.bytes + p->coef32.bytes;
+  info->precision = p->prec;
+  return HP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// u (+)= Q_M v for nrhs <= max_nrhs right-hand sides.
+// in_kind/out_kind: 0 = complex128, 1 = complex64.
+hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, void* u, int out_kind,
+                     size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st) {
+  const int rk = P->real_kind();
+  const size_t np = P->npts;
+  hipError_t e;
+  const int nl = P->n[P->dim - 1];
+  const int rows = (int)(np / nl);
+  e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, st);
+  if (e != hipSuccess) return e;
+  if (P->dim == 3) {   // forward along the middle axis, in place
+    hp::ColsArgs m{};
+    m.real_kind = rk; m.n = P->n[1]; m.dir = -1; m.mode = 0;
+    m.in = P->t.p; m.out = P->t.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = 1; m.nrhs = nrhs;
+    m.in_rs = np; m.out_rs = np; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
+    if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
+  }
+  hp::ColsArgs b{};
+  b.real_kind = rk; b.n = P->n[0]; b.dir = -1; b.mode = 1;
+  b.in = P->t.p; b.out = P->fields.p; b.S = (int)(np / P->n[0]); b.outer = 1; b.nfields = 1; b.nrhs = nrhs;
+  b.in_rs = np; b.out_rs = np * P->K; b.in_fs = np; b.out_fs = np; b.tw = P->tw(0); b.skip = skip;
+  b.lam_ax = (const double*)P->lam_ax.p; b.lam_in = (const double*)P->lam_in.p;
+  b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
+  if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
+  if (P->dim == 3) {   // inverse along the middle axis for the K fields, in place
+    hp::ColsArgs m{};
+    m.real_kind = rk; m.n = P->n[1]; m.dir = +1; m.mode = 0;
+    m.in = P->fields.p; m.out = P->fields.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = P->K; m.nrhs = nrhs;
+    m.in_rs = np * P->K; m.out_rs = np * P->K; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
+    if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
+  }
+  hp::CombineArgs c{};
+  c.real_kind = rk; c.out_kind = out_kind; c.accumulate = acc ? 1 : 0; c.n = nl;
+  c.fields = P->fields.p; c.fs = np; c.frs = np * P->K; c.pos = (const double*)P->pos.p;
+  c.grpmask = (const uint64_t*)P->grpmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
+  c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
+  return hp::launch_combine(c, st);
+}
+
+hipError_t run_stencil(hp_plan_s* P, int kind, const void* u, size_t u_rs, void* y, size_t y_rs,
+                       const void* f, int nrhs, const int* skip, hipStream_t st) {
+  hp::StencilArgs s{};
+  s.kind = kind;
+  s.dim = P->dim;
+  for (int d = 0; d < 3; ++d) {
+    s.n[d] = P->n[d];
+    const double h = P->len[d] / P->n[d];
+    s.ih2[d] = d < P->dim ? 1.0 / (h * h) : 0.0;
+  }
+  s.u = u; s.u_rs = u_rs; s.y = y; s.y_rs = y_rs; s.f = f;
+  s.coef = (kind == 1 || kind == 2) ? P->coef32.p : P->coef64.p;
+  s.nrhs = nrhs;
+  s.skip = skip;
+  return hp::launch_stencil(s, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+hp_status hp_apply_precond(hp_plan p, const void* v, void* u, int nrhs, void* stream) {
+  if (!p || !v || !u || nrhs < 0) return HP_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t fs = p->fsize();
+  const int kind = p->prec == HP_FP64 ? 0 : 1;
+  for (int r0 = 0; r0 < nrhs; r0 += p->max_nrhs) {
+    const int nr = std::min(p->max_nrhs, nrhs - r0);
+    const char* vi = (const char*)v + (size_t)r0 * p->npts * fs;
+    char* uo = (char*)u + (size_t)r0 * p->npts * fs;
+    HP_TRY(run_apply(p, vi, kind, p->npts, uo, kind, p->npts, false, nr, nullptr, st));
+  }
+  return HP_OK;
+}
+
+hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream) {
+  if (!p || !u || !y || nrhs < 0) return HP_E_INVALID;
+  if (u == y) return HP_E_INVALID;
+  if (nrhs == 0) return HP_OK;
+  const int kind = p->prec == HP_FP64 ? 0 : 1;
+  HP_TRY(run_stencil(p, kind, u, p->npts, y, p->npts, nullptr, nrhs, nullptr, (hipStream_t)stream));
+  return HP_OK;
+}
+
+static hipError_t ensure_solver_ws(hp_plan_s* P, int restart, int nrhs) {
+  if (P->ws_restart >= restart && P->ws_nrhs >= nrhs) return hipSuccess;
+  const int r = std::max(restart, P->ws_restart), n = std::max(nrhs, P->ws_nrhs);
+  const size_t np = P->npts;
+  hipError_t e;
+  if ((e = P->V.alloc((size_t)n * (r + 1) * np * 16)) != hipSuccess) return e;
+  if ((e = P->z.alloc((size_t)n * np * P->fsize())) != hipSuccess) return e;
+  if ((e = P->tvec.alloc((size_t)n * np * 16)) != hipSuccess) return e;
+  if ((e = P->state.alloc((size_t)n * sizeof(hp::KState))) != hipSuccess) return e;
+  if ((e = P->part.alloc((size_t)n * hp::kRedBlocks * hp::kPartSlots * 16)) != hipSuccess) return e;
+  if ((e = P->flags.alloc((size_t)n * 2 * sizeof(int))) != hipSuccess) return e;
+  if (P->pinned) (void)hipHostFree(P->pinned);
+  P->pinned = nullptr;
+  if ((e = hipHostMalloc(&P->pinned, (size_t)n * sizeof(int))) != hipSuccess) return e;
+  P->ws_restart = r;
+  P->ws_nrhs = n;
+  return hipSuccess;
+}
+
+static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x, int nrhs,
+                             const hp_solve_opts& o, hp_solve_info* info, hipStream_t st) {
+  const size_t np = P->npts;
+  HP_TRY(ensure_solver_ws(P, o.restart, nrhs));
+  const size_t vrs = (size_t)(P->ws_restart + 1) * np;
+  hp::KrylovArgs K{};
+  K.V = (cpx<double>*)P->V.p;
+  K.npts = np;
+  K.vrs = vrs;
+  K.state = (hp::KState*)P->state.p;
+  K.part = (cpx<double>*)P->part.p;
+  K.skip_step = (int*)P->flags.p;
+  K.done = (int*)P->flags.p + P->ws_nrhs;
+  K.nrhs = nrhs;
+  K.restart = o.restart;
+  const int mixed = P->prec == HP_MIXED;
+  HP_TRY(hp::launch_fill_zero(P->flags.p, P->flags.bytes, st));
+  HP_TRY(hp::launch_dots(K, f, np, 0, nullptr, st));
+  HP_TRY(hp::launch_fnorm(K, o.rtol, st));
+  int* hdone = (int*)P->pinned;
+  for (int cyc = 0;; ++cyc) {
+    // true residual r = f - P_N x into v_0, its norm, convergence test
+    HP_TRY(run_stencil(P, 3, x, np, K.V, vrs, f, nrhs, K.done, st));
+    HP_TRY(hp::launch_dots(K, K.V, vrs, 0, K.done, st));
+    HP_TRY(hp::launch_cycle_start(K, o.rtol, st));
+    HP_TRY(hipMemcpyAsync(hdone, K.done, (size_t)nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+    HP_TRY(hipStreamSynchronize(st));
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) all = all && hdone[r];
+    if (all || cyc >= o.max_cycles) break;
+    HP_TRY(hp::launch_scale_v0(K, st));
+    for (int j = 0; j < o.restart; ++j) {
+      cpx<double>* vj = K.V + (size_t)j * np;
+      cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
+      // z = Q v_j ; v_{j+1} = P_N z
+      HP_TRY(run_apply(P, vj, 0, vrs, P->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st));
+      HP_TRY(run_stencil(P, mixed ? 2 : 0, P->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st));
+      HP_TRY(hp::launch_dots(K, vj1, vrs, j + 1, K.skip_step, st));
+      HP_TRY(hp::launch_arnoldi_reduce(K, j, 1, st));
+      HP_TRY(hp::launch_arnoldi_update(K, j, 1, st));
+      HP_TRY(hp::launch_arnoldi_reduce(K, j, 2, st));
+      HP_TRY(hp::launch_arnoldi_update(K, j, 2, st));
+    }
+    // x += Q (V_k y)
+    HP_TRY(hp::launch_backsolve(K, st));
+    HP_TRY(hp::launch_lincomb(K, (cpx<double>*)P->tvec.p, np, st));
+    HP_TRY(run_apply(P, P->tvec.p, 0, np, x, 0, np, true, nrhs, K.done, st));
+  }
+  std::vector<hp::KState> hs(nrhs);
+  HP_TRY(hipMemcpyAsync(hs.data(), P->state.p, (size_t)nrhs * sizeof(hp::KState), hipMemcpyDeviceToHost, st));
+  HP_TRY(hipStreamSynchronize(st));
+  hp_status ret = HP_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    info[r].iters = hs[r].iters;
+    info[r].cycles = hs[r].cycles;
+    info[r].rel_true_residual = hs[r].relres;
+    info[r].status = hdone[r] ? HP_OK : HP_E_NOT_CONVERGED;
+    if (!hdone[r]) ret = HP_E_NOT_CONVERGED;
+  }
+  return ret;
+}
+
+hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts, hp_solve_info* info,
+                   void* stream) {
+  if (!p || !f || !x || !opts || !info || nrhs < 0) return HP_E_INVALID;
+  if (opts->restart < 1 || opts->restart > hp::kMaxRestart || opts->max_cycles < 1 || !(opts->rtol > 0))
+    return HP_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  hp_status ret = HP_OK;
+  for (int r0 = 0; r0 < nrhs; r0 += p->max_nrhs) {
+    const int nr = std::min(p->max_nrhs, nrhs - r0);
+    hp_status s = solve_batch(p, (const cpx<double>*)f + (size_t)r0 * p->npts, (cpx<double>*)x + (size_t)r0 * p->npts,
+                              nr, *opts, info + r0, st);
+    if (s != HP_OK && s != HP_E_NOT_CONVERGED) return s;
+    if (s == HP_E_NOT_CONVERGED) ret = s;
+  }
+  return ret;
+}
+
+hp_status hp_plan_destroy(hp_plan p) {
+  if (!p) return HP_E_INVALID;
+  (void)hipDeviceSynchronize();
+  p->release_all();
+  delete p;
+  return HP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+// Device-side FFT engine for gfx950: register-resident Stockham transforms.
+//
+// A transform of length N (power of two) is computed by T = N/E threads, each
+// holding E elements in registers.  On entry and on exit thread j holds the
+// elements j + T*s, s = 0..E-1, of its line, so that loads and stores of a
+// wavefront touch consecutive addresses (or consecutive row segments of a
+// column tile).  Each radix-R stage performs E/R butterflies per thread; the
+// data is exchanged through LDS between stages (autosort, no bit reversal),
+// and the last stage writes its outputs straight back into the same registers.
+//
+// Sign convention: forward uses exp(-2 pi i jk/N), inverse exp(+2 pi i jk/N),
+// both unnormalised; the Fourier transform of the paper (Eqn. FT) fixes the
+// forward sign.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hp {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.re * s, a.im * s}; }
+
+// exp(2 pi i m / 16) for m = 0..15 (real and imaginary parts).
+__host__ __device__ constexpr double cos16(int m) {
+  constexpr double c1 = 0.92387953251128675613;   // cos(pi/8)
+  constexpr double c2 = 0.70710678118654752440;   // cos(pi/4)
+  constexpr double c3 = 0.38268343236508977173;   // cos(3pi/8)
+  constexpr double t[16] = {1.0, c1, c2, c3, 0.0, -c3, -c2, -c1, -1.0, -c1, -c2, -c3, 0.0, c3, c2, c1};
+  return t[m & 15];
+}
+__host__ __device__ constexpr double sin16(int m) { return cos16(m - 4); }
+
+// Multiply by the constant w = exp(DIR * 2 pi i k / N), N <= 16, with the trivial
+// cases folded at compile time.
+template <typename R, int N, int K, int DIR>
+__device__ __forceinline__ cpx<R> twc(cpx<R> a) {
+  constexpr int m = ((K * (16 / N)) % 16 + 16) % 16;      // angle index on the 16-grid
+  constexpr int md = DIR > 0 ? m : (16 - m) % 16;
+  if constexpr (md == 0) return a;
+  else if constexpr (md == 4) return {-a.im, a.re};        // * i
+  else if constexpr (md == 8) return {-a.re, -a.im};
+  else if constexpr (md == 12) return {a.im, -a.re};       // * -i
+  else if constexpr (md == 2 || md == 6 || md == 10 || md == 14) {
+    constexpr R h = (R)0.70710678118654752440;
+    constexpr R cr = (md == 2 || md == 14) ? h : -h;
+    constexpr R ci = (md == 2 || md == 6) ? h : -h;
+    // (a.re + i a.im)(cr + i ci) with |cr| = |ci| = h
+    return {h * ((cr > 0 ? a.re : -a.re) - (ci > 0 ? a.im : -a.im)),
+            h * ((ci > 0 ? a.re : -a.re) + (cr > 0 ? a.im : -a.im))};
+  } else {
+    constexpr R cr = (R)cos16(md), ci = (R)sin16(md);
+    return {a.re * cr - a.im * ci, a.re * ci + a.im * cr};
+  }
+}
+
+// In-register DFT of size N <= 16 by radix-2 decimation in time.
+// in[i] -> out[k] = sum_i in[i] exp(DIR 2 pi i ik / N).
+template <typename R, int N, int DIR>
+struct Dft {
+  __device__ __forceinline__ static void run(const cpx<R>* in, cpx<R>* out) {
+    if constexpr (N == 1) {
+      out[0] = in[0];
+    } else if constexpr (N == 2) {
+      out[0] = cadd(in[0], in[1]);
+      out[1] = csub(in[0], in[1]);
+    } else {
+      constexpr int H = N / 2;
+      cpx<R> ev[H], od[H], E[H], O[H];
+#pragma unroll
+      for (int i = 0; i < H; ++i) { ev[i] = in[2 * i]; od[i] = in[2 * i + 1]; }
+      Dft<R, H, DIR>::run(ev, E);
+      Dft<R, H, DIR>::run(od, O);
+      combine<0>(E, O, out);
+    }
+  }
+  template <int K>
+  __device__ __forceinline__ static void combine(const cpx<R>* E, const cpx<R>* O, cpx<R>* out) {
+    if constexpr (K < N / 2) {
+      cpx<R> o = twc<R, N, K, DIR>(O[K]);
+      out[K] = cadd(E[K], o);
+      out[K + N / 2] = csub(E[K], o);
+      combine<K + 1>(E, O, out);
+    }
+  }
+};
+
+// LDS index with one pad element every E elements: the first stage writes
+// runs of E consecutive elements per thread, and the padding staggers those
+// runs across the LDS banks.
+template <int E>
+__device__ __forceinline__ int lpad(int i) { return i + i / E; }
+template <int E>
+__host__ __device__ constexpr int lds_elems_e(int n) { return n + n / E; }
+
+// Elements per thread: 8 complex doubles or 16 complex floats (64 VGPRs either
+// way), fewer for tiny transforms.
+template <typename R>
+__host__ __device__ constexpr int elems_per_thread(int n) {
+  return n < (sizeof(R) == 8 ? 8 : 16) ? n : (sizeof(R) == 8 ? 8 : 16);
+}
+
+template <int N, int NS, int E>
+__host__ __device__ constexpr int stage_radix() {
+  return (N / NS) < E ? (N / NS) : E;
+}
+
+// One Stockham stage of radix R at sub-transform size NS, then the next stage.
+// tw: table of exp(-2 pi i m / N), m < N.
+template <typename R, int N, int E, int DIR, int NS>
+struct Stage {
+  __device__ __forceinline__ static void run(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
+    constexpr int RS = stage_radix<N, NS, E>();
+    constexpr int B = E / RS;
+    constexpr int T = N / E;
+    constexpr bool last = (NS * RS == N);
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int b = j + T * i;
+      cpx<R> in[RS], out[RS];
+#pragma unroll
+      for (int t = 0; t < RS; ++t) in[t] = x[i + B * t];
+      const int k = (NS > 1) ? (b % NS) : 0;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int t = 1; t < RS; ++t) {
+          cpx<R> w = tw[k * t * (N / (NS * RS))];
+          in[t] = DIR < 0 ? cmul(in[t], w) : cmulc(in[t], w);
+        }
+      }
+      Dft<R, RS, DIR>::run(in, out);
+      if constexpr (last) {
+#pragma unroll
+        for (int t = 0; t < RS; ++t) x[i + B * t] = out[t];
+      } else {
+        const int base = (b / NS) * NS * RS + k;
+#pragma unroll
+        for (int t = 0; t < RS; ++t) lds[lpad<E>(base + t * NS)] = out[t];
+      }
+    }
+    if constexpr (!last) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < E; ++s) x[s] = lds[lpad<E>(j + T * s)];
+      __syncthreads();
+      Stage<R, N, E, DIR, NS * RS>::run(x, lds, j, tw);
+    }
+  }
+};
+
+template <typename R>
+__host__ __device__ constexpr int lds_elems(int n) { return lds_elems_e<elems_per_thread<R>(8192)>(n); }
+
+// Full transform.  All threads of the workgroup must call it together
+// (it contains workgroup barriers when N > E).
+template <typename R, int N, int DIR>
+__device__ __forceinline__ void fft(cpx<R> (&x)[elems_per_thread<R>(N)], cpx<R>* lds, int j,
+                                    const cpx<R>* __restrict__ tw) {
+  Stage<R, N, elems_per_thread<R>(N), DIR, 1>::run(x, lds, j, tw);
+}
+
+}  // namespace hp

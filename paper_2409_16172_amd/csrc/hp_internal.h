@@ -1,0 +1,123 @@
+// Internal declarations shared by the kernels (hp_kernels.hip) and the host
+// side of the library (hp_api.cpp).  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hp_fft.h"
+
+namespace hp {
+
+// Symbol constants of one node: q_n(lambda) = 1 / (A_n - g_n lambda) with
+// A_n = omega^2 + i omega ahat_n and g_n = gamma_n^2 (Eqn. 021 with gamma).
+struct NodeConst {
+  double are, aim, gre, gim;
+};
+
+constexpr int kMaxNodes = 64;
+constexpr int kMaxRestart = 64;
+
+// Krylov state of one right-hand side, resident on the device.
+struct KState {
+  cpx<double> H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart + 1
+  cpx<double> cs[kMaxRestart], sn[kMaxRestart];
+  cpx<double> g[kMaxRestart + 1];
+  cpx<double> y[kMaxRestart];
+  cpx<double> h[kMaxRestart + 1];   // projections of the current step
+  cpx<double> h2[kMaxRestart + 1];  // reorthogonalisation projections
+  double fnorm, target, beta, w2, w2_first, hnext, relres;
+  int k;        // columns finished in the current cycle
+  int reorth;   // the current step needs a second projection
+  int iters;    // Arnoldi steps in total
+  int cycles;
+  int pad_[4];
+};
+
+constexpr int kRedThreads = 256;   // threads per block of the reduction kernels
+constexpr int kRedBlocks = 512;    // blocks per right-hand side (fixed: deterministic sums)
+constexpr int kPartSlots = kMaxRestart + 2;
+
+// ---- launchers (all enqueue on `st`, return the launch status) ----
+
+// Pass A: forward transform along the contiguous axis.
+// in_kind: 0 = complex128 input, 1 = complex64 input.  real_kind: 0 = FP64, 1 = FP32.
+hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
+                           size_t in_rs, size_t out_rs, int nrhs, const void* tw, const int* skip,
+                           hipStream_t st);
+
+// Strided-axis transform over column tiles: element (o, p, c) at o*n*S + p*S + c.
+// mode 0: plain transform (dir -1/+1) of nfields fields;
+// mode 1: forward, then for every node: symbol multiply and inverse (pass B).
+struct ColsArgs {
+  int real_kind, n, dir, mode;
+  const void* in;
+  void* out;
+  int S, outer, nfields, nrhs;
+  size_t in_rs, out_rs, in_fs, out_fs;
+  const void* tw;
+  const int* skip;
+  const double* lam_ax;
+  const double* lam_in;
+  const NodeConst* nodes;
+  int K;
+  double scale;
+};
+hipError_t launch_cols(const ColsArgs& a, hipStream_t st);
+
+// Pass C: inverse transform along the contiguous axis of the K node fields and
+// the interpolation combine.  out_kind: 0 = complex128, 1 = complex64.
+struct CombineArgs {
+  int real_kind, out_kind, accumulate, n;
+  const void* fields;
+  size_t fs, frs;
+  const double* pos;
+  const uint64_t* grpmask;
+  void* out;
+  size_t out_rs;
+  int rows, K, M, Mt, mo, nrhs;
+  const void* tw;
+  const int* skip;
+};
+hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
+int combine_group_rows(int real_kind, int n);  // rows per workgroup of pass C
+
+// Stencil.  kind: 0 = FP64 (c128 -> c128), 1 = FP32 arithmetic c64 -> c64,
+// 2 = FP32 arithmetic c64 -> c128, 3 = FP64 residual y = f - P u (c128).
+struct StencilArgs {
+  int kind, dim;
+  int n[3];
+  double ih2[3];
+  const void* u;
+  void* y;
+  const void* coef;
+  const void* f;     // residual mode: right-hand side, same strides as u
+  size_t u_rs, y_rs;
+  int nrhs;
+  const int* skip;
+};
+hipError_t launch_stencil(const StencilArgs& a, hipStream_t st);
+
+// Krylov kernels (FP64).  Basis of one right-hand side: (restart + 1) vectors of
+// npts points; bases of consecutive right-hand sides are vrs elements apart.
+struct KrylovArgs {
+  cpx<double>* V;
+  size_t npts, vrs;
+  KState* state;
+  cpx<double>* part;
+  int* skip_step;   // 1 when the current cycle's Arnoldi process has ended
+  int* done;        // 1 when the right-hand side has converged
+  int nrhs, restart;
+};
+hipError_t launch_dots(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int nvec, const int* skip,
+                       hipStream_t st);
+hipError_t launch_fnorm(const KrylovArgs& a, double rtol, hipStream_t st);
+hipError_t launch_cycle_start(const KrylovArgs& a, double rtol, hipStream_t st);
+hipError_t launch_scale_v0(const KrylovArgs& a, hipStream_t st);
+hipError_t launch_arnoldi_reduce(const KrylovArgs& a, int j, int stage, hipStream_t st);
+hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, int stage, hipStream_t st);
+hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);
+hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace hp
