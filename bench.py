@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the preconditioned GMRES hot path on one MI355X.
+
+A step is one full solve P_N x = f to FP64 true residual rtol 1e-8 with restarted
+GMRES(30) right-preconditioned by Q_M: every Arnoldi step applies Q_M (FFT
+passes, symbol multiplies, inverse FFTs, combine), the stencil P_N and the FP64
+orthogonalisation; every cycle adds the FP64 true residual.  The workload is the
+2-D 1024 x 1024 Gaussian-random-field medium with a 32-cell absorbing layer, 100
+wavelengths, 16 + 3 interpolation nodes, FP64, one Gaussian source (synthetic,
+seeded; inputs already on the GPU when timing starts).
+
+Also reported: the preconditioner apply rate (algorithmic bytes over event-timed
+pass durations), p50/p99 solve latency over the timed steps, the same solve in
+mixed precision, the roofline of the dominant kernel and the CPU oracle timed
+on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "P-apply HBM GB/s + GMRES solves/s at rtol 1e-8; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = ["rows_fwd", "cols_fwd_mid", "cols_symbol_inv", "cols_inv_mid", "rows_inv_combine"]
+KERNEL_NAMES = {0: "k_rows_fwd", 1: "k_cols (forward, middle axis)", 2: "k_cols (symbol mode)",
+                3: "k_cols (inverse, middle axis)", 4: "k_rows_combine"}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2409_16172_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload, kernel_slot):
+    """HBM bytes per launch measured by rocprofv3 counters for the current kernel sources,
+    or None when no measurement for these sources is committed."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    v = t.get("bytes_per_launch", {}).get(PASS_NAMES[kernel_slot])
+    return None if v is None else float(v)
+
+
+def cpu_baseline(w, gpu_iters, gpu_cycles, steps=6):
+    """The FP64 oracle, single-threaded, timed on a bounded sample: `steps` Arnoldi steps
+    (each one Q_M apply, one P_N matvec and modified Gram-Schmidt) plus one apply and one
+    matvec (the per-cycle solution update and true residual), extrapolated to a whole solve
+    with the GPU run's iteration and cycle counts."""
+    import oracle
+    p = oracle.from_workload(w)
+    f = w.f[0]
+    t0 = time.perf_counter()
+    p.arnoldi(f, steps)
+    t_step = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    p.matvec(p.apply(f))
+    t_cycle = time.perf_counter() - t0
+    t_solve = gpu_iters * t_step + gpu_cycles * t_cycle
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} Arnoldi steps + 1 apply/matvec of {w.name} ({w.shape[0]}^2, K="
+                      f"{w.m_real + w.m_layer}), FP64 C oracle; {t_step:.2f} s/step, solve extrapolated "
+                      f"to {gpu_iters} steps and {gpu_cycles} cycles = {t_solve:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="2d_1024_grf")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
+    ap.add_argument("--apply-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2409_16172_amd import binding, inputs
+
+    dev = torch.device("cuda:0")
+    w = inputs.workload(args.workload)
+    plan = binding.plan_from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    rtol, restart = 1e-8, 30
+    print(f"[bench] workload {w.name} {w.shape} K={plan.info()['K']} warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+    for _ in range(args.warmup):
+        plan.solve(f, rtol=rtol, restart=restart)
+    torch.cuda.synchronize()
+    lat = []
+    infos = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        x, infos = plan.solve(f, rtol=rtol, restart=restart)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    info = infos[0]
+    print(f"[bench] solve: {info.iters} iters {info.cycles} cycles res {info.rel_true_residual:.3e} "
+          f"{total / args.steps * 1e3:.2f} ms/solve", file=sys.stderr, flush=True)
+    if info.status != 0:
+        raise SystemExit(f"solve did not converge: {info}")
+
+    # preconditioner apply: event-timed passes on the launch stream
+    rng = np.random.default_rng(0)
+    vh = rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape)
+    v = torch.from_numpy(vh).to(dev)
+    plan.profile_apply(v, reps=3)
+    ms, by = plan.profile_apply(v, reps=args.apply_reps)
+    apply_ms = sum(ms)
+    apply_gbs = sum(by) / (apply_ms * 1e-3) / 1e9
+    dom = int(np.argmax(ms))
+    achieved = by[dom] / (ms[dom] * 1e-3) / 1e9
+    traffic = traffic_from_profiles(w.name, dom)
+    print(f"[bench] apply {apply_ms * 1e3:.1f} us, passes us {[round(t * 1e3, 1) for t in ms]}, "
+          f"{apply_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
+    mixed = None
+    if not args.no_mixed:
+        pm = binding.plan_from_workload(w, precision="mixed")
+        pm.solve(f, rtol=rtol, restart=restart)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = max(1, args.steps)
+        for _ in range(reps):
+            xm, im = pm.solve(f, rtol=rtol, restart=restart)
+        torch.cuda.synchronize()
+        tm = (time.perf_counter() - t1) / reps
+        mixed = {"solves_per_s": 1.0 / tm, "iters": im[0].iters, "rel_true_residual": im[0].rel_true_residual,
+                 "converged": im[0].status == 0}
+        pm.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(w, info.iters, info.cycles)
+    lat_ms = sorted(t * 1e3 for t in lat)
+    out = {
+        "metric": METRIC,
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: 2-D {w.shape[0]}x{w.shape[1]} periodic, 5-point FD Helmholtz, "
+                               f"{w.info['n_lambda']:.0f} wavelengths, Gaussian random field c in [0.8,1.2], "
+                               f"a=0.05 omega, {w.info['layer_cells']}-cell absorbing layer, "
+                               f"{w.m_real}+{w.m_layer} nodes, GMRES({restart}) rtol {rtol:g}, FP64",
+                   "global_batch": int(w.f.shape[0]), "parallelism": "single GPU"},
+        "p_apply": {"GBps": apply_gbs, "us": apply_ms * 1e3, "bytes": sum(by),
+                    "pass_us": dict(zip(PASS_NAMES, [t * 1e3 for t in ms])),
+                    "pass_bytes": dict(zip(PASS_NAMES, by)), "frac_of_hbm_peak": apply_gbs / HBM_PEAK_GBS},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "solve": {"iters": info.iters, "cycles": info.cycles, "rel_true_residual": info.rel_true_residual},
+        "mixed": mixed,
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes": by[dom], "launch_us": ms[dom] * 1e3},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

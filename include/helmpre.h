@@ -162,6 +162,21 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts,
                    hp_solve_info* info, void* stream);
 
+/* Diagnostic timing of the preconditioner passes (for benchmarks): runs `reps`
+ * applies of v -> u (as hp_apply_precond, nrhs <= max_nrhs) and records HIP
+ * events on `stream` around every pass.  Blocks until done.  ms[5] receives the
+ * average milliseconds per launch of the passes in order
+ *   0: forward transform along the last (contiguous) axis
+ *   1: forward transform along the middle axis (3-D only, else 0)
+ *   2: forward transform along axis 0, symbol multiplies and inverse transforms
+ *   3: inverse transform along the middle axis of the K fields (3-D only, else 0)
+ *   4: inverse transform along the last axis and interpolation combine
+ * bytes[5] receives the algorithmic HBM bytes of each pass per launch: the
+ * fields each pass must read and write, counting only the node fields that
+ * some point of a row uses (the others are neither written nor read). */
+hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps, double* ms, double* bytes,
+                           void* stream);
+
 hp_status hp_plan_destroy(hp_plan p);
 
 const char* hp_status_str(hp_status st);

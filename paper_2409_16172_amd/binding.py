@@ -23,7 +23,8 @@ SYMBOLS = {"continuous": 0, "discrete": 1}
 PRECISIONS = {"fp64": HP_FP64, "mixed": HP_MIXED}
 
 EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_bytes", "hp_plan_query",
-            "hp_apply_precond", "hp_matvec", "hp_solve", "hp_plan_destroy", "hp_status_str"]
+            "hp_apply_precond", "hp_matvec", "hp_solve", "hp_profile_apply", "hp_plan_destroy",
+            "hp_status_str"]
 
 
 class HpGrid(C.Structure):
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     lib.hp_matvec.restype = i
     lib.hp_solve.argtypes = [vp, vp, vp, i, C.POINTER(HpSolveOpts), C.POINTER(HpSolveInfo), vp]
     lib.hp_solve.restype = i
+    lib.hp_profile_apply.argtypes = [vp, vp, vp, i, i, C.POINTER(d), C.POINTER(d), vp]
+    lib.hp_profile_apply.restype = i
     lib.hp_plan_destroy.argtypes = [vp]
     lib.hp_plan_destroy.restype = i
     lib.hp_status_str.argtypes = [i]
@@ -242,6 +245,17 @@ class Plan:
         if code not in (HP_OK, HP_E_NOT_CONVERGED) or (raise_on_fail and code != HP_OK):
             raise HelmpreError(code, "hp_solve")
         return x, [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status) for i in infos]
+
+    def profile_apply(self, v, out=None, reps=20, stream=None):
+        """Event-timed applies: (ms per launch of the 5 pass slots, algorithmic bytes per pass)."""
+        import torch
+        nr = self._fields(v, self.field_dtype, "v")
+        u = torch.empty_like(v) if out is None else out
+        ms = (C.c_double * 5)()
+        by = (C.c_double * 5)()
+        _check(load_library().hp_profile_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()), nr,
+                                               int(reps), ms, by, _stream(stream)), "hp_profile_apply")
+        return list(ms), list(by)
 
     def close(self):
         if getattr(self, "_h", None):

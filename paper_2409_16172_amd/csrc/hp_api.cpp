@@ -53,7 +53,10 @@ struct hp_plan_s {
   double cmin = 0, cmax = 0, zmax = 0;
   double cnode[64] = {0}, znode[65] = {0}, ahat[64] = {0}, gre[64] = {0}, gim[64] = {0};
   // device data
-  DevBuf nodes, pos, grpmask, coef64, coef32, lam_ax, lam_in, tw64[3], tw32[3];
+  DevBuf nodes, pos, grpmask, rowmask, slabneed, storemask, coef64, coef32, lam_ax, lam_in, tw64[3], tw32[3];
+  // node usage counts for the byte model of the passes
+  double rows_used = 0;    // sum over pass-C rows of the nodes the row uses
+  double slabs_used = 0;   // sum over nodes of the axis-0 indices that use the node
   DevBuf t, fields;                  // apply workspace
   // solver workspace
   DevBuf V, z, tvec, state, part, flags;
@@ -64,7 +67,7 @@ struct hp_plan_s {
   size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
   const void* tw(int axis) const { return prec == HP_FP64 ? tw64[axis].p : tw32[axis].p; }
   void release_all() {
-    for (DevBuf* b : {&nodes, &pos, &grpmask, &coef64, &coef32, &lam_ax, &lam_in, &t, &fields, &V, &z, &tvec,
+    for (DevBuf* b : {&nodes, &pos, &grpmask, &rowmask, &slabneed, &storemask, &coef64, &coef32, &lam_ax, &lam_in, &t, &fields, &V, &z, &tvec,
                       &state, &part, &flags})
       b->release();
     for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
@@ -392,21 +395,42 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
         if (nc[k].are - nc[k].gre * (lam0[k0] + lamin[ci]) == 0.0) return fail(HP_E_MEDIA);
   }
 
-  // pass-C group masks: which nodes any point of a workgroup's rows uses
+  // Node usage.  Each point has at most two non-zero weights, so a row of
+  // pass C only needs the node fields its points use; the passes before it
+  // neither write nor transform the rest.
   const int nl = P->n[P->dim - 1];
   const size_t rows = np / nl;
   const int G = hp::combine_group_rows(P->real_kind(), nl);
-  std::vector<uint64_t> gm((rows + G - 1) / G, 0);
+  std::vector<uint64_t> rm(rows, 0), gm((rows + G - 1) / G, 0);
   for (size_t r = 0; r < rows; ++r) {
     uint64_t m = 0;
     for (int i = 0; i < nl; ++i) {
       int A, B;
       double t;
       point_nodes(*P, pos[r * nl + i], A, B, t);
-      m |= (1ull << A) | (1ull << B);
+      if (A == B || t != 1.0) m |= 1ull << A;
+      if (A != B && t != 0.0) m |= 1ull << B;
     }
+    rm[r] = m;
     gm[r / G] |= m;
+    P->rows_used += (double)__builtin_popcountll(m);
   }
+  const int n0 = P->n[0];
+  const size_t rows_per_slab = rows / n0;
+  std::vector<uint8_t> need((size_t)P->K * n0, 0);
+  for (int i0 = 0; i0 < n0; ++i0) {
+    uint64_t m = 0;
+    for (size_t r = 0; r < rows_per_slab; ++r) m |= rm[(size_t)i0 * rows_per_slab + r];
+    for (int k = 0; k < P->K; ++k)
+      if ((m >> k) & 1ull) { need[(size_t)k * n0 + i0] = 1; P->slabs_used += 1.0; }
+  }
+  const int Tb = hp::symbol_pass_line_threads(P->real_kind(), n0);
+  const int Eb = n0 / Tb;
+  std::vector<uint16_t> smask((size_t)P->K * Tb, 0);
+  for (int k = 0; k < P->K; ++k)
+    for (int j = 0; j < Tb; ++j)
+      for (int e = 0; e < Eb; ++e)
+        if (need[(size_t)k * n0 + j + (size_t)Tb * e]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e);
 
   // stencil coefficients {gamma^2, beta} (Section 5 with gamma of Section 4.3)
   double sih2 = 0, ih2[3] = {0, 0, 0};
@@ -427,6 +451,9 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   if ((e = upload(P->nodes, nc)) != hipSuccess) return fail(from_hip(e));
   if ((e = upload(P->pos, pos)) != hipSuccess) return fail(from_hip(e));
   if ((e = upload(P->grpmask, gm)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->rowmask, rm)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->slabneed, need)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->storemask, smask)) != hipSuccess) return fail(from_hip(e));
   if ((e = upload(P->coef64, cf)) != hipSuccess) return fail(from_hip(e));
   if (P->prec == HP_MIXED) {
     std::vector<cpx<float>> cf32(2 * np);
@@ -454,6 +481,8 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   if ((e = P->t.alloc(fb)) != hipSuccess) return fail(from_hip(e));
   if ((e = P->fields.alloc(fb * P->K)) != hipSuccess) return fail(from_hip(e));
   (void)stream;
+  // node-field rows that no point uses are never written; keep them finite
+  if ((e = hp::launch_fill_zero(P->fields.p, P->fields.bytes, nullptr)) != hipSuccess) return fail(from_hip(e));
   if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(from_hip(e));
   *out = P;
   return HP_OK;
@@ -489,15 +518,21 @@ namespace {
 
 // u (+)= Q_M v for nrhs <= max_nrhs right-hand sides.
 // in_kind/out_kind: 0 = complex128, 1 = complex64.
+// ev (optional): 6 events recorded before pass A and after each of the five
+// pass slots (A, A', B, M, C; the 3-D-only slots are recorded even when empty).
 hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, void* u, int out_kind,
-                     size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st) {
+                     size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st,
+                     hipEvent_t* ev = nullptr) {
   const int rk = P->real_kind();
   const size_t np = P->npts;
   hipError_t e;
   const int nl = P->n[P->dim - 1];
   const int rows = (int)(np / nl);
+  auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+  if ((e = mark(0)) != hipSuccess) return e;
   e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, st);
   if (e != hipSuccess) return e;
+  if ((e = mark(1)) != hipSuccess) return e;
   if (P->dim == 3) {   // forward along the middle axis, in place
     hp::ColsArgs m{};
     m.real_kind = rk; m.n = P->n[1]; m.dir = -1; m.mode = 0;
@@ -505,26 +540,43 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.in_rs = np; m.out_rs = np; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
   }
+  if ((e = mark(2)) != hipSuccess) return e;
   hp::ColsArgs b{};
   b.real_kind = rk; b.n = P->n[0]; b.dir = -1; b.mode = 1;
   b.in = P->t.p; b.out = P->fields.p; b.S = (int)(np / P->n[0]); b.outer = 1; b.nfields = 1; b.nrhs = nrhs;
   b.in_rs = np; b.out_rs = np * P->K; b.in_fs = np; b.out_fs = np; b.tw = P->tw(0); b.skip = skip;
   b.lam_ax = (const double*)P->lam_ax.p; b.lam_in = (const double*)P->lam_in.p;
   b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
+  b.store_mask = (const uint16_t*)P->storemask.p;
   if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
+  if ((e = mark(3)) != hipSuccess) return e;
   if (P->dim == 3) {   // inverse along the middle axis for the K fields, in place
     hp::ColsArgs m{};
     m.real_kind = rk; m.n = P->n[1]; m.dir = +1; m.mode = 0;
     m.in = P->fields.p; m.out = P->fields.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = P->K; m.nrhs = nrhs;
     m.in_rs = np * P->K; m.out_rs = np * P->K; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
+    m.slab_need = (const uint8_t*)P->slabneed.p;
     if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
   }
+  if ((e = mark(4)) != hipSuccess) return e;
   hp::CombineArgs c{};
   c.real_kind = rk; c.out_kind = out_kind; c.accumulate = acc ? 1 : 0; c.n = nl;
   c.fields = P->fields.p; c.fs = np; c.frs = np * P->K; c.pos = (const double*)P->pos.p;
-  c.grpmask = (const uint64_t*)P->grpmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
+  c.grpmask = (const uint64_t*)P->grpmask.p; c.rowmask = (const uint64_t*)P->rowmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
   c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
-  return hp::launch_combine(c, st);
+  if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
+  return mark(5);
+}
+
+// Algorithmic bytes of each pass for one launch over nrhs fields.
+void pass_bytes(const hp_plan_s* P, int nrhs, int in_bytes, int out_bytes, double* b) {
+  const double np = (double)P->npts, sf = (double)P->fsize(), nr = nrhs;
+  const double S = np / P->n[0];
+  b[0] = nr * np * (in_bytes + sf);
+  b[1] = P->dim == 3 ? nr * np * 2 * sf : 0.0;
+  b[2] = nr * (np * sf + P->slabs_used * S * sf);
+  b[3] = P->dim == 3 ? nr * P->slabs_used * S * 2 * sf : 0.0;
+  b[4] = nr * (np * (8.0 + out_bytes) + P->rows_used * P->n[P->dim - 1] * sf);
 }
 
 hipError_t run_stencil(hp_plan_s* P, int kind, const void* u, size_t u_rs, void* y, size_t y_rs,
@@ -667,6 +719,31 @@ hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_o
     if (s == HP_E_NOT_CONVERGED) ret = s;
   }
   return ret;
+}
+
+hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps, double* ms, double* bytes,
+                           void* stream) {
+  if (!p || !v || !u || !ms || !bytes || nrhs < 1 || nrhs > p->max_nrhs || reps < 1) return HP_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  const int kind = p->prec == HP_FP64 ? 0 : 1;
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) HP_TRY(hipEventCreate(&ev[i]));
+  double acc[5] = {0, 0, 0, 0, 0};
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < reps && err == hipSuccess; ++r) {
+    err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st, ev);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[5]);
+    for (int i = 0; i < 5 && err == hipSuccess; ++i) {
+      float t = 0;
+      err = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      acc[i] += t;
+    }
+  }
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+  HP_TRY(err);
+  for (int i = 0; i < 5; ++i) ms[i] = acc[i] / reps;
+  pass_bytes(p, nrhs, (int)p->fsize(), (int)p->fsize(), bytes);
+  return HP_OK;
 }
 
 hp_status hp_plan_destroy(hp_plan p) {

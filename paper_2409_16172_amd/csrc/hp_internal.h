@@ -62,6 +62,8 @@ struct ColsArgs {
   const NodeConst* nodes;
   int K;
   double scale;
+  const uint16_t* store_mask;   // mode 1: [K][T] bit s = axis-0 index j + T*s uses node n
+  const uint8_t* slab_need;     // mode 0 over node fields: [K][outer] != 0 if the slab uses node n
 };
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st);
 
@@ -72,7 +74,8 @@ struct CombineArgs {
   const void* fields;
   size_t fs, frs;
   const double* pos;
-  const uint64_t* grpmask;
+  const uint64_t* grpmask;   // per workgroup: nodes used by any of its rows
+  const uint64_t* rowmask;   // per row: nodes used by the row
   void* out;
   size_t out_rs;
   int rows, K, M, Mt, mo, nrhs;
@@ -80,7 +83,8 @@ struct CombineArgs {
   const int* skip;
 };
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
-int combine_group_rows(int real_kind, int n);  // rows per workgroup of pass C
+int combine_group_rows(int real_kind, int n);        // rows per workgroup of pass C
+int symbol_pass_line_threads(int real_kind, int n);  // threads per line T of pass B
 
 // Stencil.  kind: 0 = FP64 (c128 -> c128), 1 = FP32 arithmetic c64 -> c64,
 // 2 = FP32 arithmetic c64 -> c128, 3 = FP64 residual y = f - P u (c128).

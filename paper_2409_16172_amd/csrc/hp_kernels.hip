@@ -101,13 +101,16 @@ __global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>()>::THREADS)) 
     const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
     size_t out_rs, size_t in_fs, size_t out_fs, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip, const double* __restrict__ lam_ax, const double* __restrict__ lam_in,
-    const NodeConst* __restrict__ nodes, int K, double scale) {
+    const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
+    const uint8_t* __restrict__ slab_need) {
   using C = ColCfg<R, N, cols_max_threads<MODE>()>;
   __shared__ cpx<R> lds[C::LDS];
   const int z = blockIdx.z;
   const int rhs = (MODE == 0) ? z / nfields : z;
   const int fld = (MODE == 0) ? z % nfields : 0;
   if (skip != nullptr && skip[rhs] != 0) return;
+  // plain passes over node fields: slabs whose points never use this node are skipped
+  if (MODE == 0 && slab_need != nullptr && slab_need[(size_t)fld * gridDim.y + blockIdx.y] == 0) return;
   const int g = threadIdx.x % C::TC, j = threadIdx.x / C::TC;
   const int c = blockIdx.x * C::TC + g;
   const bool act = c < S;
@@ -139,10 +142,11 @@ __global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>()>::THREADS)) 
     for (int n = 0; n < K; ++n) {
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
       fft<R, N, +1>(x, lg, j, tw);
-      if (act) {
+      // bit s: some point of axis-0 index j + T*s uses node n (else the row is never read)
+      const uint32_t m = act ? (uint32_t)store_mask[n * C::T + j] : 0u;
 #pragma unroll
-        for (int s = 0; s < C::E; ++s) dst[(size_t)n * out_fs + (size_t)(j + C::T * s) * S] = x[s];
-      }
+      for (int s = 0; s < C::E; ++s)
+        if ((m >> s) & 1u) dst[(size_t)n * out_fs + (size_t)(j + C::T * s) * S] = x[s];
     }
   }
 }
@@ -172,8 +176,9 @@ __device__ __forceinline__ void decode_pos(double p, int M, int Mt, int mo, int&
 template <typename R, typename TO, int N, bool ACC>
 __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_combine(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
-    const uint64_t* __restrict__ grpmask, cpx<TO>* __restrict__ out, size_t out_rs, int rows, int K,
-    int M, int Mt, int mo, const cpx<R>* __restrict__ tw, const int* __restrict__ skip) {
+    const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
+    size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
+    const int* __restrict__ skip) {
   using C = RowCfg<R, N>;
   __shared__ cpx<R> lds[C::LDS];
   const int rhs = blockIdx.y;
@@ -195,13 +200,16 @@ __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_combine(
     acc[s] = {0, 0};
   }
   const uint64_t mask = grpmask[blockIdx.x];
+  const uint64_t rmask = act ? rowmask[row] : 0ull;
   const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
   cpx<R>* lg = lds + g * lds_elems<R>(N);
   for (int n = 0; n < K; ++n) {
     if (((mask >> n) & 1ull) == 0) continue;   // no point of this group uses node n
+    // rows that do not use node n contribute nothing and were not written by pass B
+    const bool ld = ((rmask >> n) & 1ull) != 0;
     cpx<R> x[C::E];
 #pragma unroll
-    for (int s = 0; s < C::E; ++s) x[s] = act ? fr[(size_t)n * fs + j + C::T * s] : cpx<R>{0, 0};
+    for (int s = 0; s < C::E; ++s) x[s] = ld ? fr[(size_t)n * fs + j + C::T * s] : cpx<R>{0, 0};
     fft<R, N, +1>(x, lg, j, tw);
 #pragma unroll
     for (int s = 0; s < C::E; ++s) {
@@ -288,15 +296,15 @@ struct ColsL {
         if (a.mode == 1)
           hipLaunchKernelGGL((k_cols<R, R, N, -1, 1>), grid, dim3(C1::THREADS), 0, st, in, out, a.S,
                              a.nfields, a.in_rs, a.out_rs, a.in_fs, a.out_fs, tw, a.skip, a.lam_ax,
-                             a.lam_in, a.nodes, a.K, a.scale);
+                             a.lam_in, a.nodes, a.K, a.scale, a.store_mask, a.slab_need);
         else if (a.dir < 0)
           hipLaunchKernelGGL((k_cols<R, R, N, -1, 0>), grid, dim3(C0::THREADS), 0, st, in, out, a.S,
                              a.nfields, a.in_rs, a.out_rs, a.in_fs, a.out_fs, tw, a.skip, a.lam_ax,
-                             a.lam_in, a.nodes, a.K, a.scale);
+                             a.lam_in, a.nodes, a.K, a.scale, a.store_mask, a.slab_need);
         else
           hipLaunchKernelGGL((k_cols<R, R, N, +1, 0>), grid, dim3(C0::THREADS), 0, st, in, out, a.S,
                              a.nfields, a.in_rs, a.out_rs, a.in_fs, a.out_fs, tw, a.skip, a.lam_ax,
-                             a.lam_in, a.nodes, a.K, a.scale);
+                             a.lam_in, a.nodes, a.K, a.scale, a.store_mask, a.slab_need);
         return hipGetLastError();
       }
     }
@@ -316,7 +324,7 @@ struct CombineL {
       using C = RowCfg<R, N>;
       dim3 grid((a.rows + C::G - 1) / C::G, a.nrhs);
       hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC>), grid, dim3(C::THREADS), 0, st,
-                         (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, (cpx<TO>*)a.out,
+                         (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
                          a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip);
       return hipGetLastError();
     }
@@ -352,6 +360,27 @@ int group_rows(int n) {
     case 4096: return RowCfg<R, 4096>::G;
     default: return 1;
   }
+}
+
+template <typename R>
+int sym_line_threads(int n) {
+  switch (n) {
+    case 8: return ColCfg<R, 8, 512>::T;
+    case 16: return ColCfg<R, 16, 512>::T;
+    case 32: return ColCfg<R, 32, 512>::T;
+    case 64: return ColCfg<R, 64, 512>::T;
+    case 128: return ColCfg<R, 128, 512>::T;
+    case 256: return ColCfg<R, 256, 512>::T;
+    case 512: return ColCfg<R, 512, 512>::T;
+    case 1024: return ColCfg<R, 1024, 512>::T;
+    case 2048: return ColCfg<R, 2048, 512>::T;
+    case 4096: return ColCfg<R, 4096, 512>::T;
+    default: return 1;
+  }
+}
+
+int symbol_pass_line_threads(int real_kind, int n) {
+  return real_kind == 0 ? sym_line_threads<double>(n) : sym_line_threads<float>(n);
 }
 
 int combine_group_rows(int real_kind, int n) {
