@@ -82,6 +82,29 @@ def cpu_baseline(w, gpu_iters, gpu_cycles, steps=6):
                       f"to {gpu_iters} steps and {gpu_cycles} cycles = {t_solve:.1f} s"}
 
 
+def apply_only(args, w, plan, dev):
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(0)
+    vh = rng.standard_normal((w.f.shape[0],) + w.shape) + 1j * rng.standard_normal((w.f.shape[0],) + w.shape)
+    v = torch.from_numpy(vh).to(dev).to(plan.field_dtype)
+    plan.profile_apply(v, reps=2)
+    ms, by = plan.profile_apply(v, reps=args.apply_reps)
+    # a plain device copy of known size (2^28 bytes read, 2^28 written) as the counter reference
+    src = torch.ones(1 << 24, dtype=torch.complex128, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out = {"mode": "apply", "workload": w.name, "precision": plan.precision, "apply_reps": args.apply_reps,
+           "pass_us": dict(zip(PASS_NAMES, [t * 1e3 for t in ms])), "pass_bytes": dict(zip(PASS_NAMES, by)),
+           "pass_GBps": dict(zip(PASS_NAMES, [b / (t * 1e-3) / 1e9 if t > 0 else 0 for b, t in zip(by, ms)])),
+           "apply_us": sum(ms) * 1e3, "apply_GBps": sum(by) / (sum(ms) * 1e-3) / 1e9,
+           "copy_reference_bytes": {"read": 1 << 28, "write": 1 << 28, "launches": 3},
+           "source_hash": source_hash()}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +114,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--apply-reps", type=int, default=20)
+    ap.add_argument("--mode", choices=["solve", "apply"], default="solve",
+                    help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
+                         "(used to calibrate hardware byte counters)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -104,8 +131,13 @@ def main():
 
     dev = torch.device("cuda:0")
     w = inputs.workload(args.workload)
+    if args.precision:
+        w.precision = args.precision
     plan = binding.plan_from_workload(w)
     f = torch.from_numpy(w.f).to(dev)
+    if args.mode == "apply":
+        apply_only(args, w, plan, dev)
+        return
     rtol, restart = 1e-8, 30
     print(f"[bench] workload {w.name} {w.shape} K={plan.info()['K']} warmup {args.warmup}", file=sys.stderr,
           flush=True)

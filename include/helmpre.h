@@ -181,6 +181,10 @@ hp_status hp_plan_destroy(hp_plan p);
 
 const char* hp_status_str(hp_status st);
 
+/* Description of the last HIP failure on this thread (function, source line and
+ * the runtime's message), or "" if none. */
+const char* hp_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

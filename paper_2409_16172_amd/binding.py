@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": HP_FP64, "mixed": HP_MIXED}
 
 EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_bytes", "hp_plan_query",
             "hp_apply_precond", "hp_matvec", "hp_solve", "hp_profile_apply", "hp_plan_destroy",
-            "hp_status_str"]
+            "hp_status_str", "hp_last_error"]
 
 
 class HpGrid(C.Structure):
@@ -66,6 +66,9 @@ def load_library(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime; it must be the one in the process before this
+    # library is mapped, so that both share one runtime (tensors, streams).
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise OSError(f"{path} is not built; run __graft_entry__.build() or "
                       "python paper_2409_16172_amd/build.py")
@@ -92,14 +95,18 @@ def load_library(path: str = LIB_PATH):
     lib.hp_plan_destroy.restype = i
     lib.hp_status_str.argtypes = [i]
     lib.hp_status_str.restype = C.c_char_p
+    lib.hp_last_error.argtypes = []
+    lib.hp_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
 
 class HelmpreError(RuntimeError):
     def __init__(self, code: int, where: str):
-        msg = load_library().hp_status_str(code).decode()
-        super().__init__(f"{where}: {msg} (status {code})")
+        lib = load_library()
+        msg = lib.hp_status_str(code).decode()
+        detail = lib.hp_last_error().decode() if code in (HP_E_DEVICE, HP_E_NOMEM) else ""
+        super().__init__(f"{where}: {msg} (status {code})" + (f" [{detail}]" if detail else ""))
         self.code = code
 
 

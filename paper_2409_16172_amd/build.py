@@ -18,15 +18,16 @@ HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Wall", "-Wno-unused-result", "-munsafe-fp-atomics"]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 2, defines=(), out: str = LIB, objdir: str = None) -> str:
+    """Compile the sources and link `out`.  `defines`: extra -D options (tuning variants)."""
+    objdir = objdir or os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = ["hipcc", *HIPFLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *HIPFLAGS, *["-D" + d for d in defines], *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))
@@ -38,13 +39,13 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     for p, name in procs:
         if p.wait() != 0:
             raise RuntimeError(f"hipcc failed on {name}")
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -78,11 +79,14 @@ struct hp_plan_s {
 
 namespace {
 
-hp_status from_hip(hipError_t e) {
-  if (e == hipSuccess) return HP_OK;
-  if (e == hipErrorOutOfMemory) return HP_E_NOMEM;
-  return HP_E_DEVICE;
+thread_local char g_last_error[256] = "";
+
+hp_status record(hipError_t e, const char* where, int line) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s (line %d): %s", where, line, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? HP_E_NOMEM : HP_E_DEVICE;
 }
+
+#define from_hip(e) ((e) == hipSuccess ? HP_OK : record((e), __func__, __LINE__))
 
 #define HP_TRY(expr)                         \
   do {                                       \
@@ -217,6 +221,8 @@ hp_status check_grid(const hp_grid* g, int prec) {
 }  // namespace
 
 extern "C" {
+
+const char* hp_last_error(void) { return g_last_error; }
 
 const char* hp_status_str(hp_status st) {
   switch (st) {
@@ -528,7 +534,10 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   hipError_t e;
   const int nl = P->n[P->dim - 1];
   const int rows = (int)(np / nl);
-  auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+  // the middle-axis slots (2 and 4) only exist in 3-D
+  auto mark = [&](int i) {
+    return (ev && (P->dim == 3 || (i != 2 && i != 4))) ? hipEventRecord(ev[i], st) : hipSuccess;
+  };
   if ((e = mark(0)) != hipSuccess) return e;
   e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, st);
   if (e != hipSuccess) return e;
@@ -733,9 +742,13 @@ hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps
   for (int r = 0; r < reps && err == hipSuccess; ++r) {
     err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st, ev);
     if (err == hipSuccess) err = hipEventSynchronize(ev[5]);
+    const int slots3[5][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}};
+    const int slots2[5][2] = {{0, 1}, {-1, -1}, {1, 3}, {-1, -1}, {3, 5}};
     for (int i = 0; i < 5 && err == hipSuccess; ++i) {
+      const int a = p->dim == 3 ? slots3[i][0] : slots2[i][0], b = p->dim == 3 ? slots3[i][1] : slots2[i][1];
+      if (a < 0) continue;
       float t = 0;
-      err = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+      err = hipEventElapsedTime(&t, ev[a], ev[b]);
       acc[i] += t;
     }
   }

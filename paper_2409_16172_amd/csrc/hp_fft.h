@@ -110,11 +110,35 @@ __device__ __forceinline__ int lpad(int i) { return i + i / E; }
 template <int E>
 __host__ __device__ constexpr int lds_elems_e(int n) { return n + n / E; }
 
-// Elements per thread: 8 complex doubles or 16 complex floats (64 VGPRs either
-// way), fewer for tiny transforms.
+// Elements per thread (fewer for tiny transforms).
+#ifndef HP_E64
+#define HP_E64 8
+#endif
+#ifndef HP_E32
+#define HP_E32 16
+#endif
 template <typename R>
 __host__ __device__ constexpr int elems_per_thread(int n) {
-  return n < (sizeof(R) == 8 ? 8 : 16) ? n : (sizeof(R) == 8 ? 8 : 16);
+  return n < (sizeof(R) == 8 ? HP_E64 : HP_E32) ? n : (sizeof(R) == 8 ? HP_E64 : HP_E32);
+}
+
+// Synchronisation between the LDS write and read of an exchange.  When every
+// transform lives inside one wavefront (its T threads are consecutive and T
+// divides 64) the wavefront's own ordering of LDS operations suffices, with
+// fences that keep the compiler from moving LDS accesses across.
+template <bool WAVE>
+__device__ __forceinline__ void xsync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    // workgroup barrier ordering LDS only: global loads issued before it (e.g. the
+    // next node's data or twiddles) stay in flight
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  }
 }
 
 template <int N, int NS, int E>
@@ -124,7 +148,10 @@ __host__ __device__ constexpr int stage_radix() {
 
 // One Stockham stage of radix R at sub-transform size NS, then the next stage.
 // tw: table of exp(-2 pi i m / N), m < N.
-template <typename R, int N, int E, int DIR, int NS>
+// ILV: several transforms share one LDS array with their elements interleaved
+// (element p of transform g at lpad(p) * ILV + g; the caller passes lds + g),
+// so that lanes of neighbouring transforms touch neighbouring banks.
+template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV>
 struct Stage {
   __device__ __forceinline__ static void run(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
     constexpr int RS = stage_radix<N, NS, E>();
@@ -152,15 +179,15 @@ struct Stage {
       } else {
         const int base = (b / NS) * NS * RS + k;
 #pragma unroll
-        for (int t = 0; t < RS; ++t) lds[lpad<E>(base + t * NS)] = out[t];
+        for (int t = 0; t < RS; ++t) lds[lpad<E>(base + t * NS) * ILV] = out[t];
       }
     }
     if constexpr (!last) {
-      __syncthreads();
+      xsync<WAVE>();
 #pragma unroll
-      for (int s = 0; s < E; ++s) x[s] = lds[lpad<E>(j + T * s)];
-      __syncthreads();
-      Stage<R, N, E, DIR, NS * RS>::run(x, lds, j, tw);
+      for (int s = 0; s < E; ++s) x[s] = lds[lpad<E>(j + T * s) * ILV];
+      xsync<WAVE>();
+      Stage<R, N, E, DIR, NS * RS, WAVE, ILV>::run(x, lds, j, tw);
     }
   }
 };
@@ -168,12 +195,15 @@ struct Stage {
 template <typename R>
 __host__ __device__ constexpr int lds_elems(int n) { return lds_elems_e<elems_per_thread<R>(8192)>(n); }
 
-// Full transform.  All threads of the workgroup must call it together
-// (it contains workgroup barriers when N > E).
-template <typename R, int N, int DIR>
+// Full transform.  All threads of the workgroup must call it together (it
+// contains workgroup barriers when N > E, unless CONTIG says that the T threads
+// of a transform are consecutive, in which case transforms of at most 64
+// threads synchronise within their wavefront only).
+template <typename R, int N, int DIR, bool CONTIG = false, int ILV = 1>
 __device__ __forceinline__ void fft(cpx<R> (&x)[elems_per_thread<R>(N)], cpx<R>* lds, int j,
                                     const cpx<R>* __restrict__ tw) {
-  Stage<R, N, elems_per_thread<R>(N), DIR, 1>::run(x, lds, j, tw);
+  constexpr int T = N / elems_per_thread<R>(N);
+  Stage<R, N, elems_per_thread<R>(N), DIR, 1, CONTIG && (T <= 64), ILV>::run(x, lds, j, tw);
 }
 
 }  // namespace hp

@@ -35,7 +35,7 @@ struct KState {
 };
 
 constexpr int kRedThreads = 256;   // threads per block of the reduction kernels
-constexpr int kRedBlocks = 512;    // blocks per right-hand side (fixed: deterministic sums)
+constexpr int kRedBlocks = 1024;   // blocks per right-hand side (fixed: deterministic sums)
 constexpr int kPartSlots = kMaxRestart + 2;
 
 // ---- launchers (all enqueue on `st`, return the launch status) ----

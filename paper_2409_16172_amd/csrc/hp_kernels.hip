@@ -22,29 +22,49 @@ __device__ __forceinline__ cpx<R> cvt(cpx<S> a) {
 
 // Rows (contiguous axis): G lines of length N per workgroup of 256 threads
 // (one line per workgroup when a line needs 256 threads or more).
-template <typename R, int N>
+#ifndef HP_ROWC_THREADS
+#define HP_ROWC_THREADS 128
+#endif
+#ifndef HP_PREFETCH_C
+#define HP_PREFETCH_C 0
+#endif
+template <typename R, int N, int WG = 256>
 struct RowCfg {
   static constexpr int E = elems_per_thread<R>(N);
   static constexpr int T = N / E;
-  static constexpr int G = T >= 256 ? 1 : 256 / T;
+  static constexpr int G = T >= WG ? 1 : WG / T;
   static constexpr int THREADS = G * T;
   static constexpr int LDS = (N > E) ? G * lds_elems<R>(N) : 1;
 };
+template <typename R, int N>
+using CombCfg = RowCfg<R, N, HP_ROWC_THREADS>;
 
-// Column tiles (strided axis): TC adjacent columns per workgroup, aiming at
-// 64-byte row segments, at least 256 threads, and at most MAXT threads.
-template <typename R, int N, int MAXT>
+// Column tiles (strided axis): TC adjacent columns per workgroup.  Plain
+// passes aim at 64-byte row segments; the symbol pass, whose workgroups stay
+// resident through K transforms, uses the smallest workgroup (>= 256 threads)
+// that still reads and writes 32-byte row segments, so that more independent
+// workgroups share a CU.
+template <typename R, int N, int MAXT, int SEG = 64>
 struct ColCfg {
   static constexpr int E = elems_per_thread<R>(N);
   static constexpr int T = N / E;
-  static constexpr int TC0 = 64 / (2 * (int)sizeof(R));
+  static constexpr int TC0 = SEG / (2 * (int)sizeof(R));
   static constexpr int THR0 = TC0 * T < 256 ? 256 : TC0 * T;
   static constexpr int THREADS = THR0 > MAXT ? MAXT : THR0;
   static constexpr int TC = THREADS / T;
   static constexpr int LDS = (N > E) ? TC * lds_elems<R>(N) : 1;
 };
+#ifndef HP_SYM_MAXT
+#define HP_SYM_MAXT 512
+#endif
+#ifndef HP_SYM_SEG
+#define HP_SYM_SEG 32
+#endif
+#ifndef HP_XCD_REMAP
+#define HP_XCD_REMAP 1
+#endif
 template <int MODE>
-constexpr int cols_max_threads() { return MODE == 1 ? 512 : 1024; }
+constexpr int cols_max_threads() { return MODE == 1 ? HP_SYM_MAXT : 1024; }
 
 // ---------------------------------------------------------------- pass A
 template <typename R, typename TI, int N>
@@ -64,7 +84,7 @@ __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_fwd(const cpx<
   cpx<R> x[C::E];
 #pragma unroll
   for (int s = 0; s < C::E; ++s) x[s] = act ? cvt<R>(src[j + C::T * s]) : cpx<R>{0, 0};
-  fft<R, N, -1>(x, lds + g * lds_elems<R>(N), j, tw);
+  fft<R, N, -1, true>(x, lds + g * lds_elems<R>(N), j, tw);
   if (act) {
     cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)row * N;
 #pragma unroll
@@ -73,6 +93,21 @@ __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_fwd(const cpx<
 }
 
 // ---------------------------------------------------------------- strided passes
+// 1/x for finite x > 0: hardware reciprocal estimate refined by Newton-Raphson
+// steps r <- r + r (1 - x r) (two in FP64, one in FP32).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+
 // Symbol multiply of one node on the elements a thread holds.  The denominator
 // A_n - g_n lambda is formed in FP64 (it cancels near |xi| = omega/|gamma_n|),
 // then reciprocated in the working precision.
@@ -85,11 +120,11 @@ __device__ __forceinline__ void symbol_mul(const cpx<R> (&vh)[E], cpx<R> (&x)[E]
     const double dim = nc.aim - nc.gim * lam[s];
     cpx<R> q;
     if constexpr (sizeof(R) == 8) {
-      const double inv = scale / (dre * dre + dim * dim);
+      const double inv = scale * recip(dre * dre + dim * dim);
       q = {dre * inv, -dim * inv};
     } else {
       const float fr = (float)dre, fi = (float)dim;
-      const float inv = (float)scale / (fr * fr + fi * fi);
+      const float inv = (float)scale * recip(fr * fr + fi * fi);
       q = {fr * inv, -fi * inv};
     }
     x[s] = cmul(vh[s], q);
@@ -97,13 +132,13 @@ __device__ __forceinline__ void symbol_mul(const cpx<R> (&vh)[E], cpx<R> (&x)[E]
 }
 
 template <typename R, typename TI, int N, int DIR, int MODE>
-__global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>()>::THREADS)) void k_cols(
+__global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>(), MODE == 1 ? HP_SYM_SEG : 64>::THREADS)) void k_cols(
     const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
     size_t out_rs, size_t in_fs, size_t out_fs, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip, const double* __restrict__ lam_ax, const double* __restrict__ lam_in,
     const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
     const uint8_t* __restrict__ slab_need) {
-  using C = ColCfg<R, N, cols_max_threads<MODE>()>;
+  using C = ColCfg<R, N, cols_max_threads<MODE>(), MODE == 1 ? HP_SYM_SEG : 64>;
   __shared__ cpx<R> lds[C::LDS];
   const int z = blockIdx.z;
   const int rhs = (MODE == 0) ? z / nfields : z;
@@ -112,24 +147,31 @@ __global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>()>::THREADS)) 
   // plain passes over node fields: slabs whose points never use this node are skipped
   if (MODE == 0 && slab_need != nullptr && slab_need[(size_t)fld * gridDim.y + blockIdx.y] == 0) return;
   const int g = threadIdx.x % C::TC, j = threadIdx.x / C::TC;
-  const int c = blockIdx.x * C::TC + g;
+  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+  // L2).  Give the workgroups of one XCD consecutive column tiles so that tiles
+  // sharing cache lines meet in the same L2.
+  int tile = blockIdx.x;
+#if HP_XCD_REMAP
+  if ((gridDim.x & 7) == 0) tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+#endif
+  const int c = tile * C::TC + g;
   const bool act = c < S;
   const size_t obase = (size_t)blockIdx.y * N * S + c;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
-  cpx<R>* lg = lds + g * lds_elems<R>(N);
+  cpx<R>* lg = lds + g;   // the TC columns are interleaved in LDS
   cpx<R> x[C::E];
 #pragma unroll
   for (int s = 0; s < C::E; ++s)
     x[s] = act ? cvt<R>(src[(size_t)(j + C::T * s) * S]) : cpx<R>{0, 0};
   if constexpr (MODE == 0) {
-    fft<R, N, DIR>(x, lg, j, tw);
+    fft<R, N, DIR, false, C::TC>(x, lg, j, tw);
     if (act) {
       cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)fld * out_fs + obase;
 #pragma unroll
       for (int s = 0; s < C::E; ++s) dst[(size_t)(j + C::T * s) * S] = x[s];
     }
   } else {
-    fft<R, N, -1>(x, lg, j, tw);
+    fft<R, N, -1, false, C::TC>(x, lg, j, tw);
     cpx<R> vh[C::E];
     double lam[C::E];
     const double lc = act ? lam_in[c] : 0.0;
@@ -141,7 +183,7 @@ __global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>()>::THREADS)) 
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
     for (int n = 0; n < K; ++n) {
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
-      fft<R, N, +1>(x, lg, j, tw);
+      fft<R, N, +1, false, C::TC>(x, lg, j, tw);
       // bit s: some point of axis-0 index j + T*s uses node n (else the row is never read)
       const uint32_t m = act ? (uint32_t)store_mask[n * C::T + j] : 0u;
 #pragma unroll
@@ -174,12 +216,12 @@ __device__ __forceinline__ void decode_pos(double p, int M, int Mt, int mo, int&
 }
 
 template <typename R, typename TO, int N, bool ACC>
-__global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_combine(
+__global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
     const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
     size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip) {
-  using C = RowCfg<R, N>;
+  using C = CombCfg<R, N>;
   __shared__ cpx<R> lds[C::LDS];
   const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
@@ -203,14 +245,39 @@ __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_combine(
   const uint64_t rmask = act ? rowmask[row] : 0ull;
   const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
   cpx<R>* lg = lds + g * lds_elems<R>(N);
-  for (int n = 0; n < K; ++n) {
-    if (((mask >> n) & 1ull) == 0) continue;   // no point of this group uses node n
-    // rows that do not use node n contribute nothing and were not written by pass B
+  // Nodes no point of this group uses are skipped; rows that do not use a node
+  // read zeros (pass B did not write them).  The next used node's row is loaded
+  // while the current one is transformed.
+  auto next_node = [&](int n) {
+    while (n < K && ((mask >> n) & 1ull) == 0) ++n;
+    return n;
+  };
+  cpx<R> nx[C::E];
+  int n = next_node(0);
+  if (!HP_PREFETCH_C && n < K) {
+    // loaded at the top of the loop instead
+  } else if (n < K) {
     const bool ld = ((rmask >> n) & 1ull) != 0;
-    cpx<R> x[C::E];
 #pragma unroll
-    for (int s = 0; s < C::E; ++s) x[s] = ld ? fr[(size_t)n * fs + j + C::T * s] : cpx<R>{0, 0};
-    fft<R, N, +1>(x, lg, j, tw);
+    for (int s = 0; s < C::E; ++s) nx[s] = ld ? fr[(size_t)n * fs + j + C::T * s] : cpx<R>{0, 0};
+  }
+  for (; n < K;) {
+    cpx<R> x[C::E];
+    const int n2 = next_node(n + 1);
+    if (!HP_PREFETCH_C) {
+      const bool ld = ((rmask >> n) & 1ull) != 0;
+#pragma unroll
+      for (int s = 0; s < C::E; ++s) x[s] = ld ? fr[(size_t)n * fs + j + C::T * s] : cpx<R>{0, 0};
+    } else {
+#pragma unroll
+      for (int s = 0; s < C::E; ++s) x[s] = nx[s];
+    }
+    if (HP_PREFETCH_C && n2 < K) {
+      const bool ld = ((rmask >> n2) & 1ull) != 0;
+#pragma unroll
+      for (int s = 0; s < C::E; ++s) nx[s] = ld ? fr[(size_t)n2 * fs + j + C::T * s] : cpx<R>{0, 0};
+    }
+    fft<R, N, +1, true>(x, lg, j, tw);
 #pragma unroll
     for (int s = 0; s < C::E; ++s) {
       const int A = ab[s] & 0xff, B = (ab[s] >> 8) & 0xff;
@@ -218,6 +285,7 @@ __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_combine(
       acc[s].re += w * x[s].re;
       acc[s].im += w * x[s].im;
     }
+    n = n2;
   }
   if (act) {
     cpx<TO>* dst = out + (size_t)rhs * out_rs + rbase;
@@ -284,7 +352,7 @@ struct ColsL {
   struct F {
     static hipError_t run(const ColsArgs& a, hipStream_t st) {
       using C0 = ColCfg<R, N, cols_max_threads<0>()>;
-      using C1 = ColCfg<R, N, cols_max_threads<1>()>;
+      using C1 = ColCfg<R, N, cols_max_threads<1>(), HP_SYM_SEG>;
       if constexpr (sizeof(R) == 8 && N > 2048) {
         return hipErrorInvalidValue;   // the FP64 column tile would not fit in LDS
       } else {
@@ -321,7 +389,7 @@ struct CombineL {
   template <int N>
   struct F {
     static hipError_t run(const CombineArgs& a, hipStream_t st) {
-      using C = RowCfg<R, N>;
+      using C = CombCfg<R, N>;
       dim3 grid((a.rows + C::G - 1) / C::G, a.nrhs);
       hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC>), grid, dim3(C::THREADS), 0, st,
                          (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
@@ -348,16 +416,16 @@ hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
 template <typename R>
 int group_rows(int n) {
   switch (n) {
-    case 8: return RowCfg<R, 8>::G;
-    case 16: return RowCfg<R, 16>::G;
-    case 32: return RowCfg<R, 32>::G;
-    case 64: return RowCfg<R, 64>::G;
-    case 128: return RowCfg<R, 128>::G;
-    case 256: return RowCfg<R, 256>::G;
-    case 512: return RowCfg<R, 512>::G;
-    case 1024: return RowCfg<R, 1024>::G;
-    case 2048: return RowCfg<R, 2048>::G;
-    case 4096: return RowCfg<R, 4096>::G;
+    case 8: return CombCfg<R, 8>::G;
+    case 16: return CombCfg<R, 16>::G;
+    case 32: return CombCfg<R, 32>::G;
+    case 64: return CombCfg<R, 64>::G;
+    case 128: return CombCfg<R, 128>::G;
+    case 256: return CombCfg<R, 256>::G;
+    case 512: return CombCfg<R, 512>::G;
+    case 1024: return CombCfg<R, 1024>::G;
+    case 2048: return CombCfg<R, 2048>::G;
+    case 4096: return CombCfg<R, 4096>::G;
     default: return 1;
   }
 }
@@ -365,16 +433,16 @@ int group_rows(int n) {
 template <typename R>
 int sym_line_threads(int n) {
   switch (n) {
-    case 8: return ColCfg<R, 8, 512>::T;
-    case 16: return ColCfg<R, 16, 512>::T;
-    case 32: return ColCfg<R, 32, 512>::T;
-    case 64: return ColCfg<R, 64, 512>::T;
-    case 128: return ColCfg<R, 128, 512>::T;
-    case 256: return ColCfg<R, 256, 512>::T;
-    case 512: return ColCfg<R, 512, 512>::T;
-    case 1024: return ColCfg<R, 1024, 512>::T;
-    case 2048: return ColCfg<R, 2048, 512>::T;
-    case 4096: return ColCfg<R, 4096, 512>::T;
+    case 8: return ColCfg<R, 8, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 16: return ColCfg<R, 16, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 32: return ColCfg<R, 32, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 64: return ColCfg<R, 64, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 128: return ColCfg<R, 128, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 256: return ColCfg<R, 256, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 512: return ColCfg<R, 512, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 1024: return ColCfg<R, 1024, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 2048: return ColCfg<R, 2048, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 4096: return ColCfg<R, 4096, cols_max_threads<1>(), HP_SYM_SEG>::T;
     default: return 1;
   }
 }
@@ -702,7 +770,8 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi_update(cpx<double>* __r
   const int reorth = S.reorth;
   if (stage == 2 && !reorth) return;
   const bool final_pass = (stage == 2) || !reorth;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) coef[i] = stage == 1 ? S.h[i] : S.h2[i];
+  for (int i = threadIdx.x; i <= kMaxRestart; i += blockDim.x)
+    coef[i] = i > j ? cpx<double>{0.0, 0.0} : (stage == 1 ? S.h[i] : S.h2[i]);
   __syncthreads();
   const double inv = final_pass ? 1.0 / S.hnext : 1.0;
   cpx<double>* Vr = V + (size_t)rhs * vrs;
@@ -711,10 +780,17 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi_update(cpx<double>* __r
   if (final_pass) {
     for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
       cpx<double> a = w[i];
-      for (int v = 0; v <= j; ++v) {
-        const cpx<double> b = Vr[(size_t)v * npts + i], c = coef[v];
-        a.re -= c.re * b.re - c.im * b.im;
-        a.im -= c.re * b.im + c.im * b.re;
+      // groups of 8 basis vectors: their loads are independent and issued together
+      for (int v0 = 0; v0 <= j; v0 += 8) {
+        cpx<double> b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = (v0 + u <= j) ? Vr[(size_t)(v0 + u) * npts + i] : cpx<double>{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const cpx<double> c = coef[v0 + u < kMaxRestart + 1 ? v0 + u : kMaxRestart];
+          a.re -= c.re * b[u].re - c.im * b[u].im;
+          a.im -= c.re * b[u].im + c.im * b[u].re;
+        }
       }
       w[i] = cscale(a, inv);
     }
@@ -726,10 +802,16 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi_update(cpx<double>* __r
     cpx<double> nrm[1] = {{0.0, 0.0}};
     for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
       cpx<double> a = w[i];
-      for (int v = 0; v <= j; ++v) {
-        const cpx<double> b = Vr[(size_t)v * npts + i], c = coef[v];
-        a.re -= c.re * b.re - c.im * b.im;
-        a.im -= c.re * b.im + c.im * b.re;
+      for (int v0 = 0; v0 <= j; v0 += 8) {
+        cpx<double> b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = (v0 + u <= j) ? Vr[(size_t)(v0 + u) * npts + i] : cpx<double>{0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const cpx<double> c = coef[v0 + u < kMaxRestart + 1 ? v0 + u : kMaxRestart];
+          a.re -= c.re * b[u].re - c.im * b[u].im;
+          a.im -= c.re * b[u].im + c.im * b[u].re;
+        }
       }
       w[i] = a;
       nrm[0].re += a.re * a.re + a.im * a.im;
@@ -790,10 +872,16 @@ __global__ __launch_bounds__(256) void k_lincomb(const cpx<double>* __restrict__
   cpx<double>* o = out + (size_t)rhs * out_rs;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < npts; i += (size_t)gridDim.x * 256) {
     cpx<double> a = {0.0, 0.0};
-    for (int v = 0; v < k; ++v) {
-      const cpx<double> b = Vr[(size_t)v * npts + i], c = y[v];
-      a.re += c.re * b.re - c.im * b.im;
-      a.im += c.re * b.im + c.im * b.re;
+    for (int v0 = 0; v0 < k; v0 += 8) {
+      cpx<double> b[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = (v0 + u < k) ? Vr[(size_t)(v0 + u) * npts + i] : cpx<double>{0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const cpx<double> c = (v0 + u < k) ? y[v0 + u] : cpx<double>{0.0, 0.0};
+        a.re += c.re * b[u].re - c.im * b[u].im;
+        a.im += c.re * b[u].im + c.im * b[u].re;
+      }
     }
     o[i] = a;
   }
