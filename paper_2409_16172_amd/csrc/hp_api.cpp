@@ -63,6 +63,7 @@ struct hp_plan_s {
   DevBuf V, z, tvec, state, part, flags;
   int ws_restart = 0, ws_nrhs = 0;
   void* pinned = nullptr;
+  hipEvent_t step_ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
   int real_kind() const { return prec == HP_FP64 ? 0 : 1; }
   size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
@@ -74,6 +75,10 @@ struct hp_plan_s {
     for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
+    for (hipEvent_t& e : step_ev) {
+      if (e) (void)hipEventDestroy(e);
+      e = nullptr;
+    }
   }
 };
 
@@ -642,10 +647,13 @@ static hipError_t ensure_solver_ws(hp_plan_s* P, int restart, int nrhs) {
   if ((e = P->tvec.alloc((size_t)n * np * 16)) != hipSuccess) return e;
   if ((e = P->state.alloc((size_t)n * sizeof(hp::KState))) != hipSuccess) return e;
   if ((e = P->part.alloc((size_t)n * hp::kRedBlocks * hp::kPartSlots * 16)) != hipSuccess) return e;
-  if ((e = P->flags.alloc((size_t)n * 2 * sizeof(int))) != hipSuccess) return e;
+  if ((e = P->flags.alloc((size_t)n * 3 * sizeof(int))) != hipSuccess) return e;
   if (P->pinned) (void)hipHostFree(P->pinned);
   P->pinned = nullptr;
-  if ((e = hipHostMalloc(&P->pinned, (size_t)n * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipHostMalloc(&P->pinned, (size_t)n * 2 * sizeof(int))) != hipSuccess) return e;
+  for (hipEvent_t& ev : P->step_ev)
+    if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  std::memset(P->pinned, 0, (size_t)n * 2 * sizeof(int));
   P->ws_restart = r;
   P->ws_nrhs = n;
   return hipSuccess;
@@ -664,17 +672,17 @@ static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x,
   K.part = (cpx<double>*)P->part.p;
   K.skip_step = (int*)P->flags.p;
   K.done = (int*)P->flags.p + P->ws_nrhs;
+  int* hstop = (int*)P->pinned + P->ws_nrhs;
+  K.host_stop = hstop;
   K.nrhs = nrhs;
   K.restart = o.restart;
   const int mixed = P->prec == HP_MIXED;
   HP_TRY(hp::launch_fill_zero(P->flags.p, P->flags.bytes, st));
-  HP_TRY(hp::launch_dots(K, f, np, 0, nullptr, st));
-  HP_TRY(hp::launch_fnorm(K, o.rtol, st));
+  HP_TRY(hp::launch_fnorm(K, f, np, o.rtol, st));
   int* hdone = (int*)P->pinned;
   for (int cyc = 0;; ++cyc) {
     // true residual r = f - P_N x into v_0, its norm, convergence test
     HP_TRY(run_stencil(P, 3, x, np, K.V, vrs, f, nrhs, K.done, st));
-    HP_TRY(hp::launch_dots(K, K.V, vrs, 0, K.done, st));
     HP_TRY(hp::launch_cycle_start(K, o.rtol, st));
     HP_TRY(hipMemcpyAsync(hdone, K.done, (size_t)nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
     HP_TRY(hipStreamSynchronize(st));
@@ -682,17 +690,27 @@ static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x,
     for (int r = 0; r < nrhs; ++r) all = all && hdone[r];
     if (all || cyc >= o.max_cycles) break;
     HP_TRY(hp::launch_scale_v0(K, st));
+    // Throttle: before enqueuing step j, wait for step j - kLag and stop when
+    // every right-hand side has ended its cycle (the kernels publish that to
+    // pinned host memory), so that few no-op steps are enqueued.  Skipped for
+    // small problems, where a step is too short to hide the host round trip.
+    constexpr int kLag = 3;
+    const bool throttle = np * (size_t)nrhs >= ((size_t)1 << 18);
     for (int j = 0; j < o.restart; ++j) {
+      if (throttle && j >= kLag) {
+        HP_TRY(hipEventSynchronize(P->step_ev[(j - kLag) % (kLag + 1)]));
+        bool all_stopped = true;
+        for (int r = 0; r < nrhs; ++r) all_stopped = all_stopped && __atomic_load_n(&hstop[r], __ATOMIC_ACQUIRE);
+        if (all_stopped) break;
+      }
       cpx<double>* vj = K.V + (size_t)j * np;
       cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
       // z = Q v_j ; v_{j+1} = P_N z
       HP_TRY(run_apply(P, vj, 0, vrs, P->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st));
       HP_TRY(run_stencil(P, mixed ? 2 : 0, P->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st));
-      HP_TRY(hp::launch_dots(K, vj1, vrs, j + 1, K.skip_step, st));
-      HP_TRY(hp::launch_arnoldi_reduce(K, j, 1, st));
-      HP_TRY(hp::launch_arnoldi_update(K, j, 1, st));
-      HP_TRY(hp::launch_arnoldi_reduce(K, j, 2, st));
-      HP_TRY(hp::launch_arnoldi_update(K, j, 2, st));
+      HP_TRY(hp::launch_arnoldi_dots(K, j, st));
+      HP_TRY(hp::launch_arnoldi_update(K, j, st));
+      if (throttle) HP_TRY(hipEventRecord(P->step_ev[j % (kLag + 1)], st));
     }
     // x += Q (V_k y)
     HP_TRY(hp::launch_backsolve(K, st));

@@ -19,24 +19,37 @@ constexpr int kMaxNodes = 64;
 constexpr int kMaxRestart = 64;
 
 // Krylov state of one right-hand side, resident on the device.
+// Arnoldi with classical Gram-Schmidt and lagged reorthogonalisation: step j
+// applies the operator to the provisional vector u_j (projected once), and one
+// reduction gives both the second projection of u_j (which finalises v_j and
+// Hessenberg column j-1) and the projections of A u_j (which give column j).
 struct KState {
-  cpx<double> H[(kMaxRestart + 1) * kMaxRestart];  // column-major, ld = kMaxRestart + 1
+  cpx<double> H[(kMaxRestart + 1) * kMaxRestart];     // rotated (R of the QR), column-major, ld kMaxRestart+1
+  cpx<double> Hraw[(kMaxRestart + 1) * kMaxRestart];  // Hessenberg columns before rotation
   cpx<double> cs[kMaxRestart], sn[kMaxRestart];
   cpx<double> g[kMaxRestart + 1];
   cpx<double> y[kMaxRestart];
-  cpx<double> h[kMaxRestart + 1];   // projections of the current step
-  cpx<double> h2[kMaxRestart + 1];  // reorthogonalisation projections
-  double fnorm, target, beta, w2, w2_first, hnext, relres;
+  cpx<double> hprov[kMaxRestart + 1];  // provisional column of the last step
+  cpx<double> cv[kMaxRestart + 1];     // update coefficients on v_0..v_{j-1}
+  cpx<double> av[kMaxRestart + 1];     // second-projection coefficients a of u_j
+  cpx<double> cu;                      // update coefficient on u_j
+  double fnorm, target, beta, inv_sigma, relres;
   int k;        // columns finished in the current cycle
-  int reorth;   // the current step needs a second projection
+  int stop_at;  // step at which the current cycle ends (-1: not yet)
   int iters;    // Arnoldi steps in total
   int cycles;
   int pad_[4];
 };
 
-constexpr int kRedThreads = 256;   // threads per block of the reduction kernels
-constexpr int kRedBlocks = 1024;   // blocks per right-hand side (fixed: deterministic sums)
-constexpr int kPartSlots = kMaxRestart + 2;
+#ifndef HP_RED_THREADS
+#define HP_RED_THREADS 512
+#endif
+#ifndef HP_RED_BLOCKS
+#define HP_RED_BLOCKS 512
+#endif
+constexpr int kRedThreads = HP_RED_THREADS;  // threads per block of the reduction kernels
+constexpr int kRedBlocks = HP_RED_BLOCKS;    // blocks per right-hand side (fixed: deterministic sums)
+constexpr int kPartSlots = 2 * kMaxRestart + 4;
 
 // ---- launchers (all enqueue on `st`, return the launch status) ----
 
@@ -111,15 +124,19 @@ struct KrylovArgs {
   cpx<double>* part;
   int* skip_step;   // 1 when the current cycle's Arnoldi process has ended
   int* done;        // 1 when the right-hand side has converged
+  int* host_stop;   // pinned host copy of skip_step written by the kernels (may be null)
   int nrhs, restart;
 };
-hipError_t launch_dots(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int nvec, const int* skip,
-                       hipStream_t st);
-hipError_t launch_fnorm(const KrylovArgs& a, double rtol, hipStream_t st);
+// ||f|| of f [nrhs][npts] (stride frs) -> state.fnorm, target; done/skip_step for f = 0.
+hipError_t launch_fnorm(const KrylovArgs& a, const cpx<double>* f, size_t frs, double rtol, hipStream_t st);
+// ||v_0|| (v_0 holds the true residual) -> beta, convergence test, cycle reset.
 hipError_t launch_cycle_start(const KrylovArgs& a, double rtol, hipStream_t st);
 hipError_t launch_scale_v0(const KrylovArgs& a, hipStream_t st);
-hipError_t launch_arnoldi_reduce(const KrylovArgs& a, int j, int stage, hipStream_t st);
-hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, int stage, hipStream_t st);
+// Arnoldi step j (slot j holds u_j, slot j+1 holds w = A u_j): the one reduction
+// of the step (partial sums, then one block per right-hand side finishes it).
+hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st);
+// Arnoldi step j: slot j <- v_j, slot j+1 <- u_{j+1}.
+hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, hipStream_t st);
 hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);

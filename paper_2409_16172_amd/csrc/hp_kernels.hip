@@ -562,21 +562,141 @@ __device__ __forceinline__ void block_reduce_write(cpx<double> (&acc)[CNT], int 
     double re = 0.0, im = 0.0;
 #pragma unroll
     for (int w = 0; w < kRedThreads / 64; ++w) { re += red[w][2 * threadIdx.x]; im += red[w][2 * threadIdx.x + 1]; }
-    dst[threadIdx.x] = {re, im};
+    dst[(size_t)threadIdx.x * kRedBlocks] = {re, im};   // partials are stored [slot][block]
   }
   __syncthreads();
 }
 
-// part[rhs][blk][0..nvec-1] = V_v^H w (partial), part[..][nvec] = ||w||^2 (partial).
+__device__ __forceinline__ double cabs2(cpx<double> a) { return a.re * a.re + a.im * a.im; }
+
+// Sum the kRedBlocks block partials of `cnt` slots of right-hand side `rhs`
+// into sums[] in a fixed order (wave w handles slots w, w + 4, ...).
+__device__ void reduce_slots(const cpx<double>* __restrict__ part, int rhs, int cnt, cpx<double>* sums) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks;
+  for (int s = wv; s < cnt; s += nw) {
+    double re = 0.0, im = 0.0;
+    const cpx<double>* ps = pr + (size_t)s * kRedBlocks;
+#pragma unroll 4
+    for (int b = lane; b < kRedBlocks; b += 64) {
+      re += ps[b].re;
+      im += ps[b].im;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) sums[s] = {re, im};
+  }
+  __syncthreads();
+}
+
+// Givens state of one right-hand side staged in LDS by the finishing kernels.
+struct GivensLds {
+  cpx<double> cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1];
+  cpx<double> col[kMaxRestart + 2];
+};
+
+// Commit Hessenberg column j given its unrotated entries raw[0..j+1] (in LDS):
+// store it (raw and rotated) in the state, apply the previous Givens rotations,
+// form rotation j and rotate g.  Single thread.  Returns |g_{j+1}|.
+__device__ double commit_column(KState& S, GivensLds& L, int j, const cpx<double>* raw) {
+  cpx<double>* col = L.col;
+  for (int i = 0; i <= j + 1; ++i) col[i] = raw[i];
+  for (int i = 0; i < j; ++i) {
+    const cpx<double> a = col[i], b = col[i + 1];
+    const cpx<double> c = L.cs[i], s = L.sn[i];
+    // [conj(c) conj(s); -s c] applied to (a, b)
+    col[i] = {c.re * a.re + c.im * a.im + s.re * b.re + s.im * b.im,
+              c.re * a.im - c.im * a.re + s.re * b.im - s.im * b.re};
+    col[i + 1] = {-(s.re * a.re - s.im * a.im) + (c.re * b.re - c.im * b.im),
+                  -(s.re * a.im + s.im * a.re) + (c.re * b.im + c.im * b.re)};
+  }
+  const cpx<double> a = col[j];
+  const double hn = raw[j + 1].re;   // the subdiagonal entry is real and >= 0
+  const double aa = sqrt(cabs2(a));
+  const double den = sqrt(aa * aa + hn * hn);
+  cpx<double> c, s;
+  if (den == 0.0) { c = {1.0, 0.0}; s = {0.0, 0.0}; }
+  else if (aa == 0.0) { c = {0.0, 0.0}; s = {1.0, 0.0}; }
+  else { c = {a.re / den, a.im / den}; s = {hn / den, 0.0}; }
+  L.cs[j] = c;
+  L.sn[j] = s;
+  col[j] = {den, 0.0};
+  col[j + 1] = {0.0, 0.0};
+  const cpx<double> gj = L.g[j];
+  L.g[j] = {c.re * gj.re + c.im * gj.im, c.re * gj.im - c.im * gj.re};   // conj(c) g_j
+  L.g[j + 1] = {-s.re * gj.re, -s.re * gj.im};
+  cpx<double>* hr = S.Hraw + (size_t)j * (kMaxRestart + 1);
+  cpx<double>* hc = S.H + (size_t)j * (kMaxRestart + 1);
+  for (int i = 0; i <= j + 1; ++i) { hr[i] = raw[i]; hc[i] = col[i]; }
+  S.cs[j] = c;
+  S.sn[j] = s;
+  S.g[j] = L.g[j];
+  S.g[j + 1] = L.g[j + 1];
+  S.k = j + 1;
+  S.iters += 1;
+  return sqrt(cabs2(L.g[j + 1]));
+}
+
+__device__ __forceinline__ void publish_stop(int* host_stop, int rhs, int v) {
+  if (host_stop != nullptr) host_stop[rhs] = v;
+}
+
+// What the last block does with the sums.
+enum DotsMode { kDotsFnorm = 0, kDotsCycle = 1 };
+
+struct DotsCtl {
+  KState* state;
+  int* skip_step;
+  int* done;
+  int* host_stop;
+  int mode, j, restart;
+  double rtol;
+};
+
+__device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs, int nvec) {
+  __shared__ cpx<double> sums[kPartSlots];
+  reduce_slots(part, rhs, nvec + 1, sums);
+  if (threadIdx.x != 0) return;
+  KState& S = c.state[rhs];
+  if (c.mode == kDotsFnorm) {            // ||f|| once per solve; target = rtol ||f||
+    S.fnorm = sqrt(sums[0].re);
+    S.target = c.rtol * S.fnorm;
+    S.iters = 0;
+    S.cycles = 0;
+    S.relres = S.fnorm > 0.0 ? 1.0 : 0.0;
+    c.done[rhs] = S.fnorm > 0.0 ? 0 : 1;
+    c.skip_step[rhs] = c.done[rhs];
+    publish_stop(c.host_stop, rhs, c.skip_step[rhs]);
+  } else if (c.mode == kDotsCycle) {     // cycle start: beta = ||r||, true-residual test
+    const double beta = sqrt(sums[0].re);
+    S.beta = beta;
+    S.relres = S.fnorm > 0.0 ? beta / S.fnorm : 0.0;
+    S.stop_at = -1;
+    if (S.relres <= c.rtol || beta == 0.0) {
+      c.done[rhs] = 1;
+      c.skip_step[rhs] = 1;
+    } else {
+      S.cycles += 1;
+      S.k = 0;
+      for (int i = 0; i <= kMaxRestart; ++i) S.g[i] = {0.0, 0.0};
+      S.g[0] = {beta, 0.0};
+      c.skip_step[rhs] = 0;
+    }
+    publish_stop(c.host_stop, rhs, c.skip_step[rhs]);
+  }
+}
+
+// part[rhs][blk][0..nvec-1] = V_v^H w (partial), part[..][nvec] = ||w||^2 (partial);
+// the last block of each right-hand side reduces them (see DotsMode).
 __global__ __launch_bounds__(kRedThreads) void k_dots(const cpx<double>* __restrict__ V, size_t npts,
                                                        size_t vrs, const cpx<double>* __restrict__ w,
                                                        size_t wrs, int nvec, cpx<double>* __restrict__ part,
-                                                       const int* __restrict__ skip) {
+                                                       const int* __restrict__ skip, DotsCtl ctl) {
   const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
   const cpx<double>* Vr = V + (size_t)rhs * vrs;
   const cpx<double>* wr = w + (size_t)rhs * wrs;
-  cpx<double>* pr = part + ((size_t)rhs * kRedBlocks + blockIdx.x) * kPartSlots;
+  cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x;
   const size_t stride = (size_t)kRedBlocks * kRedThreads;
   {
     cpx<double> nrm[1] = {{0.0, 0.0}};
@@ -584,7 +704,7 @@ __global__ __launch_bounds__(kRedThreads) void k_dots(const cpx<double>* __restr
       const cpx<double> a = wr[i];
       nrm[0].re += a.re * a.re + a.im * a.im;
     }
-    block_reduce_write<1>(nrm, 1, pr + nvec);
+    block_reduce_write<1>(nrm, 1, pr + (size_t)nvec * kRedBlocks);
   }
   for (int c0 = 0; c0 < nvec; c0 += kChunk) {
     const int cnt = nvec - c0 < kChunk ? nvec - c0 : kChunk;
@@ -602,74 +722,14 @@ __global__ __launch_bounds__(kRedThreads) void k_dots(const cpx<double>* __restr
         }
       }
     }
-    block_reduce_write<kChunk>(acc, cnt, pr + c0);
+    block_reduce_write<kChunk>(acc, cnt, pr + (size_t)c0 * kRedBlocks);
   }
 }
 
-// Sum the block partials of `cnt` slots of right-hand side `rhs` into sums[]
-// (one 1024-thread block; wave w handles slots w, w+16, ...).
-__device__ void reduce_slots(const cpx<double>* __restrict__ part, int rhs, int cnt, cpx<double>* sums) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const cpx<double>* pr = part + (size_t)rhs * kRedBlocks * kPartSlots;
-  for (int s = wv; s < cnt; s += nw) {
-    double re = 0.0, im = 0.0;
-    for (int b = lane; b < kRedBlocks; b += 64) {
-      re += pr[(size_t)b * kPartSlots + s].re;
-      im += pr[(size_t)b * kPartSlots + s].im;
-    }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) sums[s] = {re, im};
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double cabs2(cpx<double> a) { return a.re * a.re + a.im * a.im; }
-
-// ||f|| once per solve; target = rtol ||f||.
-__global__ __launch_bounds__(1024) void k_fnorm(const cpx<double>* part, KState* state, int* done,
-                                                double rtol) {
-  __shared__ cpx<double> sums[1];
+__global__ __launch_bounds__(1024) void k_dots_fin(const cpx<double>* __restrict__ part, DotsCtl ctl) {
   const int rhs = blockIdx.x;
-  reduce_slots(part, rhs, 1, sums);
-  if (threadIdx.x == 0) {
-    KState& S = state[rhs];
-    S.fnorm = sqrt(sums[0].re);
-    S.target = rtol * S.fnorm;
-    S.iters = 0;
-    S.cycles = 0;
-    S.relres = S.fnorm > 0.0 ? 1.0 : 0.0;
-    done[rhs] = S.fnorm > 0.0 ? 0 : 1;
-  }
-}
-
-// Cycle start: beta = ||r||, convergence test on the true residual.
-__global__ __launch_bounds__(1024) void k_cycle_start(const cpx<double>* part, KState* state, int* done,
-                                                      int* skip_step, double rtol) {
-  __shared__ cpx<double> sums[1];
-  const int rhs = blockIdx.x;
-  if (done[rhs]) {
-    if (threadIdx.x == 0) skip_step[rhs] = 1;
-    return;
-  }
-  reduce_slots(part, rhs, 1, sums);
-  if (threadIdx.x == 0) {
-    KState& S = state[rhs];
-    const double beta = sqrt(sums[0].re);
-    S.beta = beta;
-    S.relres = S.fnorm > 0.0 ? beta / S.fnorm : 0.0;
-    if (S.relres <= rtol || beta == 0.0) {
-      done[rhs] = 1;
-      skip_step[rhs] = 1;
-    } else {
-      S.cycles += 1;
-      S.k = 0;
-      S.reorth = 0;
-      for (int i = 0; i <= kMaxRestart; ++i) S.g[i] = {0.0, 0.0};
-      S.g[0] = {beta, 0.0};
-      skip_step[rhs] = 0;
-    }
-  }
+  if (ctl.mode == kDotsCycle && ctl.done[rhs]) return;
+  dots_finalize(ctl, part, rhs, 0);
 }
 
 __global__ __launch_bounds__(256) void k_scale_v0(cpx<double>* V, size_t npts, size_t vrs, const KState* state,
@@ -682,179 +742,232 @@ __global__ __launch_bounds__(256) void k_scale_v0(cpx<double>* V, size_t npts, s
     v[i] = cscale(v[i], s);
 }
 
-// Finish Hessenberg column j: apply the previous Givens rotations, form the new
-// one, rotate the right-hand side g and decide whether the cycle ends here.
-__device__ void finish_column(KState& S, int j, int restart, int* skip_step, int rhs) {
-  cpx<double>* col = S.H + (size_t)j * (kMaxRestart + 1);
-  for (int i = 0; i <= j; ++i) col[i] = S.h[i];
-  const double hn = S.hnext;
-  for (int i = 0; i < j; ++i) {
-    const cpx<double> a = col[i], b = col[i + 1];
-    const cpx<double> c = S.cs[i], s = S.sn[i];
-    // [conj(c) conj(s); -s c] applied to (a, b)
-    col[i] = {c.re * a.re + c.im * a.im + s.re * b.re + s.im * b.im,
-              c.re * a.im - c.im * a.re + s.re * b.im - s.im * b.re};
-    col[i + 1] = {-(s.re * a.re - s.im * a.im) + (c.re * b.re - c.im * b.im),
-                  -(s.re * a.im + s.im * a.re) + (c.re * b.im + c.im * b.re)};
-  }
-  const cpx<double> a = col[j];
-  const double aa = sqrt(cabs2(a));
-  const double den = sqrt(aa * aa + hn * hn);
-  cpx<double> c, s;
-  if (den == 0.0) { c = {1.0, 0.0}; s = {0.0, 0.0}; }
-  else if (aa == 0.0) { c = {0.0, 0.0}; s = {1.0, 0.0}; }
-  else { c = {a.re / den, a.im / den}; s = {hn / den, 0.0}; }
-  S.cs[j] = c;
-  S.sn[j] = s;
-  col[j] = {den, 0.0};
-  col[j + 1] = {0.0, 0.0};
-  const cpx<double> gj = S.g[j];
-  S.g[j] = {c.re * gj.re + c.im * gj.im, c.re * gj.im - c.im * gj.re};   // conj(c) g_j
-  S.g[j + 1] = {-s.re * gj.re, -s.re * gj.im};
-  S.k = j + 1;
-  S.iters += 1;
-  const double est = sqrt(cabs2(S.g[j + 1]));
-  const bool breakdown = hn <= 1e-14 * sqrt(S.w2_first);
-  if (est <= S.target || breakdown || j + 1 >= restart) skip_step[rhs] = 1;
-}
+// Arnoldi step j, one reduction over v_0..v_{j-1} (slots 0..j-1), u_j (slot j)
+// and w = A u_j (slot j+1).  Partial-sum slots: [0, j) a = V^H u_j,
+// [j, 2j) b = V^H w, 2j ||u_j||^2, 2j+1 u_j^H w, 2j+2 ||w||^2.
+constexpr int kDualChunk = 8;
 
-// stage 1: projections h = V^H w and ||w||^2; a second projection is needed when
-// more than half of ||w||^2 was removed (Kahan-Parlett / DGKS criterion).
-// stage 2: the second projections are added to h.
-__global__ __launch_bounds__(1024) void k_arnoldi_reduce(const cpx<double>* part, KState* state,
-                                                         int* skip_step, int j, int stage, int restart) {
-  __shared__ cpx<double> sums[kMaxRestart + 2];
-  const int rhs = blockIdx.x;
-  if (skip_step[rhs]) return;
-  KState& S = state[rhs];
-  if (stage == 2 && !S.reorth) return;
-  reduce_slots(part, rhs, j + 2, sums);
+__device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, int j, int restart,
+                                 int* skip_step, int* host_stop) {
+  __shared__ cpx<double> sums[kPartSlots];
+  __shared__ cpx<double> zz[kMaxRestart + 1], hp[kMaxRestart + 1], raw[kMaxRestart + 2];
+  __shared__ GivensLds L;
+  __shared__ double sh_sigma;
+  __shared__ int sh_break;
+  for (int i = threadIdx.x; i < kMaxRestart; i += blockDim.x) { L.cs[i] = S.cs[i]; L.sn[i] = S.sn[i]; }
+  for (int i = threadIdx.x; i <= kMaxRestart; i += blockDim.x) { L.g[i] = S.g[i]; hp[i] = S.hprov[i]; }
+  reduce_slots(part, rhs, 2 * j + 3, sums);   // ends with a barrier
+  const cpx<double>* a = sums;
+  const cpx<double>* bv = sums + j;
+  if (threadIdx.x == 0) {
+    // v_j = (u_j - V a) / sigma; column j-1 = (hprov_{j-1} + a, sigma)
+    double aa = 0.0;
+    for (int k = 0; k < j; ++k) aa += cabs2(a[k]);
+    const double s2 = sums[2 * j].re - aa;
+    const double sigma = s2 > 0.0 ? sqrt(s2) : 0.0;
+    sh_sigma = sigma;
+    sh_break = !(sigma > 0.0);
+    if (j >= 1) {
+      for (int k = 0; k < j; ++k) raw[k] = cadd(hp[k], a[k]);
+      raw[j] = {sigma, 0.0};
+      const double est = commit_column(S, L, j - 1, raw);
+      if (sh_break || est <= S.target) {   // the cycle ended with column j-1
+        S.stop_at = j - 1;
+        skip_step[rhs] = 1;
+        publish_stop(host_stop, rhs, 1);
+        sh_break = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (sh_break) return;
+  // z = Hraw[0..j][0..j-1] a, the expansion of A V a in v_0..v_j
+  for (int k = threadIdx.x; k <= j; k += blockDim.x) {
+    cpx<double> acc = {0.0, 0.0};
+    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) acc = cadd(acc, cmul(S.Hraw[(size_t)i * (kMaxRestart + 1) + k], a[i]));
+    zz[k] = acc;
+  }
+  __syncthreads();
+  const double sigma = sh_sigma, isg = 1.0 / sigma;
+  if (threadIdx.x == 0) {
+    // p_j = v_j^H w
+    cpx<double> ab = {0.0, 0.0};
+    for (int k = 0; k < j; ++k) ab = cadd(ab, {a[k].re * bv[k].re + a[k].im * bv[k].im, a[k].re * bv[k].im - a[k].im * bv[k].re});
+    raw[j] = cscale(csub(sums[2 * j + 1], ab), isg);
+  }
+  __syncthreads();
+  // hprov_j = [V, v_j]^H A v_j = (p - z) / sigma (parallel over k)
+  for (int k = threadIdx.x; k <= j; k += blockDim.x) {
+    const cpx<double> pk = k < j ? bv[k] : raw[j];
+    hp[k] = cscale(csub(pk, zz[k]), isg);
+  }
+  __syncthreads();
+  // update coefficients: u_{j+1} = w/sigma - V cv - cu u_j, y = z/sigma + hprov_j
+  const cpx<double> cu = cscale(cadd(cscale(zz[j], isg), hp[j]), isg);
+  for (int k = threadIdx.x; k <= j; k += blockDim.x) {
+    S.hprov[k] = hp[k];
+    if (k < j) {
+      const cpx<double> yk = cadd(cscale(zz[k], isg), hp[k]);
+      S.cv[k] = csub(yk, cmul(cu, a[k]));
+      S.av[k] = a[k];
+    }
+  }
   if (threadIdx.x != 0) return;
-  double hh = 0.0;
-  const double w2 = sums[j + 1].re;
-  if (stage == 1) {
-    for (int i = 0; i <= j; ++i) { S.h[i] = sums[i]; hh += cabs2(sums[i]); }
-    S.w2_first = w2;
-    const double p2 = w2 - hh;
-    if (p2 > 0.5 * w2) {
-      S.reorth = 0;
-      S.hnext = sqrt(p2);
-      finish_column(S, j, restart, skip_step, rhs);
-    } else {
-      S.reorth = 1;
-    }
-  } else {
-    for (int i = 0; i <= j; ++i) {
-      S.h2[i] = sums[i];
-      S.h[i] = cadd(S.h[i], sums[i]);
-      hh += cabs2(sums[i]);
-    }
-    const double p2 = w2 - hh;
-    S.hnext = p2 > 0.0 ? sqrt(p2) : 0.0;
-    finish_column(S, j, restart, skip_step, rhs);
+  S.cu = cu;
+  S.inv_sigma = isg;
+  double zp = 0.0, z2 = 0.0, h2 = 0.0;
+  for (int k = 0; k <= j; ++k) {
+    const cpx<double> pk = k < j ? bv[k] : raw[j];
+    zp += zz[k].re * pk.re + zz[k].im * pk.im;
+    z2 += cabs2(zz[k]);
+    h2 += cabs2(hp[k]);
+  }
+  const double av2 = (sums[2 * j + 2].re - 2.0 * zp + z2) * isg * isg;   // ||A v_j||^2
+  const double r2 = av2 - h2;
+  const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+  // residual estimate with the provisional column j
+  cpx<double> t0 = hp[0];
+  for (int i = 0; i < j; ++i) {
+    const cpx<double> x1 = hp[i + 1], c = L.cs[i], s = L.sn[i];
+    t0 = {-(s.re * t0.re - s.im * t0.im) + (c.re * x1.re - c.im * x1.im),
+          -(s.re * t0.im + s.im * t0.re) + (c.re * x1.im + c.im * x1.re)};
+  }
+  const double tt = sqrt(cabs2(t0));
+  const double den = sqrt(tt * tt + rho * rho);
+  const double est = den > 0.0 ? rho / den * sqrt(cabs2(L.g[j])) : 0.0;
+  const bool breakdown = rho <= 1e-14 * sqrt(av2 > 0.0 ? av2 : 0.0);
+  if (est <= S.target || breakdown || j + 1 >= restart) {
+    // end the cycle with the provisional column j (its second projection would
+    // change it by the loss of orthogonality only)
+    for (int k = 0; k <= j; ++k) raw[k] = hp[k];
+    raw[j + 1] = {rho, 0.0};
+    commit_column(S, L, j, raw);
+    S.stop_at = j;
+    skip_step[rhs] = 1;
+    publish_stop(host_stop, rhs, 1);
   }
 }
 
-// stage 1 without reorthogonalisation: v_{j+1} = (w - V h) / h_{j+1,j}.
-// stage 1 with: w <- w - V h (kept in place) and partial sums of V^H w, ||w||^2.
-// stage 2: v_{j+1} = (w - V h2) / h_{j+1,j}.
-__global__ __launch_bounds__(kRedThreads) void k_arnoldi_update(cpx<double>* __restrict__ V, size_t npts,
-                                                                size_t vrs, const KState* __restrict__ state,
-                                                                cpx<double>* __restrict__ part,
-                                                                const int* __restrict__ skip_step, int j,
-                                                                int stage) {
-  __shared__ cpx<double> coef[kMaxRestart + 1];
+__global__ __launch_bounds__(kRedThreads) void k_arnoldi_dots(const cpx<double>* __restrict__ V, size_t npts,
+                                                               size_t vrs, cpx<double>* __restrict__ part,
+                                                               const int* __restrict__ skip_step, int j) {
   const int rhs = blockIdx.y;
   if (skip_step[rhs]) return;
-  const KState& S = state[rhs];
-  const int reorth = S.reorth;
-  if (stage == 2 && !reorth) return;
-  const bool final_pass = (stage == 2) || !reorth;
-  for (int i = threadIdx.x; i <= kMaxRestart; i += blockDim.x)
-    coef[i] = i > j ? cpx<double>{0.0, 0.0} : (stage == 1 ? S.h[i] : S.h2[i]);
-  __syncthreads();
-  const double inv = final_pass ? 1.0 / S.hnext : 1.0;
-  cpx<double>* Vr = V + (size_t)rhs * vrs;
-  cpx<double>* w = Vr + (size_t)(j + 1) * npts;
+  const cpx<double>* Vr = V + (size_t)rhs * vrs;
+  const cpx<double>* U = Vr + (size_t)j * npts;
+  const cpx<double>* W = Vr + (size_t)(j + 1) * npts;
+  cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x;
   const size_t stride = (size_t)kRedBlocks * kRedThreads;
-  if (final_pass) {
-    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
-      cpx<double> a = w[i];
-      // groups of 8 basis vectors: their loads are independent and issued together
-      for (int v0 = 0; v0 <= j; v0 += 8) {
-        cpx<double> b[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = (v0 + u <= j) ? Vr[(size_t)(v0 + u) * npts + i] : cpx<double>{0.0, 0.0};
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const cpx<double> c = coef[v0 + u < kMaxRestart + 1 ? v0 + u : kMaxRestart];
-          a.re -= c.re * b[u].re - c.im * b[u].im;
-          a.im -= c.re * b[u].im + c.im * b[u].re;
-        }
-      }
-      w[i] = cscale(a, inv);
-    }
-    return;
-  }
-  // reorthogonalisation path: update in place, then project again
-  cpx<double>* pr = part + ((size_t)rhs * kRedBlocks + blockIdx.x) * kPartSlots;
   {
-    cpx<double> nrm[1] = {{0.0, 0.0}};
+    cpx<double> sc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
-      cpx<double> a = w[i];
-      for (int v0 = 0; v0 <= j; v0 += 8) {
-        cpx<double> b[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = (v0 + u <= j) ? Vr[(size_t)(v0 + u) * npts + i] : cpx<double>{0.0, 0.0};
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const cpx<double> c = coef[v0 + u < kMaxRestart + 1 ? v0 + u : kMaxRestart];
-          a.re -= c.re * b[u].re - c.im * b[u].im;
-          a.im -= c.re * b[u].im + c.im * b[u].re;
-        }
-      }
-      w[i] = a;
-      nrm[0].re += a.re * a.re + a.im * a.im;
+      const cpx<double> u = U[i], w = W[i];
+      sc[0].re += u.re * u.re + u.im * u.im;
+      sc[1].re += u.re * w.re + u.im * w.im;     // conj(u) w
+      sc[1].im += u.re * w.im - u.im * w.re;
+      sc[2].re += w.re * w.re + w.im * w.im;
     }
-    block_reduce_write<1>(nrm, 1, pr + j + 1);
+    block_reduce_write<3>(sc, 3, pr + (size_t)(2 * j) * kRedBlocks);
   }
-  const int nvec = j + 1;
-  for (int c0 = 0; c0 < nvec; c0 += kChunk) {
-    const int cnt = nvec - c0 < kChunk ? nvec - c0 : kChunk;
-    cpx<double> acc[kChunk];
+  for (int c0 = 0; c0 < j; c0 += kDualChunk) {
+    const int cnt = j - c0 < kDualChunk ? j - c0 : kDualChunk;
+    cpx<double> acc[2 * kDualChunk];
 #pragma unroll
-    for (int v = 0; v < kChunk; ++v) acc[v] = {0.0, 0.0};
+    for (int v = 0; v < 2 * kDualChunk; ++v) acc[v] = {0.0, 0.0};
     for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
-      const cpx<double> a = w[i];
+      const cpx<double> u = U[i], w = W[i];
 #pragma unroll
-      for (int v = 0; v < kChunk; ++v) {
+      for (int v = 0; v < kDualChunk; ++v) {
         if (v < cnt) {
-          const cpx<double> b = Vr[(size_t)(c0 + v) * npts + i];
-          acc[v].re += b.re * a.re + b.im * a.im;
-          acc[v].im += b.re * a.im - b.im * a.re;
+          const cpx<double> x = Vr[(size_t)(c0 + v) * npts + i];
+          acc[v].re += x.re * u.re + x.im * u.im;                  // conj(v) u
+          acc[v].im += x.re * u.im - x.im * u.re;
+          acc[kDualChunk + v].re += x.re * w.re + x.im * w.im;     // conj(v) w
+          acc[kDualChunk + v].im += x.re * w.im - x.im * w.re;
         }
       }
     }
-    block_reduce_write<kChunk>(acc, cnt, pr + c0);
+    // slots: a at c0.., b at j + c0..
+    cpx<double> aa[kDualChunk], bb[kDualChunk];
+#pragma unroll
+    for (int v = 0; v < kDualChunk; ++v) { aa[v] = acc[v]; bb[v] = acc[kDualChunk + v]; }
+    block_reduce_write<kDualChunk>(aa, cnt, pr + (size_t)c0 * kRedBlocks);
+    block_reduce_write<kDualChunk>(bb, cnt, pr + (size_t)(j + c0) * kRedBlocks);
   }
 }
 
-// y = R^{-1} g over the k finished columns (upper triangular back substitution).
-__global__ void k_backsolve(KState* state, const int* done) {
+__global__ __launch_bounds__(1024) void k_arnoldi_fin(const cpx<double>* __restrict__ part, int* __restrict__ skip_step,
+                                                      KState* state, int j, int restart, int* __restrict__ host_stop) {
   const int rhs = blockIdx.x;
-  if (done[rhs] || threadIdx.x != 0) return;
+  if (skip_step[rhs]) return;
+  arnoldi_finalize(state[rhs], part, rhs, j, restart, skip_step, host_stop);
+}
+
+// slot j <- v_j = (u_j - V a) / sigma ; slot j+1 <- u_{j+1} = w / sigma - V cv - cu u_j.
+// Runs for right-hand sides still in the cycle, and for the step that ended it.
+__global__ __launch_bounds__(256) void k_arnoldi_update(cpx<double>* __restrict__ V, size_t npts, size_t vrs,
+                                                        const KState* __restrict__ state,
+                                                        const int* __restrict__ skip_step, int j) {
+  __shared__ cpx<double> ca[kMaxRestart + 8], cc[kMaxRestart + 8];
+  const int rhs = blockIdx.y;
+  const KState& S = state[rhs];
+  if (skip_step[rhs] && S.stop_at != j) return;
+  for (int i = threadIdx.x; i < kMaxRestart + 8; i += blockDim.x) {
+    ca[i] = i < j ? S.av[i] : cpx<double>{0.0, 0.0};
+    cc[i] = i < j ? S.cv[i] : cpx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  const double isg = S.inv_sigma;
+  const cpx<double> cu = S.cu;
+  cpx<double>* Vr = V + (size_t)rhs * vrs;
+  cpx<double>* U = Vr + (size_t)j * npts;
+  cpx<double>* W = Vr + (size_t)(j + 1) * npts;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < npts; i += (size_t)gridDim.x * 256) {
+    const cpx<double> u = U[i], w = W[i];
+    cpx<double> sa = {0.0, 0.0}, sc = {0.0, 0.0};
+    for (int v0 = 0; v0 < j; v0 += 8) {
+      cpx<double> x[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) x[t] = (v0 + t < j) ? Vr[(size_t)(v0 + t) * npts + i] : cpx<double>{0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const cpx<double> p = ca[v0 + t], q = cc[v0 + t];
+        sa.re += p.re * x[t].re - p.im * x[t].im;
+        sa.im += p.re * x[t].im + p.im * x[t].re;
+        sc.re += q.re * x[t].re - q.im * x[t].im;
+        sc.im += q.re * x[t].im + q.im * x[t].re;
+      }
+    }
+    U[i] = cscale(csub(u, sa), isg);
+    const cpx<double> cuu = cmul(cu, u);
+    W[i] = {w.re * isg - sc.re - cuu.re, w.im * isg - sc.im - cuu.im};
+  }
+}
+
+// y = R^{-1} g over the k finished columns (upper triangular back substitution),
+// with R and g staged in LDS.
+__global__ __launch_bounds__(256) void k_backsolve(KState* state, const int* done) {
+  __shared__ cpx<double> R[kMaxRestart * kMaxRestart];
+  __shared__ cpx<double> y[kMaxRestart];
+  const int rhs = blockIdx.x;
+  if (done[rhs]) return;
   KState& S = state[rhs];
   const int k = S.k;
-  for (int i = k - 1; i >= 0; --i) {
-    cpx<double> s = S.g[i];
-    for (int l = i + 1; l < k; ++l) {
-      const cpx<double> r = S.H[(size_t)l * (kMaxRestart + 1) + i];
-      s = csub(s, cmul(r, S.y[l]));
-    }
-    const cpx<double> d = S.H[(size_t)i * (kMaxRestart + 1) + i];
-    const double dd = cabs2(d);
-    S.y[i] = {(s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd};
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+    const int col = t / k, row = t % k;
+    R[row * kMaxRestart + col] = row <= col ? S.H[(size_t)col * (kMaxRestart + 1) + row] : cpx<double>{0.0, 0.0};
   }
+  for (int t = threadIdx.x; t < k; t += blockDim.x) y[t] = S.g[t];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    cpx<double> s = y[i];
+    for (int l = i + 1; l < k; ++l) s = csub(s, cmul(R[i * kMaxRestart + l], y[l]));
+    const cpx<double> d = R[i * kMaxRestart + i];
+    const double dd = cabs2(d);
+    y[i] = {(s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd};
+  }
+  for (int i = 0; i < k; ++i) S.y[i] = y[i];
 }
 
 // out = sum_{i<k} y_i v_i
@@ -897,21 +1010,32 @@ static unsigned stream_blocks(size_t npts) {
   return (unsigned)(b < 2048 ? (b == 0 ? 1 : b) : 2048);
 }
 
-hipError_t launch_dots(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int nvec, const int* skip,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs, w, wrs,
-                     nvec, a.part, skip);
-  return hipGetLastError();
+static DotsCtl dots_ctl(const KrylovArgs& a, int mode, int j, double rtol) {
+  DotsCtl c;
+  c.state = a.state;
+  c.skip_step = a.skip_step;
+  c.done = a.done;
+  c.host_stop = a.host_stop;
+  c.mode = mode;
+  c.j = j;
+  c.restart = a.restart;
+  c.rtol = rtol;
+  return c;
 }
 
-hipError_t launch_fnorm(const KrylovArgs& a, double rtol, hipStream_t st) {
-  hipLaunchKernelGGL(k_fnorm, dim3(a.nrhs), dim3(1024), 0, st, a.part, a.state, a.done, rtol);
+hipError_t launch_fnorm(const KrylovArgs& a, const cpx<double>* f, size_t frs, double rtol, hipStream_t st) {
+  const DotsCtl c = dots_ctl(a, kDotsFnorm, 0, rtol);
+  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs, f, frs, 0,
+                     a.part, (const int*)nullptr, c);
+  hipLaunchKernelGGL(k_dots_fin, dim3(a.nrhs), dim3(1024), 0, st, (const cpx<double>*)a.part, c);
   return hipGetLastError();
 }
 
 hipError_t launch_cycle_start(const KrylovArgs& a, double rtol, hipStream_t st) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(a.nrhs), dim3(1024), 0, st, a.part, a.state, a.done, a.skip_step,
-                     rtol);
+  const DotsCtl c = dots_ctl(a, kDotsCycle, 0, rtol);
+  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs, a.V, a.vrs, 0,
+                     a.part, (const int*)a.done, c);
+  hipLaunchKernelGGL(k_dots_fin, dim3(a.nrhs), dim3(1024), 0, st, (const cpx<double>*)a.part, c);
   return hipGetLastError();
 }
 
@@ -921,20 +1045,22 @@ hipError_t launch_scale_v0(const KrylovArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_reduce(const KrylovArgs& a, int j, int stage, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_reduce, dim3(a.nrhs), dim3(1024), 0, st, a.part, a.state, a.skip_step, j, stage,
-                     a.restart);
+hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs,
+                     a.part, (const int*)a.skip_step, j);
+  hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(1024), 0, st, (const cpx<double>*)a.part, a.skip_step,
+                     a.state, j, a.restart, a.host_stop);
   return hipGetLastError();
 }
 
-hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, int stage, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_update, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs,
-                     a.state, a.part, a.skip_step, j, stage);
+hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_update, dim3(stream_blocks(a.npts), a.nrhs), dim3(256), 0, st, a.V, a.npts, a.vrs,
+                     a.state, a.skip_step, j);
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_backsolve, dim3(a.nrhs), dim3(64), 0, st, a.state, a.done);
+  hipLaunchKernelGGL(k_backsolve, dim3(a.nrhs), dim3(256), 0, st, a.state, a.done);
   return hipGetLastError();
 }
 
