@@ -162,6 +162,28 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts,
                    hp_solve_info* info, void* stream);
 
+/* Resumable solves, for callers that interleave several solves (a serving
+ * loop).  A solver owns the Krylov workspace of nrhs right-hand sides
+ * (hp_solve_workspace_bytes) and runs the same right-preconditioned restarted
+ * GMRES as hp_solve on one stream, with its state kept on the device.
+ *   hp_solver_create   allocate the workspace (nrhs <= the plan's max_nrhs)
+ *   hp_solver_start    enqueue the start of a solve of f (x: initial guess,
+ *                      overwritten by the solution); f, x stay owned by the
+ *                      caller and must remain valid until the solve finishes
+ *   hp_solver_advance  enqueue at most max_steps further Arnoldi steps without
+ *                      waiting for the device; *finished = 1 once the solve
+ *                      has ended (converged or max_cycles)
+ *   hp_solver_wait     block until the solve ends; fills info[nrhs]; returns
+ *                      HP_E_NOT_CONVERGED if a right-hand side stopped above rtol
+ * A plan's preconditioner workspace is shared by everything that runs on it:
+ * solvers of one plan must not progress concurrently on different streams. */
+typedef struct hp_solver_s* hp_solver;
+hp_status hp_solver_create(hp_solver* out, hp_plan p, int nrhs, const hp_solve_opts* opts);
+hp_status hp_solver_start(hp_solver s, const void* f, void* x, void* stream);
+hp_status hp_solver_advance(hp_solver s, int max_steps, int* finished);
+hp_status hp_solver_wait(hp_solver s, hp_solve_info* info);
+hp_status hp_solver_destroy(hp_solver s);
+
 /* Diagnostic timing of the preconditioner passes (for benchmarks): runs `reps`
  * applies of v -> u (as hp_apply_precond, nrhs <= max_nrhs) and records HIP
  * events on `stream` around every pass.  Blocks until done.  ms[5] receives the

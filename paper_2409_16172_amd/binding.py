@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": HP_FP64, "mixed": HP_MIXED}
 
 EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_bytes", "hp_plan_query",
             "hp_apply_precond", "hp_matvec", "hp_solve", "hp_profile_apply", "hp_plan_destroy",
-            "hp_status_str", "hp_last_error"]
+            "hp_status_str", "hp_last_error", "hp_solver_create", "hp_solver_start", "hp_solver_advance",
+            "hp_solver_wait", "hp_solver_destroy"]
 
 
 class HpGrid(C.Structure):
@@ -91,6 +92,16 @@ def load_library(path: str = LIB_PATH):
     lib.hp_solve.restype = i
     lib.hp_profile_apply.argtypes = [vp, vp, vp, i, i, C.POINTER(d), C.POINTER(d), vp]
     lib.hp_profile_apply.restype = i
+    lib.hp_solver_create.argtypes = [C.POINTER(vp), vp, i, C.POINTER(HpSolveOpts)]
+    lib.hp_solver_create.restype = i
+    lib.hp_solver_start.argtypes = [vp, vp, vp, vp]
+    lib.hp_solver_start.restype = i
+    lib.hp_solver_advance.argtypes = [vp, i, C.POINTER(i)]
+    lib.hp_solver_advance.restype = i
+    lib.hp_solver_wait.argtypes = [vp, C.POINTER(HpSolveInfo)]
+    lib.hp_solver_wait.restype = i
+    lib.hp_solver_destroy.argtypes = [vp]
+    lib.hp_solver_destroy.restype = i
     lib.hp_plan_destroy.argtypes = [vp]
     lib.hp_plan_destroy.restype = i
     lib.hp_status_str.argtypes = [i]
@@ -274,6 +285,73 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Solver:
+    """Resumable restarted-GMRES solve on one stream (hp_solver_*): start(), then
+    advance() without blocking until finished, then result().  The Krylov state
+    stays on the GPU."""
+
+    def __init__(self, plan, nrhs=1, *, restart=30, max_cycles=200, rtol=1e-8):
+        self.plan = plan
+        self.nrhs = int(nrhs)
+        self._opts = HpSolveOpts(int(restart), int(max_cycles), float(rtol))
+        h = C.c_void_p()
+        _check(load_library().hp_solver_create(C.byref(h), plan._h, self.nrhs, C.byref(self._opts)),
+               "hp_solver_create")
+        self._h = h
+        self._keep = None
+
+    def start(self, f, x=None, stream=None):
+        import torch
+        nr = self.plan._fields(f, torch.complex128, "f")
+        if nr != self.nrhs:
+            raise ValueError(f"f holds {nr} right-hand sides, solver was made for {self.nrhs}")
+        if x is None:
+            x = torch.zeros_like(f)
+        self.plan._fields(x, torch.complex128, "x")
+        self._keep = (f, x, stream)
+        _check(load_library().hp_solver_start(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()),
+                                              _stream(stream)), "hp_solver_start")
+        return x
+
+    def advance(self, max_steps=4):
+        done = C.c_int(0)
+        _check(load_library().hp_solver_advance(self._h, int(max_steps), C.byref(done)), "hp_solver_advance")
+        return bool(done.value)
+
+    def result(self):
+        infos = (HpSolveInfo * self.nrhs)()
+        code = load_library().hp_solver_wait(self._h, infos)
+        if code not in (HP_OK, HP_E_NOT_CONVERGED):
+            raise HelmpreError(code, "hp_solver_wait")
+        return self._keep[1], [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status) for i in infos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().hp_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(shape, precision, K, nrhs=1, restart=30):
+    """Device bytes a plan plus one solver of nrhs right-hand sides hold (admission by footprint)."""
+    lib = load_library()
+    g = HpGrid()
+    g.dim = len(shape)
+    for k, n in enumerate(shape):
+        g.n[k] = int(n)
+        g.len[k] = 1.0
+    o = HpPlanOpts()
+    o.precision = PRECISIONS[precision]
+    o.max_nrhs = int(nrhs)
+    return int(lib.hp_plan_workspace_bytes(C.byref(g), C.byref(o), int(K))) + \
+        int(lib.hp_solve_workspace_bytes(C.byref(g), int(restart), int(nrhs)))
 
 
 def plan_from_workload(w, **over):

@@ -59,27 +59,19 @@ struct hp_plan_s {
   double rows_used = 0;    // sum over pass-C rows of the nodes the row uses
   double slabs_used = 0;   // sum over nodes of the axis-0 indices that use the node
   DevBuf t, fields;                  // apply workspace
-  // solver workspace
-  DevBuf V, z, tvec, state, part, flags;
-  int ws_restart = 0, ws_nrhs = 0;
-  void* pinned = nullptr;
-  hipEvent_t step_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // solver workspace of hp_solve (sessions created with hp_solver_create own theirs)
+  struct SolverWs* solver_ws_ptr = nullptr;
 
   int real_kind() const { return prec == HP_FP64 ? 0 : 1; }
   size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
   const void* tw(int axis) const { return prec == HP_FP64 ? tw64[axis].p : tw32[axis].p; }
   void release_all() {
-    for (DevBuf* b : {&nodes, &pos, &grpmask, &rowmask, &slabneed, &storemask, &coef64, &coef32, &lam_ax, &lam_in, &t, &fields, &V, &z, &tvec,
-                      &state, &part, &flags})
+    for (DevBuf* b : {&nodes, &pos, &grpmask, &rowmask, &slabneed, &storemask, &coef64, &coef32, &lam_ax, &lam_in, &t, &fields})
       b->release();
     for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
-    if (pinned) (void)hipHostFree(pinned);
-    pinned = nullptr;
-    for (hipEvent_t& e : step_ev) {
-      if (e) (void)hipEventDestroy(e);
-      e = nullptr;
-    }
+    release_solver_ws();
   }
+  void release_solver_ws();
 };
 
 namespace {
@@ -637,99 +629,252 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream) {
   return HP_OK;
 }
 
-static hipError_t ensure_solver_ws(hp_plan_s* P, int restart, int nrhs) {
-  if (P->ws_restart >= restart && P->ws_nrhs >= nrhs) return hipSuccess;
-  const int r = std::max(restart, P->ws_restart), n = std::max(nrhs, P->ws_nrhs);
-  const size_t np = P->npts;
-  hipError_t e;
-  if ((e = P->V.alloc((size_t)n * (r + 1) * np * 16)) != hipSuccess) return e;
-  if ((e = P->z.alloc((size_t)n * np * P->fsize())) != hipSuccess) return e;
-  if ((e = P->tvec.alloc((size_t)n * np * 16)) != hipSuccess) return e;
-  if ((e = P->state.alloc((size_t)n * sizeof(hp::KState))) != hipSuccess) return e;
-  if ((e = P->part.alloc((size_t)n * hp::kRedBlocks * hp::kPartSlots * 16)) != hipSuccess) return e;
-  if ((e = P->flags.alloc((size_t)n * 3 * sizeof(int))) != hipSuccess) return e;
-  if (P->pinned) (void)hipHostFree(P->pinned);
-  P->pinned = nullptr;
-  if ((e = hipHostMalloc(&P->pinned, (size_t)n * 2 * sizeof(int))) != hipSuccess) return e;
-  for (hipEvent_t& ev : P->step_ev)
-    if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
-  std::memset(P->pinned, 0, (size_t)n * 2 * sizeof(int));
-  P->ws_restart = r;
-  P->ws_nrhs = n;
-  return hipSuccess;
+}  // extern "C"
+
+// Krylov workspace of one batch of right-hand sides: the FP64 basis, the
+// preconditioned vector, the solution update, the per-right-hand-side state,
+// partial sums, device flags and their pinned host copies.
+struct SolverWs {
+  static constexpr int kLag = 3;   // Arnoldi steps a session keeps in flight
+  DevBuf V, z, tvec, state, part, flags;
+  int* pinned = nullptr;           // [0, n): done (host copy), [n, 2n): cycle ended (host copy)
+  hipEvent_t step_ev[kLag + 1] = {};
+  hipEvent_t cyc_ev = nullptr;
+  int restart = 0, nrhs = 0;
+
+  static size_t bytes(size_t np, size_t fsize, int restart, int nrhs) {
+    const size_t n = (size_t)nrhs;
+    return n * ((size_t)(restart + 1) * np * 16 + np * fsize + np * 16 + sizeof(hp::KState) +
+                (size_t)hp::kRedBlocks * hp::kPartSlots * 16 + 3 * sizeof(int));
+  }
+  hipError_t ensure(size_t np, size_t fsize, int r, int n) {
+    if (restart >= r && nrhs >= n) return hipSuccess;
+    r = std::max(r, restart);
+    n = std::max(n, nrhs);
+    hipError_t e;
+    if ((e = V.alloc((size_t)n * (r + 1) * np * 16)) != hipSuccess) return e;
+    if ((e = z.alloc((size_t)n * np * fsize)) != hipSuccess) return e;
+    if ((e = tvec.alloc((size_t)n * np * 16)) != hipSuccess) return e;
+    if ((e = state.alloc((size_t)n * sizeof(hp::KState))) != hipSuccess) return e;
+    if ((e = part.alloc((size_t)n * hp::kRedBlocks * hp::kPartSlots * 16)) != hipSuccess) return e;
+    if ((e = flags.alloc((size_t)n * 3 * sizeof(int))) != hipSuccess) return e;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    if ((e = hipHostMalloc((void**)&pinned, (size_t)n * 2 * sizeof(int))) != hipSuccess) return e;
+    std::memset(pinned, 0, (size_t)n * 2 * sizeof(int));
+    for (hipEvent_t& ev : step_ev)
+      if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    if (!cyc_ev && (e = hipEventCreateWithFlags(&cyc_ev, hipEventDisableTiming)) != hipSuccess) return e;
+    restart = r;
+    nrhs = n;
+    return hipSuccess;
+  }
+  void release() {
+    for (DevBuf* b : {&V, &z, &tvec, &state, &part, &flags}) b->release();
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    for (hipEvent_t& ev : step_ev) {
+      if (ev) (void)hipEventDestroy(ev);
+      ev = nullptr;
+    }
+    if (cyc_ev) (void)hipEventDestroy(cyc_ev);
+    cyc_ev = nullptr;
+    restart = nrhs = 0;
+  }
+};
+
+// A resumable restarted-GMRES solve of nrhs right-hand sides on one stream.
+// The Krylov state stays on the device; the host only enqueues work and reads
+// two pinned flag arrays the kernels publish (converged, cycle ended), so that
+// several sessions can progress concurrently on separate streams.
+struct Session {
+  hp_plan_s* P = nullptr;
+  SolverWs* W = nullptr;
+  const cpx<double>* f = nullptr;
+  cpx<double>* x = nullptr;
+  int nrhs = 0;
+  hp_solve_opts o{};
+  hipStream_t st = nullptr;
+  hp::KrylovArgs K{};
+  size_t vrs = 0;
+  enum Phase { kIdle, kCycleStart, kArnoldi, kFinished } phase = kIdle;
+  int cycles_run = 0, j = 0;
+  bool throttle = true;
+  hp_status status = HP_OK;
+
+  hipError_t start(const cpx<double>* f_, cpx<double>* x_, hipStream_t s) {
+    f = f_;
+    x = x_;
+    st = s;
+    const size_t np = P->npts;
+    vrs = (size_t)(W->restart + 1) * np;
+    K = hp::KrylovArgs{};
+    K.V = (cpx<double>*)W->V.p;
+    K.npts = np;
+    K.vrs = vrs;
+    K.state = (hp::KState*)W->state.p;
+    K.part = (cpx<double>*)W->part.p;
+    K.skip_step = (int*)W->flags.p;
+    K.done = (int*)W->flags.p + W->nrhs;
+    K.host_done = W->pinned;
+    K.host_stop = W->pinned + W->nrhs;
+    K.nrhs = nrhs;
+    K.restart = o.restart;
+    cycles_run = 0;
+    j = 0;
+    hipError_t e;
+    if ((e = hp::launch_fill_zero(W->flags.p, W->flags.bytes, st)) != hipSuccess) return e;
+    if ((e = hp::launch_fnorm(K, f, np, o.rtol, st)) != hipSuccess) return e;
+    return enqueue_cycle_start();
+  }
+
+  // true residual r = f - P_N x into v_0, its norm and the convergence test
+  hipError_t enqueue_cycle_start() {
+    hipError_t e;
+    if ((e = run_stencil(P, 3, x, P->npts, K.V, vrs, f, nrhs, K.done, st)) != hipSuccess) return e;
+    if ((e = hp::launch_cycle_start(K, o.rtol, st)) != hipSuccess) return e;
+    if ((e = hipEventRecord(W->cyc_ev, st)) != hipSuccess) return e;
+    phase = kCycleStart;
+    return hipSuccess;
+  }
+
+  hipError_t enqueue_step() {
+    const size_t np = P->npts;
+    const int mixed = P->prec == HP_MIXED;
+    cpx<double>* vj = K.V + (size_t)j * np;
+    cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
+    hipError_t e;
+    // w = P_N Q u_j
+    if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st)) != hipSuccess)
+      return e;
+    if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess)
+      return e;
+    if ((e = hp::launch_arnoldi_dots(K, j, st)) != hipSuccess) return e;
+    if ((e = hp::launch_arnoldi_update(K, j, st)) != hipSuccess) return e;
+    if ((e = hipEventRecord(W->step_ev[j % (SolverWs::kLag + 1)], st)) != hipSuccess) return e;
+    ++j;
+    return hipSuccess;
+  }
+
+  // x += Q (V_k y), then the next cycle start
+  hipError_t enqueue_cycle_end() {
+    hipError_t e;
+    if ((e = hp::launch_backsolve(K, st)) != hipSuccess) return e;
+    if ((e = hp::launch_lincomb(K, (cpx<double>*)W->tvec.p, P->npts, st)) != hipSuccess) return e;
+    if ((e = run_apply(P, W->tvec.p, 0, P->npts, x, 0, P->npts, true, nrhs, K.done, st)) != hipSuccess) return e;
+    ++cycles_run;
+    return enqueue_cycle_start();
+  }
+
+  static bool ready(hipEvent_t ev, bool block, hipError_t& e) {
+    if (block) {
+      e = hipEventSynchronize(ev);
+      return e == hipSuccess;
+    }
+    e = hipEventQuery(ev);
+    if (e == hipErrorNotReady) {
+      e = hipSuccess;
+      return false;
+    }
+    return e == hipSuccess;
+  }
+
+  bool all(const int* flags) const {
+    for (int r = 0; r < nrhs; ++r)
+      if (!__atomic_load_n(&flags[r], __ATOMIC_ACQUIRE)) return false;
+    return true;
+  }
+
+  // Enqueue up to max_steps Arnoldi steps (and the cycle transitions they
+  // reach).  block = false never waits: it returns when the next action needs
+  // a result the device has not produced yet.
+  hipError_t advance(int max_steps, bool block) {
+    hipError_t e = hipSuccess;
+    int steps = 0;
+    while (phase != kFinished) {
+      if (phase == kCycleStart) {
+        if (!ready(W->cyc_ev, block, e)) return e;
+        if (all(K.host_done) || cycles_run >= o.max_cycles) {
+          phase = kFinished;
+          return hipSuccess;
+        }
+        if ((e = hp::launch_scale_v0(K, st)) != hipSuccess) return e;
+        j = 0;
+        phase = kArnoldi;
+        continue;
+      }
+      // kArnoldi
+      if (j >= o.restart) {
+        if ((e = enqueue_cycle_end()) != hipSuccess) return e;
+        continue;
+      }
+      if (j >= SolverWs::kLag && (throttle || !block)) {
+        // keep at most kLag steps in flight; end the cycle once every
+        // right-hand side has ended it
+        if (!ready(W->step_ev[(j - SolverWs::kLag) % (SolverWs::kLag + 1)], block, e)) return e;
+        if (all(K.host_stop)) {
+          if ((e = enqueue_cycle_end()) != hipSuccess) return e;
+          continue;
+        }
+      }
+      if (steps >= max_steps) return hipSuccess;
+      if ((e = enqueue_step()) != hipSuccess) return e;
+      ++steps;
+    }
+    return hipSuccess;
+  }
+
+  // After kFinished: per right-hand side results (blocking copy of the states).
+  hp_status collect(hp_solve_info* info) {
+    std::vector<hp::KState> hs(nrhs);
+    HP_TRY(hipMemcpyAsync(hs.data(), W->state.p, (size_t)nrhs * sizeof(hp::KState), hipMemcpyDeviceToHost, st));
+    HP_TRY(hipStreamSynchronize(st));
+    hp_status ret = HP_OK;
+    for (int r = 0; r < nrhs; ++r) {
+      const bool ok = W->pinned[r] != 0;
+      info[r].iters = hs[r].iters;
+      info[r].cycles = hs[r].cycles;
+      info[r].rel_true_residual = hs[r].relres;
+      info[r].status = ok ? HP_OK : HP_E_NOT_CONVERGED;
+      if (!ok) ret = HP_E_NOT_CONVERGED;
+    }
+    return ret;
+  }
+};
+
+struct hp_solver_s {
+  Session sess;
+  SolverWs ws;
+};
+
+void hp_plan_s::release_solver_ws() {
+  if (solver_ws_ptr) {
+    solver_ws_ptr->release();
+    delete solver_ws_ptr;
+  }
+  solver_ws_ptr = nullptr;
 }
 
 static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x, int nrhs,
                              const hp_solve_opts& o, hp_solve_info* info, hipStream_t st) {
-  const size_t np = P->npts;
-  HP_TRY(ensure_solver_ws(P, o.restart, nrhs));
-  const size_t vrs = (size_t)(P->ws_restart + 1) * np;
-  hp::KrylovArgs K{};
-  K.V = (cpx<double>*)P->V.p;
-  K.npts = np;
-  K.vrs = vrs;
-  K.state = (hp::KState*)P->state.p;
-  K.part = (cpx<double>*)P->part.p;
-  K.skip_step = (int*)P->flags.p;
-  K.done = (int*)P->flags.p + P->ws_nrhs;
-  int* hstop = (int*)P->pinned + P->ws_nrhs;
-  K.host_stop = hstop;
-  K.nrhs = nrhs;
-  K.restart = o.restart;
-  const int mixed = P->prec == HP_MIXED;
-  HP_TRY(hp::launch_fill_zero(P->flags.p, P->flags.bytes, st));
-  HP_TRY(hp::launch_fnorm(K, f, np, o.rtol, st));
-  int* hdone = (int*)P->pinned;
-  for (int cyc = 0;; ++cyc) {
-    // true residual r = f - P_N x into v_0, its norm, convergence test
-    HP_TRY(run_stencil(P, 3, x, np, K.V, vrs, f, nrhs, K.done, st));
-    HP_TRY(hp::launch_cycle_start(K, o.rtol, st));
-    HP_TRY(hipMemcpyAsync(hdone, K.done, (size_t)nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-    HP_TRY(hipStreamSynchronize(st));
-    bool all = true;
-    for (int r = 0; r < nrhs; ++r) all = all && hdone[r];
-    if (all || cyc >= o.max_cycles) break;
-    HP_TRY(hp::launch_scale_v0(K, st));
-    // Throttle: before enqueuing step j, wait for step j - kLag and stop when
-    // every right-hand side has ended its cycle (the kernels publish that to
-    // pinned host memory), so that few no-op steps are enqueued.  Skipped for
-    // small problems, where a step is too short to hide the host round trip.
-    constexpr int kLag = 3;
-    const bool throttle = np * (size_t)nrhs >= ((size_t)1 << 18);
-    for (int j = 0; j < o.restart; ++j) {
-      if (throttle && j >= kLag) {
-        HP_TRY(hipEventSynchronize(P->step_ev[(j - kLag) % (kLag + 1)]));
-        bool all_stopped = true;
-        for (int r = 0; r < nrhs; ++r) all_stopped = all_stopped && __atomic_load_n(&hstop[r], __ATOMIC_ACQUIRE);
-        if (all_stopped) break;
-      }
-      cpx<double>* vj = K.V + (size_t)j * np;
-      cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
-      // z = Q v_j ; v_{j+1} = P_N z
-      HP_TRY(run_apply(P, vj, 0, vrs, P->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st));
-      HP_TRY(run_stencil(P, mixed ? 2 : 0, P->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st));
-      HP_TRY(hp::launch_arnoldi_dots(K, j, st));
-      HP_TRY(hp::launch_arnoldi_update(K, j, st));
-      if (throttle) HP_TRY(hipEventRecord(P->step_ev[j % (kLag + 1)], st));
-    }
-    // x += Q (V_k y)
-    HP_TRY(hp::launch_backsolve(K, st));
-    HP_TRY(hp::launch_lincomb(K, (cpx<double>*)P->tvec.p, np, st));
-    HP_TRY(run_apply(P, P->tvec.p, 0, np, x, 0, np, true, nrhs, K.done, st));
+  if (!P->solver_ws_ptr) {
+    P->solver_ws_ptr = new (std::nothrow) SolverWs();
+    if (!P->solver_ws_ptr) return HP_E_NOMEM;
   }
-  std::vector<hp::KState> hs(nrhs);
-  HP_TRY(hipMemcpyAsync(hs.data(), P->state.p, (size_t)nrhs * sizeof(hp::KState), hipMemcpyDeviceToHost, st));
-  HP_TRY(hipStreamSynchronize(st));
-  hp_status ret = HP_OK;
-  for (int r = 0; r < nrhs; ++r) {
-    info[r].iters = hs[r].iters;
-    info[r].cycles = hs[r].cycles;
-    info[r].rel_true_residual = hs[r].relres;
-    info[r].status = hdone[r] ? HP_OK : HP_E_NOT_CONVERGED;
-    if (!hdone[r]) ret = HP_E_NOT_CONVERGED;
-  }
-  return ret;
+  HP_TRY(P->solver_ws_ptr->ensure(P->npts, P->fsize(), o.restart, nrhs));
+  Session S;
+  S.P = P;
+  S.W = P->solver_ws_ptr;
+  S.nrhs = nrhs;
+  S.o = o;
+  // small problems: a step is too short to hide a host round trip, enqueue freely
+  S.throttle = P->npts * (size_t)nrhs >= ((size_t)1 << 18);
+  HP_TRY(S.start(f, x, st));
+  HP_TRY(S.advance(1 << 30, true));
+  return S.collect(info);
 }
+
+extern "C" {
 
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts, hp_solve_info* info,
                    void* stream) {
@@ -746,6 +891,56 @@ hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_o
     if (s == HP_E_NOT_CONVERGED) ret = s;
   }
   return ret;
+}
+
+hp_status hp_solver_create(hp_solver* out, hp_plan p, int nrhs, const hp_solve_opts* opts) {
+  if (!out) return HP_E_INVALID;
+  *out = nullptr;
+  if (!p || !opts || nrhs < 1 || nrhs > p->max_nrhs) return HP_E_INVALID;
+  if (opts->restart < 1 || opts->restart > hp::kMaxRestart || opts->max_cycles < 1 || !(opts->rtol > 0))
+    return HP_E_INVALID;
+  hp_solver_s* s = new (std::nothrow) hp_solver_s();
+  if (!s) return HP_E_NOMEM;
+  hipError_t e = s->ws.ensure(p->npts, p->fsize(), opts->restart, nrhs);
+  if (e != hipSuccess) {
+    s->ws.release();
+    delete s;
+    return from_hip(e);
+  }
+  s->sess.P = p;
+  s->sess.W = &s->ws;
+  s->sess.nrhs = nrhs;
+  s->sess.o = *opts;
+  s->sess.throttle = true;
+  *out = s;
+  return HP_OK;
+}
+
+hp_status hp_solver_start(hp_solver s, const void* f, void* x, void* stream) {
+  if (!s || !f || !x) return HP_E_INVALID;
+  HP_TRY(s->sess.start((const cpx<double>*)f, (cpx<double>*)x, (hipStream_t)stream));
+  return HP_OK;
+}
+
+hp_status hp_solver_advance(hp_solver s, int max_steps, int* finished) {
+  if (!s || max_steps < 0 || s->sess.phase == Session::kIdle) return HP_E_INVALID;
+  HP_TRY(s->sess.advance(max_steps, false));
+  if (finished) *finished = s->sess.phase == Session::kFinished;
+  return HP_OK;
+}
+
+hp_status hp_solver_wait(hp_solver s, hp_solve_info* info) {
+  if (!s || !info || s->sess.phase == Session::kIdle) return HP_E_INVALID;
+  HP_TRY(s->sess.advance(1 << 30, true));
+  return s->sess.collect(info);
+}
+
+hp_status hp_solver_destroy(hp_solver s) {
+  if (!s) return HP_E_INVALID;
+  if (s->sess.st) (void)hipStreamSynchronize(s->sess.st);
+  s->ws.release();
+  delete s;
+  return HP_OK;
 }
 
 hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps, double* ms, double* bytes,

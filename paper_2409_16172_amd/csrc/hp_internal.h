@@ -125,6 +125,7 @@ struct KrylovArgs {
   int* skip_step;   // 1 when the current cycle's Arnoldi process has ended
   int* done;        // 1 when the right-hand side has converged
   int* host_stop;   // pinned host copy of skip_step written by the kernels (may be null)
+  int* host_done;   // pinned host copy of done written by the kernels (may be null)
   int nrhs, restart;
 };
 // ||f|| of f [nrhs][npts] (stride frs) -> state.fnorm, target; done/skip_step for f = 0.

@@ -649,6 +649,7 @@ struct DotsCtl {
   int* skip_step;
   int* done;
   int* host_stop;
+  int* host_done;
   int mode, j, restart;
   double rtol;
 };
@@ -667,6 +668,7 @@ __device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs
     c.done[rhs] = S.fnorm > 0.0 ? 0 : 1;
     c.skip_step[rhs] = c.done[rhs];
     publish_stop(c.host_stop, rhs, c.skip_step[rhs]);
+    publish_stop(c.host_done, rhs, c.done[rhs]);
   } else if (c.mode == kDotsCycle) {     // cycle start: beta = ||r||, true-residual test
     const double beta = sqrt(sums[0].re);
     S.beta = beta;
@@ -683,6 +685,7 @@ __device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs
       c.skip_step[rhs] = 0;
     }
     publish_stop(c.host_stop, rhs, c.skip_step[rhs]);
+    publish_stop(c.host_done, rhs, c.done[rhs]);
   }
 }
 
@@ -1016,6 +1019,7 @@ static DotsCtl dots_ctl(const KrylovArgs& a, int mode, int j, double rtol) {
   c.skip_step = a.skip_step;
   c.done = a.done;
   c.host_stop = a.host_stop;
+  c.host_done = a.host_done;
   c.mode = mode;
   c.j = j;
   c.restart = a.restart;
