@@ -292,67 +292,119 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   const size_t np = P->npts;
   const double* zeta = layer ? layer->zeta : nullptr;
 
+  hipStream_t hs = (hipStream_t)stream;
+  hipError_t e;
+  // The raw media go to the device once; the per-point set-up runs there.
+  DevBuf dc, da, dz, dscan;
+  if ((e = dc.alloc(np * 8)) != hipSuccess) return fail(from_hip(e));
+  if ((e = hipMemcpyAsync(dc.p, c, np * 8, hipMemcpyHostToDevice, hs)) != hipSuccess) return fail(from_hip(e));
+  if (a) {
+    if ((e = da.alloc(np * 8)) != hipSuccess) return fail(from_hip(e));
+    if ((e = hipMemcpyAsync(da.p, a, np * 8, hipMemcpyHostToDevice, hs)) != hipSuccess) return fail(from_hip(e));
+  }
+  if (zeta) {
+    if ((e = dz.alloc(np * 8)) != hipSuccess) return fail(from_hip(e));
+    if ((e = hipMemcpyAsync(dz.p, zeta, np * 8, hipMemcpyHostToDevice, hs)) != hipSuccess) return fail(from_hip(e));
+  }
+  auto cleanup = [&]() { dc.release(); da.release(); dz.release(); dscan.release(); };
+  auto failc = [&](hp_status s) { cleanup(); return fail(s); };
+
   // media checks and ranges
+  if ((e = dscan.alloc(sizeof(hp::MediaScan) * hp::kScanBlocks)) != hipSuccess) return failc(from_hip(e));
+  if ((e = hp::launch_media_scan((const double*)dc.p, (const double*)da.p, (const double*)dz.p, np, c0,
+                                 (hp::MediaScan*)dscan.p, hs)) != hipSuccess)
+    return failc(from_hip(e));
+  std::vector<hp::MediaScan> scan(hp::kScanBlocks);
+  if ((e = hipMemcpyAsync(scan.data(), dscan.p, sizeof(hp::MediaScan) * hp::kScanBlocks, hipMemcpyDeviceToHost, hs)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(hs)) != hipSuccess)
+    return failc(from_hip(e));
   P->cmin = INFINITY;
   P->cmax = -INFINITY;
   P->zmax = 0;
-  for (size_t i = 0; i < np; ++i) {
-    const double cv = c[i];
-    if (!std::isfinite(cv) || !(cv > 0)) return fail(HP_E_MEDIA);
-    P->cmin = std::min(P->cmin, cv);
-    P->cmax = std::max(P->cmax, cv);
-    if (a && (!std::isfinite(a[i]) || a[i] < 0)) return fail(HP_E_MEDIA);
-    if (zeta) {
-      if (!std::isfinite(zeta[i]) || zeta[i] < 0) return fail(HP_E_MEDIA);
-      P->zmax = std::max(P->zmax, zeta[i]);
-    }
+  bool bad = false, layer_bad = false, a_varies = false;
+  for (const hp::MediaScan& m : scan) {
+    P->cmin = std::min(P->cmin, m.cmin);
+    P->cmax = std::max(P->cmax, m.cmax);
+    P->zmax = std::max(P->zmax, m.zmax);
+    bad = bad || m.bad;
+    layer_bad = layer_bad || m.layer_bad;
+    a_varies = a_varies || m.a_varies;
   }
+  if (bad) return failc(HP_E_MEDIA);
   const bool q1 = opts->m_real == 1 && !opts->nodes_real;
   const bool has_layer = P->zmax > 0 && !q1;
   st = place_real_nodes(*P, *opts, c0, has_layer);
-  if (st) return fail(st);
+  if (st) return failc(st);
   P->Mt = 0;
   if (has_layer) {
     const int Mt = opts->m_layer;
-    if (Mt < 1 || P->M + Mt > hp::kMaxNodes) return fail(HP_E_INVALID);
+    if (Mt < 1 || P->M + Mt > hp::kMaxNodes) return failc(HP_E_INVALID);
     P->znode[0] = 0;
     for (int j = 1; j <= Mt; ++j) {
       if (opts->nodes_zeta) {
         P->znode[j] = opts->nodes_zeta[j - 1];
-        if (!(P->znode[j] > P->znode[j - 1]) || !std::isfinite(P->znode[j])) return fail(HP_E_INVALID);
+        if (!(P->znode[j] > P->znode[j - 1]) || !std::isfinite(P->znode[j])) return failc(HP_E_INVALID);
       } else {
         P->znode[j] = (j == Mt) ? P->zmax : P->zmax * ((double)j / Mt);
       }
     }
     P->Mt = Mt;
-    for (size_t i = 0; i < np; ++i)
-      if (zeta[i] > 0 && std::fabs(c[i] - c0) > 1e-12 * c0) return fail(HP_E_LAYER);
+    if (layer_bad) return failc(HP_E_LAYER);
   }
   P->K = P->M + P->Mt;
+  hp::NodeTable T{};
+  T.M = P->M;
+  T.Mt = P->Mt;
+  T.mo = P->mo;
+  T.has_layer = has_layer ? 1 : 0;
+  for (int i = 0; i < P->M; ++i) T.cnode[i] = P->cnode[i];
+  for (int i = 0; i <= P->Mt; ++i) T.znode[i] = P->znode[i];
 
-  // per-point records
-  std::vector<double> pos(np);
-  for (size_t i = 0; i < np; ++i) pos[i] = encode_point(*P, c[i], has_layer ? zeta[i] : 0.0);
+  // per-point records and stencil coefficients {gamma^2, beta} (Section 5 with
+  // the complex speed of Section 4.3), in FP64 on the device
+  double sih2 = 0;
+  for (int d = 0; d < P->dim; ++d) {
+    const double h = P->len[d] / P->n[d];
+    sih2 += 1.0 / (h * h);
+  }
+  if ((e = P->pos.alloc(np * 8)) != hipSuccess) return failc(from_hip(e));
+  if ((e = P->coef64.alloc(np * 32)) != hipSuccess) return failc(from_hip(e));
+  if (P->prec == HP_MIXED && (e = P->coef32.alloc(np * 16)) != hipSuccess) return failc(from_hip(e));
+  if ((e = hp::launch_plan_points((const double*)dc.p, (const double*)da.p, (const double*)dz.p, np, T, omega, sih2,
+                                  (double*)P->pos.p, (cpx<double>*)P->coef64.p, (cpx<float>*)P->coef32.p, hs)) !=
+      hipSuccess)
+    return failc(from_hip(e));
+
+  // Node usage.  Each point has at most two non-zero weights, so a row of
+  // pass C only needs the node fields its points use; the passes before it
+  // neither write nor transform the rest.
+  const int nl = P->n[P->dim - 1];
+  const size_t rows = np / nl;
+  if ((e = P->rowmask.alloc(rows * 8)) != hipSuccess) return failc(from_hip(e));
+  if ((e = hp::launch_row_masks((const double*)P->pos.p, nl, rows, T, (uint64_t*)P->rowmask.p, hs)) != hipSuccess)
+    return failc(from_hip(e));
+  std::vector<uint64_t> rm(rows, 0);
+  if ((e = hipMemcpyAsync(rm.data(), P->rowmask.p, rows * 8, hipMemcpyDeviceToHost, hs)) != hipSuccess ||
+      (e = hipStreamSynchronize(hs)) != hipSuccess)
+    return failc(from_hip(e));
 
   // symbol damping per node: uniform a as is, a(c_m) if given, otherwise the
   // weight-averaged a over the points each real node serves; floored.
-  bool uniform = true;
   const double a0 = a ? a[0] : 0.0;
-  if (a)
-    for (size_t i = 1; i < np && uniform; ++i) uniform = a[i] == a0;
   for (int m = 0; m < P->M; ++m) P->ahat[m] = a0;
   if (opts->a_nodes) {
     for (int m = 0; m < P->M; ++m) {
-      if (!(opts->a_nodes[m] >= 0) || !std::isfinite(opts->a_nodes[m])) return fail(HP_E_INVALID);
+      if (!(opts->a_nodes[m] >= 0) || !std::isfinite(opts->a_nodes[m])) return failc(HP_E_INVALID);
       P->ahat[m] = opts->a_nodes[m];
     }
-  } else if (!uniform) {
+  } else if (a_varies) {
     std::vector<double> num(P->K, 0.0), den(P->K, 0.0);
     double mean = 0;
     for (size_t i = 0; i < np; ++i) {
       int A, B;
       double t;
-      point_nodes(*P, pos[i], A, B, t);
+      point_nodes(*P, encode_point(*P, c[i], has_layer ? zeta[i] : 0.0), A, B, t);
       auto add = [&](int n, double w) {
         if (n < P->M) { num[n] += w * a[i]; den[n] += w; }
       };
@@ -395,28 +447,14 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     if (nc[k].aim != 0.0 || nc[k].gim != 0.0) continue;
     for (int k0 = 0; k0 < P->n[0]; ++k0)
       for (size_t ci = 0; ci < S; ++ci)
-        if (nc[k].are - nc[k].gre * (lam0[k0] + lamin[ci]) == 0.0) return fail(HP_E_MEDIA);
+        if (nc[k].are - nc[k].gre * (lam0[k0] + lamin[ci]) == 0.0) return failc(HP_E_MEDIA);
   }
 
-  // Node usage.  Each point has at most two non-zero weights, so a row of
-  // pass C only needs the node fields its points use; the passes before it
-  // neither write nor transform the rest.
-  const int nl = P->n[P->dim - 1];
-  const size_t rows = np / nl;
   const int G = hp::combine_group_rows(P->real_kind(), nl);
-  std::vector<uint64_t> rm(rows, 0), gm((rows + G - 1) / G, 0);
+  std::vector<uint64_t> gm((rows + G - 1) / G, 0);
   for (size_t r = 0; r < rows; ++r) {
-    uint64_t m = 0;
-    for (int i = 0; i < nl; ++i) {
-      int A, B;
-      double t;
-      point_nodes(*P, pos[r * nl + i], A, B, t);
-      if (A == B || t != 1.0) m |= 1ull << A;
-      if (A != B && t != 0.0) m |= 1ull << B;
-    }
-    rm[r] = m;
-    gm[r / G] |= m;
-    P->rows_used += (double)__builtin_popcountll(m);
+    gm[r / G] |= rm[r];
+    P->rows_used += (double)__builtin_popcountll(rm[r]);
   }
   const int n0 = P->n[0];
   const size_t rows_per_slab = rows / n0;
@@ -432,39 +470,15 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   std::vector<uint16_t> smask((size_t)P->K * Tb, 0);
   for (int k = 0; k < P->K; ++k)
     for (int j = 0; j < Tb; ++j)
-      for (int e = 0; e < Eb; ++e)
-        if (need[(size_t)k * n0 + j + (size_t)Tb * e]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e);
+      for (int e2 = 0; e2 < Eb; ++e2)
+        if (need[(size_t)k * n0 + j + (size_t)Tb * e2]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e2);
 
-  // stencil coefficients {gamma^2, beta} (Section 5 with gamma of Section 4.3)
-  double sih2 = 0, ih2[3] = {0, 0, 0};
-  for (int d = 0; d < P->dim; ++d) {
-    const double h = P->len[d] / P->n[d];
-    ih2[d] = 1.0 / (h * h);
-    sih2 += ih2[d];
-  }
-  std::vector<cpx<double>> cf(2 * np);
-  for (size_t i = 0; i < np; ++i) {
-    const double cv = c[i], zv = zeta ? zeta[i] : 0.0, av = a ? a[i] : 0.0;
-    const double gr = cv * cv * (1 - zv * zv), gi = -2 * cv * cv * zv;   // (c (1 - i zeta))^2
-    cf[2 * i] = {gr, gi};
-    cf[2 * i + 1] = {omega * omega - 2 * gr * sih2, omega * av - 2 * gi * sih2};
-  }
-
-  hipError_t e;
-  if ((e = upload(P->nodes, nc)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->pos, pos)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->grpmask, gm)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->rowmask, rm)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->slabneed, need)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->storemask, smask)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->coef64, cf)) != hipSuccess) return fail(from_hip(e));
-  if (P->prec == HP_MIXED) {
-    std::vector<cpx<float>> cf32(2 * np);
-    for (size_t i = 0; i < 2 * np; ++i) cf32[i] = {(float)cf[i].re, (float)cf[i].im};
-    if ((e = upload(P->coef32, cf32)) != hipSuccess) return fail(from_hip(e));
-  }
-  if ((e = upload(P->lam_ax, lam0)) != hipSuccess) return fail(from_hip(e));
-  if ((e = upload(P->lam_in, lamin)) != hipSuccess) return fail(from_hip(e));
+  if ((e = upload(P->nodes, nc)) != hipSuccess) return failc(from_hip(e));
+  if ((e = upload(P->grpmask, gm)) != hipSuccess) return failc(from_hip(e));
+  if ((e = upload(P->slabneed, need)) != hipSuccess) return failc(from_hip(e));
+  if ((e = upload(P->storemask, smask)) != hipSuccess) return failc(from_hip(e));
+  if ((e = upload(P->lam_ax, lam0)) != hipSuccess) return failc(from_hip(e));
+  if ((e = upload(P->lam_in, lamin)) != hipSuccess) return failc(from_hip(e));
   for (int d = 0; d < P->dim; ++d) {
     const int n = P->n[d];
     std::vector<cpx<double>> w(n);
@@ -475,18 +489,18 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
       wf[m] = {(float)w[m].re, (float)w[m].im};
     }
     if (P->prec == HP_FP64) {
-      if ((e = upload(P->tw64[d], w)) != hipSuccess) return fail(from_hip(e));
+      if ((e = upload(P->tw64[d], w)) != hipSuccess) return failc(from_hip(e));
     } else {
-      if ((e = upload(P->tw32[d], wf)) != hipSuccess) return fail(from_hip(e));
+      if ((e = upload(P->tw32[d], wf)) != hipSuccess) return failc(from_hip(e));
     }
   }
   const size_t fb = (size_t)P->max_nrhs * np * P->fsize();
-  if ((e = P->t.alloc(fb)) != hipSuccess) return fail(from_hip(e));
-  if ((e = P->fields.alloc(fb * P->K)) != hipSuccess) return fail(from_hip(e));
-  (void)stream;
+  if ((e = P->t.alloc(fb)) != hipSuccess) return failc(from_hip(e));
+  if ((e = P->fields.alloc(fb * P->K)) != hipSuccess) return failc(from_hip(e));
   // node-field rows that no point uses are never written; keep them finite
-  if ((e = hp::launch_fill_zero(P->fields.p, P->fields.bytes, nullptr)) != hipSuccess) return fail(from_hip(e));
-  if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(from_hip(e));
+  if ((e = hp::launch_fill_zero(P->fields.p, P->fields.bytes, hs)) != hipSuccess) return failc(from_hip(e));
+  if ((e = hipStreamSynchronize(hs)) != hipSuccess) return failc(from_hip(e));
+  cleanup();
   *out = P;
   return HP_OK;
 }

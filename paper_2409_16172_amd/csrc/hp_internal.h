@@ -142,4 +142,31 @@ hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
+// ---- plan set-up on the device (FP64) ----
+struct MediaScan {
+  double cmin, cmax, zmax, a0;
+  int bad;          // non-finite or out-of-range value
+  int layer_bad;    // zeta > 0 where |c - c0| > 1e-12 c0
+  int a_varies;     // a is not uniform
+  int pad;
+};
+constexpr int kScanBlocks = 256;
+// per-block partial scans of the media (a, zeta may be null)
+hipError_t launch_media_scan(const double* c, const double* a, const double* zeta, size_t n, double c0,
+                             MediaScan* partial, hipStream_t st);
+
+struct NodeTable {
+  int M, Mt, mo, has_layer;
+  double cnode[kMaxNodes];
+  double znode[kMaxNodes + 1];
+};
+// per point: interpolation record (see decode_pos) and stencil coefficients
+// {gamma^2, omega^2 + i omega a - 2 gamma^2 sum_j h_j^-2} in FP64 (and FP32 if coef32)
+hipError_t launch_plan_points(const double* c, const double* a, const double* zeta, size_t n, const NodeTable& T,
+                              double omega, double sum_ih2, double* pos, cpx<double>* coef64, cpx<float>* coef32,
+                              hipStream_t st);
+// per row of nl points: bit k set if some point of the row has a non-zero weight on node k
+hipError_t launch_row_masks(const double* pos, int nl, size_t rows, const NodeTable& T, uint64_t* rowmask,
+                            hipStream_t st);
+
 }  // namespace hp

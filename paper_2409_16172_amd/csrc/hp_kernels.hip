@@ -1008,6 +1008,129 @@ __global__ void k_fill_zero(uint32_t* p, size_t n) {
     p[i] = 0u;
 }
 
+// ---------------------------------------------------------------- plan set-up
+__global__ __launch_bounds__(256) void k_media_scan(const double* __restrict__ c, const double* __restrict__ a,
+                                                    const double* __restrict__ z, size_t n, double c0,
+                                                    MediaScan* __restrict__ partial) {
+  __shared__ double smin[256], smax[256], szmax[256];
+  __shared__ int sbad[256], slay[256], svar[256];
+  double cmin = INFINITY, cmax = -INFINITY, zmax = 0.0;
+  int bad = 0, lay = 0, var = 0;
+  const double a0 = a ? a[0] : 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double cv = c[i];
+    bad |= !(cv > 0.0) || !isfinite(cv);
+    cmin = fmin(cmin, cv);
+    cmax = fmax(cmax, cv);
+    if (a) {
+      const double av = a[i];
+      bad |= !(av >= 0.0) || !isfinite(av);
+      var |= av != a0;
+    }
+    if (z) {
+      const double zv = z[i];
+      bad |= !(zv >= 0.0) || !isfinite(zv);
+      zmax = fmax(zmax, zv);
+      lay |= zv > 0.0 && fabs(cv - c0) > 1e-12 * c0;
+    }
+  }
+  smin[threadIdx.x] = cmin; smax[threadIdx.x] = cmax; szmax[threadIdx.x] = zmax;
+  sbad[threadIdx.x] = bad; slay[threadIdx.x] = lay; svar[threadIdx.x] = var;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      szmax[threadIdx.x] = fmax(szmax[threadIdx.x], szmax[threadIdx.x + w]);
+      sbad[threadIdx.x] |= sbad[threadIdx.x + w];
+      slay[threadIdx.x] |= slay[threadIdx.x + w];
+      svar[threadIdx.x] |= svar[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    partial[blockIdx.x] = {smin[0], smax[0], szmax[0], a0, sbad[0], slay[0], svar[0], 0};
+}
+
+// Interpolation record of a point: real segment seg + t, or layer segment
+// -(1 + j + t) (the inverse of decode_pos), by binary search in the nodes.
+__device__ double encode_pos(const NodeTable& T, double c, double z) {
+  if (T.Mt > 0 && z > 0.0) {
+    const double zz = fmin(z, T.znode[T.Mt]);
+    int lo = 0, hi = T.Mt;             // largest j with znode[j] <= zz, within [0, Mt-1]
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (T.znode[mid] <= zz) lo = mid; else hi = mid; }
+    const double t = (zz - T.znode[lo]) / (T.znode[lo + 1] - T.znode[lo]);
+    return -(1.0 + lo + t);
+  }
+  if (T.M == 1) return 0.0;
+  const double cc = fmin(fmax(c, T.cnode[0]), T.cnode[T.M - 1]);
+  int lo = 0, hi = T.M - 1;            // largest s with cnode[s] <= cc, within [0, M-2]
+  while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (T.cnode[mid] <= cc) lo = mid; else hi = mid; }
+  const double t = (cc - T.cnode[lo]) / (T.cnode[lo + 1] - T.cnode[lo]);
+  return lo + t;
+}
+
+__global__ __launch_bounds__(256) void k_plan_points(const double* __restrict__ c, const double* __restrict__ a,
+                                                     const double* __restrict__ z, size_t n, NodeTable T,
+                                                     double omega, double sih2, double* __restrict__ pos,
+                                                     cpx<double>* __restrict__ coef64,
+                                                     cpx<float>* __restrict__ coef32) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double cv = c[i], zv = z ? z[i] : 0.0, av = a ? a[i] : 0.0;
+    pos[i] = encode_pos(T, cv, T.has_layer ? zv : 0.0);
+    const double gr = cv * cv * (1.0 - zv * zv), gi = -2.0 * cv * cv * zv;   // (c (1 - i zeta))^2
+    const cpx<double> g2 = {gr, gi}, be = {omega * omega - 2.0 * gr * sih2, omega * av - 2.0 * gi * sih2};
+    coef64[2 * i] = g2;
+    coef64[2 * i + 1] = be;
+    if (coef32) {
+      coef32[2 * i] = {(float)g2.re, (float)g2.im};
+      coef32[2 * i + 1] = {(float)be.re, (float)be.im};
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_row_masks(const double* __restrict__ pos, int nl, NodeTable T,
+                                                   uint64_t* __restrict__ rowmask) {
+  __shared__ uint64_t sm[256];
+  const size_t row = blockIdx.x;
+  uint64_t m = 0;
+  for (int i = threadIdx.x; i < nl; i += 256) {
+    int A, B;
+    double t;
+    decode_pos(pos[row * nl + i], T.M, T.Mt, T.mo, A, B, t);
+    if (A == B || t != 1.0) m |= 1ull << A;
+    if (A != B && t != 0.0) m |= 1ull << B;
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] |= sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rowmask[row] = sm[0];
+}
+
+hipError_t launch_media_scan(const double* c, const double* a, const double* zeta, size_t n, double c0,
+                             MediaScan* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_media_scan, dim3(kScanBlocks), dim3(256), 0, st, c, a, zeta, n, c0, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_points(const double* c, const double* a, const double* zeta, size_t n, const NodeTable& T,
+                              double omega, double sum_ih2, double* pos, cpx<double>* coef64, cpx<float>* coef32,
+                              hipStream_t st) {
+  const size_t b = (n + 255) / 256;
+  hipLaunchKernelGGL(k_plan_points, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, st, c, a, zeta, n, T, omega,
+                     sum_ih2, pos, coef64, coef32);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_masks(const double* pos, int nl, size_t rows, const NodeTable& T, uint64_t* rowmask,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_row_masks, dim3((unsigned)rows), dim3(256), 0, st, pos, nl, T, rowmask);
+  return hipGetLastError();
+}
+
 static unsigned stream_blocks(size_t npts) {
   size_t b = (npts + 255) / 256;
   return (unsigned)(b < 2048 ? (b == 0 ? 1 : b) : 2048);

@@ -250,3 +250,35 @@ def test_solve_batch_equals_single(hp, dev):
     for r in range(3):
         x1, i1 = plan.solve(f[r:r + 1].contiguous(), rtol=1e-8)
         assert torch.equal(x1[0], x3[r]) and i1[0].iters == i3[r].iters
+
+
+def test_plan_error_paths(hp, dev):
+    """Invalid media and options are reported by status code before any apply."""
+    shape = (16, 16)
+    c = np.ones(shape)
+    zeta = inputs.frame_layer(shape, 2, 0.1)
+    bad_layer = c.copy()
+    bad_layer[0, 3] = 1.05
+    cases = [
+        (dict(c=bad_layer, zeta=zeta, m_real=3), hp.HP_E_LAYER),
+        (dict(c=np.where(np.arange(256).reshape(shape) == 7, np.nan, 1.0)), hp.HP_E_MEDIA),
+        (dict(c=-c), hp.HP_E_MEDIA),
+        (dict(c=c, a=-np.ones(shape)), hp.HP_E_MEDIA),
+        (dict(c=c, zeta=-zeta), hp.HP_E_MEDIA),
+        (dict(c=c, m_real=0), hp.HP_E_INVALID),
+        (dict(c=c, a_floor=-1.0), hp.HP_E_INVALID),
+    ]
+    for kw, code in cases:
+        args = dict(a=None, zeta=None, m_real=4, a_floor=1.0)
+        args.update(kw)
+        cc = args.pop("c")
+        with pytest.raises(hp.HelmpreError) as e:
+            hp.Plan(shape, 10.0, cc, args.pop("a"), args.pop("zeta"), **args)
+        assert e.value.code == code, (kw.keys(), e.value)
+    with pytest.raises(hp.HelmpreError) as e:
+        hp.Plan((12, 16), 10.0, np.ones((12, 16)))
+    assert e.value.code == hp.HP_E_SHAPE
+    # a = 0 with no floor and omega = c |xi| on a grid mode: zero symbol denominator
+    with pytest.raises(hp.HelmpreError) as e:
+        hp.Plan(shape, 2 * np.pi, c, None, None, m_real=1, a_floor=0.0)
+    assert e.value.code == hp.HP_E_MEDIA
