@@ -17,6 +17,7 @@ on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import numpy as np
 import hashlib
 import json
 import os
@@ -82,6 +83,93 @@ def cpu_baseline(w, gpu_iters, gpu_cycles, steps=6):
                       f"to {gpu_iters} steps and {gpu_cycles} cycles = {t_solve:.1f} s"}
 
 
+def serving_run(dev, n_requests=24, rate=40.0):
+    """Continuous-batching stream: Poisson arrivals of mixed-precision solves on
+    256^2 / 512^2 / 1024^2 random media, 20-150 wavelengths (at most N/4), rtol 1e-8;
+    latency from arrival to solution, including plan set-up."""
+    from paper_2409_16172_amd import serve
+    reqs = serve.stream_requests(n_requests, rate_per_s=rate, grids=((256, 256), (512, 512), (1024, 1024)),
+                                 precision="mixed")
+    srv = serve.Server(hbm_budget_bytes=200 << 30, max_active=8, steps_per_turn=2)
+    done = srv.run(reqs, dev=dev)
+    st = serve.latency_stats(done)
+    st.update({"arrival_rate_per_s": rate, "grids": [256, 512, 1024], "precision": "mixed",
+               "peak_workspace_GiB": srv.peak_in_use / 2 ** 30})
+    return st
+
+
+def large_grid_compare(dev, reps=2):
+    """2048^2, 200 wavelengths, 24 + 3 nodes: mixed precision against the FP64 GPU
+    path, both to the FP64 true residual 1e-8."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    w = inputs.workload("2d_2048_grf")
+    f = torch.from_numpy(w.f).to(dev)
+    out = {}
+    for prec in ("mixed", "fp64"):
+        p = binding.plan_from_workload(w, precision=prec)
+        p.solve(f)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            x, info = p.solve(f)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        rng = np.random.default_rng(0)
+        v = torch.from_numpy(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape)).to(dev).to(p.field_dtype)
+        ms, by = p.profile_apply(v, reps=10)
+        out[prec] = {"solves_per_s": 1.0 / dt, "iters": info[0].iters, "rel_true_residual": info[0].rel_true_residual,
+                     "apply_us": sum(ms) * 1e3, "apply_GBps": sum(by) / (sum(ms) * 1e-3) / 1e9}
+        p.close()
+        del x
+    out["mixed_over_fp64_solves"] = out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    return out
+
+
+def batch3d(args, dev):
+    """3-D batch: nrhs Gaussian sources on one random medium with a sphere, solved
+    together (every pass is one launch over all right-hand sides), mixed precision,
+    rtol 1e-8; compared with solving right-hand sides one at a time."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    w = inputs.workload("3d_256_grf", n=args.n3d, nrhs=args.nrhs3d)
+    t0 = time.perf_counter()
+    plan = binding.plan_from_workload(w)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    f = torch.from_numpy(w.f).to(dev)
+    print(f"[bench] 3-D batch {w.shape} x {w.f.shape[0]} K={plan.info()['K']} plan {t_plan * 1e3:.0f} ms",
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, infos = plan.solve(f, rtol=1e-8, restart=30)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[bench] batch solve {t_batch:.2f} s iters {[i.iters for i in infos]}", file=sys.stderr, flush=True)
+    del x
+    singles = []
+    for r in range(min(2, w.f.shape[0])):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x1, i1 = plan.solve(f[r:r + 1].contiguous(), rtol=1e-8, restart=30)
+        torch.cuda.synchronize()
+        singles.append(time.perf_counter() - t0)
+    rng = np.random.default_rng(0)
+    v = torch.from_numpy((rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape))[None]).to(dev).to(plan.field_dtype)
+    ms, by = plan.profile_apply(v, reps=3)
+    out = {"mode": "batch3d", "workload": f"{w.name}: {w.shape[0]}^3, 7-point FD, {w.info['n_lambda']:.0f} wavelengths, "
+                                         f"random field in [0.8,1.2] + c=1.4 sphere, {w.info['layer_cells']}-cell layer, "
+                                         f"{w.m_real}+{w.m_layer} nodes, mixed precision, rtol 1e-8",
+           "nrhs": int(w.f.shape[0]), "plan_ms": t_plan * 1e3, "batch_s": t_batch,
+           "batch_solves_per_s": w.f.shape[0] / t_batch, "single_s": singles,
+           "single_solves_per_s": len(singles) / sum(singles) if singles else None,
+           "iters": [i.iters for i in infos], "max_rel_true_residual": max(i.rel_true_residual for i in infos),
+           "converged": all(i.status == 0 for i in infos),
+           "apply_1rhs_us": sum(ms) * 1e3, "apply_1rhs_GBps": sum(by) / (sum(ms) * 1e-3) / 1e9,
+           "pass_us": dict(zip(PASS_NAMES, [t * 1e3 for t in ms]))}
+    print(json.dumps(out))
+
+
 def apply_only(args, w, plan, dev):
     import numpy as np
     import torch
@@ -114,9 +202,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--apply-reps", type=int, default=20)
-    ap.add_argument("--mode", choices=["solve", "apply"], default="solve",
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 mixed vs FP64 comparison")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--n3d", type=int, default=256)
+    ap.add_argument("--nrhs3d", type=int, default=16)
+    ap.add_argument("--mode", choices=["solve", "apply", "batch3d"], default="solve",
                     help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
-                         "(used to calibrate hardware byte counters)")
+                         "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -130,6 +224,9 @@ def main():
     from paper_2409_16172_amd import binding, inputs
 
     dev = torch.device("cuda:0")
+    if args.mode == "batch3d":
+        batch3d(args, dev)
+        return
     w = inputs.workload(args.workload)
     if args.precision:
         w.precision = args.precision
@@ -190,6 +287,8 @@ def main():
                  "converged": im[0].status == 0}
         pm.close()
 
+    serving = None if args.no_serve else serving_run(dev, args.serve_requests, args.serve_rate)
+    large = None if args.no_large else large_grid_compare(dev)
     cpu = None if args.no_cpu else cpu_baseline(w, info.iters, info.cycles)
     lat_ms = sorted(t * 1e3 for t in lat)
     out = {
@@ -216,6 +315,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "solve": {"iters": info.iters, "cycles": info.cycles, "rel_true_residual": info.rel_true_residual},
         "mixed": mixed,
+        "serving": serving,
+        "grid_2048": large,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": by[dom], "launch_us": ms[dom] * 1e3},

@@ -282,3 +282,17 @@ def test_plan_error_paths(hp, dev):
     with pytest.raises(hp.HelmpreError) as e:
         hp.Plan(shape, 2 * np.pi, c, None, None, m_real=1, a_floor=0.0)
     assert e.value.code == hp.HP_E_MEDIA
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_3d_matches_oracle_residual(orc, hp, dev, prec):
+    """3-D (7-point stencil, middle-axis passes) batched solve of 2 sources to the FP64 true residual."""
+    w = inputs.workload("3d_256_grf", n=32, nrhs=2)
+    _print_case("solve_3d", shape=w.shape, prec=prec)
+    plan = hp.plan_from_workload(w, precision=prec)
+    ref = orc.from_workload(w)
+    x, info = plan.solve(torch.from_numpy(w.f).to(dev), rtol=1e-8)
+    xh = x.cpu().numpy()
+    for r in range(2):
+        assert info[r].status == 0
+        assert rel(ref.matvec(xh[r]), w.f[r]) <= 1e-8 * 1.001
