@@ -184,10 +184,12 @@ hp_status hp_solver_advance(hp_solver s, int max_steps, int* finished);
 hp_status hp_solver_wait(hp_solver s, hp_solve_info* info);
 hp_status hp_solver_destroy(hp_solver s);
 
-/* Diagnostic timing of the preconditioner passes (for benchmarks): runs `reps`
- * applies of v -> u (as hp_apply_precond, nrhs <= max_nrhs) and records HIP
- * events on `stream` around every pass.  Blocks until done.  ms[5] receives the
- * average milliseconds per launch of the passes in order
+/* Diagnostic timing of the preconditioner passes (for benchmarks): computes
+ * u = Q_M v (as hp_apply_precond, nrhs <= max_nrhs), then launches each
+ * out-of-place pass `reps` times back to back between two HIP events on
+ * `stream` (the in-place 3-D middle-axis passes once).  u holds Q_M v on
+ * return.  Blocks until done.  ms[5] receives the average milliseconds per
+ * launch of the passes in order
  *   0: forward transform along the last (contiguous) axis
  *   1: forward transform along the middle axis (3-D only, else 0)
  *   2: forward transform along axis 0, symbol multiplies and inverse transforms

@@ -537,9 +537,13 @@ namespace {
 // in_kind/out_kind: 0 = complex128, 1 = complex64.
 // ev (optional): 6 events recorded before pass A and after each of the five
 // pass slots (A, A', B, M, C; the 3-D-only slots are recorded even when empty).
+// reps (profiling only, with acc false): the out-of-place passes A, B and C are
+// launched reps times back to back between their events; they read and write
+// disjoint buffers, so a repeat recomputes the same result.  The in-place
+// middle-axis passes of 3-D grids are launched once.
 hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, void* u, int out_kind,
                      size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st,
-                     hipEvent_t* ev = nullptr) {
+                     hipEvent_t* ev = nullptr, int reps = 1) {
   const int rk = P->real_kind();
   const size_t np = P->npts;
   hipError_t e;
@@ -550,8 +554,10 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     return (ev && (P->dim == 3 || (i != 2 && i != 4))) ? hipEventRecord(ev[i], st) : hipSuccess;
   };
   if ((e = mark(0)) != hipSuccess) return e;
-  e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, st);
-  if (e != hipSuccess) return e;
+  for (int r = 0; r < reps; ++r) {
+    e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, st);
+    if (e != hipSuccess) return e;
+  }
   if ((e = mark(1)) != hipSuccess) return e;
   if (P->dim == 3) {   // forward along the middle axis, in place
     hp::ColsArgs m{};
@@ -568,7 +574,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   b.lam_ax = (const double*)P->lam_ax.p; b.lam_in = (const double*)P->lam_in.p;
   b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
   b.store_mask = (const uint16_t*)P->storemask.p;
-  if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
+  for (int r = 0; r < reps; ++r)
+    if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
   if ((e = mark(3)) != hipSuccess) return e;
   if (P->dim == 3) {   // inverse along the middle axis for the K fields, in place
     hp::ColsArgs m{};
@@ -584,7 +591,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   c.fields = P->fields.p; c.fs = np; c.frs = np * P->K; c.pos = (const double*)P->pos.p;
   c.grpmask = (const uint64_t*)P->grpmask.p; c.rowmask = (const uint64_t*)P->rowmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
   c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
-  if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
+  for (int r = 0; r < (acc ? 1 : reps); ++r)
+    if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
   return mark(5);
 }
 
@@ -964,24 +972,27 @@ hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps
   const int kind = p->prec == HP_FP64 ? 0 : 1;
   hipEvent_t ev[6];
   for (int i = 0; i < 6; ++i) HP_TRY(hipEventCreate(&ev[i]));
+  // one plain apply first (fills the intermediate buffers and warms the caches), then
+  // every out-of-place pass reps times back to back between a pair of events, so that
+  // an event pair brackets a run of launches of one kernel and the per-launch figure
+  // is that kernel's duration (the in-place 3-D middle-axis passes run once).
   double acc[5] = {0, 0, 0, 0, 0};
-  hipError_t err = hipSuccess;
-  for (int r = 0; r < reps && err == hipSuccess; ++r) {
-    err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st, ev);
-    if (err == hipSuccess) err = hipEventSynchronize(ev[5]);
-    const int slots3[5][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}};
-    const int slots2[5][2] = {{0, 1}, {-1, -1}, {1, 3}, {-1, -1}, {3, 5}};
-    for (int i = 0; i < 5 && err == hipSuccess; ++i) {
-      const int a = p->dim == 3 ? slots3[i][0] : slots2[i][0], b = p->dim == 3 ? slots3[i][1] : slots2[i][1];
-      if (a < 0) continue;
-      float t = 0;
-      err = hipEventElapsedTime(&t, ev[a], ev[b]);
-      acc[i] += t;
-    }
+  hipError_t err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st);
+  if (err == hipSuccess) err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st, ev, reps);
+  if (err == hipSuccess) err = hipEventSynchronize(ev[5]);
+  const int slots3[5][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}};
+  const int slots2[5][2] = {{0, 1}, {-1, -1}, {1, 3}, {-1, -1}, {3, 5}};
+  const int count[5] = {reps, 1, reps, 1, reps};
+  for (int i = 0; i < 5 && err == hipSuccess; ++i) {
+    const int a = p->dim == 3 ? slots3[i][0] : slots2[i][0], b = p->dim == 3 ? slots3[i][1] : slots2[i][1];
+    if (a < 0) continue;
+    float t = 0;
+    err = hipEventElapsedTime(&t, ev[a], ev[b]);
+    acc[i] = (double)t / count[i];
   }
   for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   HP_TRY(err);
-  for (int i = 0; i < 5; ++i) ms[i] = acc[i] / reps;
+  for (int i = 0; i < 5; ++i) ms[i] = acc[i];
   pass_bytes(p, nrhs, (int)p->fsize(), (int)p->fsize(), bytes);
   return HP_OK;
 }

@@ -189,6 +189,28 @@ def test_apply_in_place(hp, dev):
     assert torch.equal(u, v2)
 
 
+@pytest.mark.parametrize("shape", [(128, 128), (16, 32, 16)])
+def test_profile_apply_result_and_timings(hp, dev, shape):
+    """The timing entry point leaves Q_M v in u (passes repeated back to back recompute it)."""
+    c, zeta = _media(shape, seed=9)
+    omega = 2 * np.pi * 4
+    plan = hp.Plan(shape, omega, c, np.full(shape, 0.05 * omega), zeta, m_real=6, max_nrhs=2,
+                   a_floor=0.05 * omega)
+    v = _tensor(_rand(shape, 10, nrhs=2), dev, torch.complex128)
+    u = plan.apply(v)
+    _print_case("profile_apply", shape=shape)
+    ms, by = plan.profile_apply(v, reps=3)
+    u2 = torch.empty_like(v)
+    ms, by = plan.profile_apply(v, out=u2, reps=3)
+    assert torch.equal(u, u2)
+    active = [0, 2, 4] if len(shape) == 2 else [0, 1, 2, 3, 4]
+    for i in range(5):
+        if i in active:
+            assert ms[i] > 0 and by[i] > 0
+        else:
+            assert ms[i] == 0 and by[i] == 0
+
+
 def test_solve_fp64_bump64(orc, hp, dev):
     w = inputs.workload("2d_64_bump")
     _print_case("solve_bump64")
