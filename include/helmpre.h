@@ -56,7 +56,7 @@ typedef struct {
 
 /* Absorbing layer by a complex wave speed gamma = c (1 - i zeta)
  * (Eqn. Complex_wave_speed).  The medium must satisfy c = c0 wherever
- * zeta > 0 (Section 4.3); zeta >= 0 on the host, n[0]*...*n[d-1] values. */
+ * zeta > 0 (Section 4.4); zeta >= 0 on the host, n[0]*...*n[d-1] values. */
 typedef struct {
   const double* zeta;   /* host, may be NULL (no layer)        */
   double c0;            /* background speed c_o (> 0)          */
@@ -66,7 +66,7 @@ typedef struct {
  *   m_real     M: real-axis interpolation nodes (Section 4.1).  1 gives the
  *              one-node preconditioner Q_1 of Eqn. OneInterpPoint (node c0,
  *              no layer nodes).  With a layer c0 is always a node and M >= 3.
- *   m_layer    M~: layer nodes zeta_1..zeta_M~ (Section 4.3), >= 1 when a layer is given.
+ *   m_layer    M~: layer nodes zeta_1..zeta_M~ (Section 4.4), >= 1 when a layer is given.
  *   nodes_real optional explicit increasing real nodes (host, m_real values)
  *   nodes_zeta optional explicit increasing layer nodes (host, m_layer values > 0)
  *   a_nodes    optional damping a(c_m) at the real nodes (host, m_real values)
@@ -120,9 +120,10 @@ typedef struct {
   int precision;
 } hp_plan_info;
 
-/* Build a plan: validate the media, place the nodes, and compute in FP64 on the
- * host the per-point interpolation records, the stencil coefficients and the
- * symbol tables, then upload them (Section 4, Eqn. 021, 403/405; Section 5).
+/* Build a plan: upload and validate the media, place the nodes, and compute in
+ * FP64 on the device the per-point interpolation records, the stencil
+ * coefficients, the symbol tables and the node masks (Section 4, Eqn. 021,
+ * 403/405; Section 5).  Blocks until the plan is ready.
  *   c      host, wave speed > 0 at every point
  *   a      host damping >= 0 at every point, or NULL (a = 0)
  *   layer  NULL: no absorbing layer
@@ -147,7 +148,7 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info);
 hp_status hp_apply_precond(hp_plan p, const void* v, void* u, int nrhs, void* stream);
 
 /* y = P_N u: second-order centred differences of Eqn. 003 with periodic
- * boundaries, gamma^2 in place of c^2 (Section 4.3, Section 5).  Same dtypes as
+ * boundaries, gamma^2 in place of c^2 (Section 4.4, Section 5).  Same dtypes as
  * apply.  y must not alias u. */
 hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
 

@@ -175,12 +175,12 @@ int or_fftnd(int dim, const int* n, cx* x, int inverse) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Interpolation nodes (Section 4.1 and Section 4.3).                  */
+/* Interpolation nodes (Section 4.1 and Section 4.4).                  */
 /* ------------------------------------------------------------------ */
 
 /* Real nodes: c_1 = c_min < ... < c_M = c_max.  Without a layer they are
  * equidistant (the setting of Lemma 3).  With a layer c_o must be a node
- * (Section 4.3); the reading used here splits the nodes into two equidistant
+ * (Section 4.4); the reading used here splits the nodes into two equidistant
  * runs on [c_min, c_o] and [c_o, c_max], with s = round-half-down of
  * (c_o - c_min)/(c_max - c_min) * (M - 1) intervals below c_o, kept in
  * [1, M-2] when c_o is strictly inside (M is raised to 3 if needed).

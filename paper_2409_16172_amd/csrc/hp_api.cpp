@@ -92,7 +92,7 @@ hp_status record(hipError_t e, const char* where, int line) {
   } while (0)
 
 // Real interpolation nodes (Section 4.1); with an absorbing layer the
-// background speed c0 must be one of them (Section 4.3).  Reading: two
+// background speed c0 must be one of them (Section 4.4).  Reading: two
 // equidistant runs on [cmin, c0] and [c0, cmax]; the number of intervals below
 // c0 is the nearest integer (ties downwards) to (c0-cmin)/(cmax-cmin)*(M-1),
 // kept in [1, M-2] when c0 is strictly inside (M raised to 3 if smaller).
@@ -362,7 +362,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   for (int i = 0; i <= P->Mt; ++i) T.znode[i] = P->znode[i];
 
   // per-point records and stencil coefficients {gamma^2, beta} (Section 5 with
-  // the complex speed of Section 4.3), in FP64 on the device
+  // the complex speed of Section 4.4), in FP64 on the device
   double sih2 = 0;
   for (int d = 0; d < P->dim; ++d) {
     const double h = P->len[d] / P->n[d];

@@ -199,11 +199,16 @@ __host__ __device__ constexpr int lds_elems(int n) { return lds_elems_e<elems_pe
 // contains workgroup barriers when N > E, unless CONTIG says that the T threads
 // of a transform are consecutive, in which case transforms of at most 64
 // threads synchronise within their wavefront only).
+// fft_e takes the elements per thread E explicitly (LDS: lds_elems_e<E>(N) per transform).
+template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1>
+__device__ __forceinline__ void fft_e(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
+  constexpr int T = N / E;
+  Stage<R, N, E, DIR, 1, CONTIG && (T <= 64), ILV>::run(x, lds, j, tw);
+}
 template <typename R, int N, int DIR, bool CONTIG = false, int ILV = 1>
 __device__ __forceinline__ void fft(cpx<R> (&x)[elems_per_thread<R>(N)], cpx<R>* lds, int j,
                                     const cpx<R>* __restrict__ tw) {
-  constexpr int T = N / elems_per_thread<R>(N);
-  Stage<R, N, elems_per_thread<R>(N), DIR, 1, CONTIG && (T <= 64), ILV>::run(x, lds, j, tw);
+  fft_e<R, N, elems_per_thread<R>(N), DIR, CONTIG, ILV>(x, lds, j, tw);
 }
 
 }  // namespace hp

@@ -11,6 +11,8 @@
 //           non-zero piecewise-linear weights of each point  K fields -> u
 // d = 3 adds the forward and inverse transforms along the middle axis as plain
 // strided passes (A' and M) between A/B and B/C.
+#include <type_traits>
+
 #include "hp_internal.h"
 
 namespace hp {
@@ -44,15 +46,15 @@ using CombCfg = RowCfg<R, N, HP_ROWC_THREADS>;
 // resident through K transforms, uses the smallest workgroup (>= 256 threads)
 // that still reads and writes 32-byte row segments, so that more independent
 // workgroups share a CU.
-template <typename R, int N, int MAXT, int SEG = 64>
+template <typename R, int N, int MAXT, int SEG = 64, int EE = elems_per_thread<R>(N)>
 struct ColCfg {
-  static constexpr int E = elems_per_thread<R>(N);
+  static constexpr int E = EE;
   static constexpr int T = N / E;
   static constexpr int TC0 = SEG / (2 * (int)sizeof(R));
   static constexpr int THR0 = TC0 * T < 256 ? 256 : TC0 * T;
   static constexpr int THREADS = THR0 > MAXT ? MAXT : THR0;
   static constexpr int TC = THREADS / T;
-  static constexpr int LDS = (N > E) ? TC * lds_elems<R>(N) : 1;
+  static constexpr int LDS = (N > E) ? TC * lds_elems_e<E>(N) : 1;
 };
 #ifndef HP_SYM_MAXT
 #define HP_SYM_MAXT 512
@@ -60,11 +62,28 @@ struct ColCfg {
 #ifndef HP_SYM_SEG
 #define HP_SYM_SEG 32
 #endif
+// elements per thread of the symbol pass (it keeps the forward spectrum and the
+// symbol argument in registers besides the transform, so it may use fewer)
+#ifndef HP_SYM_E64
+#define HP_SYM_E64 HP_E64
+#endif
+#ifndef HP_SYM_E32
+#define HP_SYM_E32 HP_E32
+#endif
+template <typename R>
+constexpr int sym_elems(int n) {
+  return n < (sizeof(R) == 8 ? HP_SYM_E64 : HP_SYM_E32) ? n : (sizeof(R) == 8 ? HP_SYM_E64 : HP_SYM_E32);
+}
+template <typename R, int N>
+using SymCfg = ColCfg<R, N, HP_SYM_MAXT, HP_SYM_SEG, sym_elems<R>(N)>;
+template <typename R, int N, int MODE>
+using ColsCfg = std::conditional_t<MODE == 1, SymCfg<R, N>, ColCfg<R, N, 1024>>;
+#ifndef HP_SYM_TW_RELOAD
+#define HP_SYM_TW_RELOAD 0
+#endif
 #ifndef HP_XCD_REMAP
 #define HP_XCD_REMAP 1
 #endif
-template <int MODE>
-constexpr int cols_max_threads() { return MODE == 1 ? HP_SYM_MAXT : 1024; }
 
 // ---------------------------------------------------------------- pass A
 template <typename R, typename TI, int N>
@@ -131,14 +150,21 @@ __device__ __forceinline__ void symbol_mul(const cpx<R> (&vh)[E], cpx<R> (&x)[E]
   }
 }
 
+#ifndef HP_SYM_WAVES
+#define HP_SYM_WAVES 0
+#endif
 template <typename R, typename TI, int N, int DIR, int MODE>
-__global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>(), MODE == 1 ? HP_SYM_SEG : 64>::THREADS)) void k_cols(
+__global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS))
+#if HP_SYM_WAVES
+__attribute__((amdgpu_waves_per_eu(HP_SYM_WAVES, HP_SYM_WAVES)))
+#endif
+void k_cols(
     const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
     size_t out_rs, size_t in_fs, size_t out_fs, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip, const double* __restrict__ lam_ax, const double* __restrict__ lam_in,
     const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
     const uint8_t* __restrict__ slab_need) {
-  using C = ColCfg<R, N, cols_max_threads<MODE>(), MODE == 1 ? HP_SYM_SEG : 64>;
+  using C = ColsCfg<R, N, MODE>;
   __shared__ cpx<R> lds[C::LDS];
   const int z = blockIdx.z;
   const int rhs = (MODE == 0) ? z / nfields : z;
@@ -171,7 +197,7 @@ __global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>(), MODE == 1 ?
       for (int s = 0; s < C::E; ++s) dst[(size_t)(j + C::T * s) * S] = x[s];
     }
   } else {
-    fft<R, N, -1, false, C::TC>(x, lg, j, tw);
+    fft_e<R, N, C::E, -1, false, C::TC>(x, lg, j, tw);
     cpx<R> vh[C::E];
     double lam[C::E];
     const double lc = act ? lam_in[c] : 0.0;
@@ -182,8 +208,14 @@ __global__ __launch_bounds__((ColCfg<R, N, cols_max_threads<MODE>(), MODE == 1 ?
     }
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
     for (int n = 0; n < K; ++n) {
+      const cpx<R>* twn = tw;
+#if HP_SYM_TW_RELOAD
+      // reload the (cached) twiddles for every node instead of keeping all of
+      // them live across the node loop: fewer registers, more waves per SIMD
+      asm volatile("" : "+s"(twn));
+#endif
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
-      fft<R, N, +1, false, C::TC>(x, lg, j, tw);
+      fft_e<R, N, C::E, +1, false, C::TC>(x, lg, j, twn);
       // bit s: some point of axis-0 index j + T*s uses node n (else the row is never read)
       const uint32_t m = act ? (uint32_t)store_mask[n * C::T + j] : 0u;
 #pragma unroll
@@ -351,8 +383,8 @@ struct ColsL {
   template <int N>
   struct F {
     static hipError_t run(const ColsArgs& a, hipStream_t st) {
-      using C0 = ColCfg<R, N, cols_max_threads<0>()>;
-      using C1 = ColCfg<R, N, cols_max_threads<1>(), HP_SYM_SEG>;
+      using C0 = ColsCfg<R, N, 0>;
+      using C1 = ColsCfg<R, N, 1>;
       if constexpr (sizeof(R) == 8 && N > 2048) {
         return hipErrorInvalidValue;   // the FP64 column tile would not fit in LDS
       } else {
@@ -433,16 +465,16 @@ int group_rows(int n) {
 template <typename R>
 int sym_line_threads(int n) {
   switch (n) {
-    case 8: return ColCfg<R, 8, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 16: return ColCfg<R, 16, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 32: return ColCfg<R, 32, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 64: return ColCfg<R, 64, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 128: return ColCfg<R, 128, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 256: return ColCfg<R, 256, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 512: return ColCfg<R, 512, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 1024: return ColCfg<R, 1024, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 2048: return ColCfg<R, 2048, cols_max_threads<1>(), HP_SYM_SEG>::T;
-    case 4096: return ColCfg<R, 4096, cols_max_threads<1>(), HP_SYM_SEG>::T;
+    case 8: return SymCfg<R, 8>::T;
+    case 16: return SymCfg<R, 16>::T;
+    case 32: return SymCfg<R, 32>::T;
+    case 64: return SymCfg<R, 64>::T;
+    case 128: return SymCfg<R, 128>::T;
+    case 256: return SymCfg<R, 256>::T;
+    case 512: return SymCfg<R, 512>::T;
+    case 1024: return SymCfg<R, 1024>::T;
+    case 2048: return SymCfg<R, 2048>::T;
+    case 4096: return SymCfg<R, 4096>::T;
     default: return 1;
   }
 }

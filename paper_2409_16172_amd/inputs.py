@@ -56,7 +56,7 @@ def frame_layer(shape, width: int, zeta_max: float = 0.133) -> np.ndarray:
 
 
 def blend_to_background(c: np.ndarray, width: int, c0: float = 1.0, taper: int = 8) -> np.ndarray:
-    """Force c = c0 inside the layer (the layer assumption of Section 4.3) and
+    """Force c = c0 inside the layer (the layer assumption of Section 4.4) and
     blend smoothly back to c over `taper` cells just inside the layer's inner
     edge with a cosine ramp."""
     if width <= 0:

@@ -1,7 +1,7 @@
 """Pins of the oracle's interpolated preconditioner Q_M (Eqn. 103/105, 403/405).
 
 T3  weights: a node is reproduced exactly, the weights sum to one and
-    reproduce the complex speed linearly (piecewise-linear hats, Section 4.1/4.3).
+    reproduce the complex speed linearly (piecewise-linear hats, Section 4.1/4.4).
 T4  a single Fourier mode is mapped to [sum_n w_n(x) q_n(k)] times the mode
     (Eqn. 403 applied to one mode); a non-square grid catches a swapped axis.
 T5  media that only take node values: Q_M equals the exact operator Q of
@@ -9,7 +9,7 @@ T5  media that only take node values: Q_M equals the exact operator Q of
 T6  the interpolation error decays like h_M^2 (Lemma 3, Theorem 2), with the
     pointwise bound h^2/8 max |d^2 q/dc^2| built from the paper's printed
     second derivative.
-    The printed first and second c-derivatives of q_{-2} (Section 4.2) match
+    The printed first and second c-derivatives of q_{-2} (Section 4.3) match
     finite differences of the oracle's symbol.
 Q_1 special case (Eqn. OneInterpPoint) and the homogeneous case: with the
 stencil's own symbol Q_1 inverts P_N exactly (one-term expansion, Section 3).
@@ -73,7 +73,7 @@ def test_weights_reproduce_nodes_and_sum_to_one(orc):
 
 
 def test_node_placement_contains_background(orc):
-    """With a layer c_o is a node (Section 4.3) and the end nodes are c_min, c_max (Section 4.1)."""
+    """With a layer c_o is a node (Section 4.4) and the end nodes are c_min, c_max (Section 4.1)."""
     shape = (16, 16)
     c = np.full(shape, 1.0)
     c[5:9, 5:9] = 1.3
@@ -156,7 +156,7 @@ def test_interpolation_error_rate(orc):
 
 
 def _d2q_paper(c, omega, a, xi2):
-    """Second c-derivative of q_{-2} as printed in Section 4.2."""
+    """Second c-derivative of q_{-2} as printed in Section 4.3."""
     p = omega ** 2 + 1j * omega * a - c ** 2 * xi2
     return (2 * xi2 * p + 8 * c ** 2 * xi2 ** 2) / p ** 3
 
