@@ -602,21 +602,39 @@ __device__ __forceinline__ void block_reduce_write(cpx<double> (&acc)[CNT], int 
 __device__ __forceinline__ double cabs2(cpx<double> a) { return a.re * a.re + a.im * a.im; }
 
 // Sum the kRedBlocks block partials of `cnt` slots of right-hand side `rhs`
-// into sums[] in a fixed order (wave w handles slots w, w + 4, ...).
+// into sums[] in a fixed order (wave w handles slots w, w + nw, ...; two slots
+// per round, every partial load of a round issued before the first add).
+static_assert(kRedBlocks % 64 == 0, "partials per slot must fill whole wavefronts");
 __device__ void reduce_slots(const cpx<double>* __restrict__ part, int rhs, int cnt, cpx<double>* sums) {
+  constexpr int kLoads = kRedBlocks / 64;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks;
-  for (int s = wv; s < cnt; s += nw) {
-    double re = 0.0, im = 0.0;
-    const cpx<double>* ps = pr + (size_t)s * kRedBlocks;
-#pragma unroll 4
-    for (int b = lane; b < kRedBlocks; b += 64) {
-      re += ps[b].re;
-      im += ps[b].im;
+  const cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks + lane;
+  for (int s0 = wv; s0 < cnt; s0 += 2 * nw) {
+    const int s1 = s0 + nw;
+    const cpx<double>* p0 = pr + (size_t)s0 * kRedBlocks;
+    const cpx<double>* p1 = pr + (size_t)(s1 < cnt ? s1 : s0) * kRedBlocks;
+    cpx<double> x0[kLoads], x1[kLoads];
+#pragma unroll
+    for (int b = 0; b < kLoads; ++b) {
+      x0[b] = p0[64 * b];
+      x1[b] = p1[64 * b];
     }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) sums[s] = {re, im};
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < kLoads; ++b) {
+      r0 += x0[b].re;
+      i0 += x0[b].im;
+      r1 += x1[b].re;
+      i1 += x1[b].im;
+    }
+    r0 = wave_sum(r0);
+    i0 = wave_sum(i0);
+    r1 = wave_sum(r1);
+    i1 = wave_sum(i1);
+    if (lane == 0) {
+      sums[s0] = {r0, i0};
+      if (s1 < cnt) sums[s1] = {r1, i1};
+    }
   }
   __syncthreads();
 }
@@ -780,7 +798,6 @@ __global__ __launch_bounds__(256) void k_scale_v0(cpx<double>* V, size_t npts, s
 // Arnoldi step j, one reduction over v_0..v_{j-1} (slots 0..j-1), u_j (slot j)
 // and w = A u_j (slot j+1).  Partial-sum slots: [0, j) a = V^H u_j,
 // [j, 2j) b = V^H w, 2j ||u_j||^2, 2j+1 u_j^H w, 2j+2 ||w||^2.
-constexpr int kDualChunk = 8;
 
 __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, int j, int restart,
                                  int* skip_step, int* host_stop) {
@@ -794,10 +811,11 @@ __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, in
   reduce_slots(part, rhs, 2 * j + 3, sums);   // ends with a barrier
   const cpx<double>* a = sums;
   const cpx<double>* bv = sums + j;
-  if (threadIdx.x == 0) {
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x < 64) {
     // v_j = (u_j - V a) / sigma; column j-1 = (hprov_{j-1} + a, sigma)
-    double aa = 0.0;
-    for (int k = 0; k < j; ++k) aa += cabs2(a[k]);
+    const double aa = wave_sum(lane < j ? cabs2(a[lane]) : 0.0);
+    if (threadIdx.x != 0) goto first_done;
     const double s2 = sums[2 * j].re - aa;
     const double sigma = s2 > 0.0 ? sqrt(s2) : 0.0;
     sh_sigma = sigma;
@@ -814,21 +832,23 @@ __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, in
       }
     }
   }
+first_done:
   __syncthreads();
   if (sh_break) return;
   // z = Hraw[0..j][0..j-1] a, the expansion of A V a in v_0..v_j
   for (int k = threadIdx.x; k <= j; k += blockDim.x) {
     cpx<double> acc = {0.0, 0.0};
+#pragma unroll 8
     for (int i = k > 0 ? k - 1 : 0; i < j; ++i) acc = cadd(acc, cmul(S.Hraw[(size_t)i * (kMaxRestart + 1) + k], a[i]));
     zz[k] = acc;
   }
-  __syncthreads();
   const double sigma = sh_sigma, isg = 1.0 / sigma;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     // p_j = v_j^H w
-    cpx<double> ab = {0.0, 0.0};
-    for (int k = 0; k < j; ++k) ab = cadd(ab, {a[k].re * bv[k].re + a[k].im * bv[k].im, a[k].re * bv[k].im - a[k].im * bv[k].re});
-    raw[j] = cscale(csub(sums[2 * j + 1], ab), isg);
+    cpx<double> t = {0.0, 0.0};
+    if (lane < j) t = {a[lane].re * bv[lane].re + a[lane].im * bv[lane].im, a[lane].re * bv[lane].im - a[lane].im * bv[lane].re};
+    const cpx<double> ab = {wave_sum(t.re), wave_sum(t.im)};
+    if (lane == 0) raw[j] = cscale(csub(sums[2 * j + 1], ab), isg);
   }
   __syncthreads();
   // hprov_j = [V, v_j]^H A v_j = (p - z) / sigma (parallel over k)
@@ -847,16 +867,20 @@ __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, in
       S.av[k] = a[k];
     }
   }
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x >= 64) return;
+  double zp = 0.0, z2 = 0.0, h2 = 0.0;
+  if (lane <= j) {
+    const cpx<double> pk = lane < j ? bv[lane] : raw[j];
+    zp = zz[lane].re * pk.re + zz[lane].im * pk.im;
+    z2 = cabs2(zz[lane]);
+    h2 = cabs2(hp[lane]);
+  }
+  zp = wave_sum(zp);
+  z2 = wave_sum(z2);
+  h2 = wave_sum(h2);
+  if (lane != 0) return;
   S.cu = cu;
   S.inv_sigma = isg;
-  double zp = 0.0, z2 = 0.0, h2 = 0.0;
-  for (int k = 0; k <= j; ++k) {
-    const cpx<double> pk = k < j ? bv[k] : raw[j];
-    zp += zz[k].re * pk.re + zz[k].im * pk.im;
-    z2 += cabs2(zz[k]);
-    h2 += cabs2(hp[k]);
-  }
   const double av2 = (sums[2 * j + 2].re - 2.0 * zp + z2) * isg * isg;   // ||A v_j||^2
   const double r2 = av2 - h2;
   const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
@@ -883,51 +907,106 @@ __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, in
   }
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_arnoldi_dots(const cpx<double>* __restrict__ V, size_t npts,
-                                                               size_t vrs, cpx<double>* __restrict__ part,
-                                                               const int* __restrict__ skip_step, int j) {
+// Block b of a right-hand side owns the contiguous point range
+// [b*range, (b+1)*range), range = ceil(npts / kRedBlocks), and walks it in tiles
+// of kDotsTile points: u_j and w of the tile are staged in LDS once (their norms
+// and u_j^H w accumulated on the way), then wave q streams the basis vectors
+// q, q + NW, q + 2 NW, ... over the tile, kDotsBatch loads in flight per lane,
+// accumulating V_k^H u_j and V_k^H w in registers.  Every basis element is read
+// once and every slot is owned by one wave (no block reduction for them).
+constexpr int kDotsTile = 1024;
+constexpr int kDotsBatch = 8;
+constexpr int kDotsSlots = 8;   // basis vectors per wave: j <= NW * kDotsSlots
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __restrict__ V, size_t npts,
+                                                          size_t vrs, cpx<double>* __restrict__ part,
+                                                          const int* __restrict__ skip_step, int j) {
+  __shared__ cpx<double> su[kDotsTile], sw[kDotsTile];
+  __shared__ double red[NW][6];
   const int rhs = blockIdx.y;
   if (skip_step[rhs]) return;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const cpx<double>* Vr = V + (size_t)rhs * vrs;
   const cpx<double>* U = Vr + (size_t)j * npts;
   const cpx<double>* W = Vr + (size_t)(j + 1) * npts;
   cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x;
-  const size_t stride = (size_t)kRedBlocks * kRedThreads;
-  {
-    cpx<double> sc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
-      const cpx<double> u = U[i], w = W[i];
-      sc[0].re += u.re * u.re + u.im * u.im;
-      sc[1].re += u.re * w.re + u.im * w.im;     // conj(u) w
-      sc[1].im += u.re * w.im - u.im * w.re;
-      sc[2].re += w.re * w.re + w.im * w.im;
+  const size_t range = (npts + kRedBlocks - 1) / kRedBlocks;
+  const size_t r0 = (size_t)blockIdx.x * range;
+  const size_t r1 = r0 + range < npts ? r0 + range : npts;
+  cpx<double> acc[2 * kDotsSlots];
+#pragma unroll
+  for (int v = 0; v < 2 * kDotsSlots; ++v) acc[v] = {0.0, 0.0};
+  double uu = 0.0, uwr = 0.0, uwi = 0.0, ww = 0.0;
+  for (size_t t0 = r0; t0 < r1; t0 += kDotsTile) {
+    const int n = (int)(r1 - t0 < (size_t)kDotsTile ? r1 - t0 : kDotsTile);
+    for (int i = threadIdx.x; i < n; i += NW * 64) {
+      const cpx<double> u = U[t0 + i], w = W[t0 + i];
+      su[i] = u;
+      sw[i] = w;
+      uu += u.re * u.re + u.im * u.im;
+      uwr += u.re * w.re + u.im * w.im;     // conj(u) w
+      uwi += u.re * w.im - u.im * w.re;
+      ww += w.re * w.re + w.im * w.im;
     }
-    block_reduce_write<3>(sc, 3, pr + (size_t)(2 * j) * kRedBlocks);
-  }
-  for (int c0 = 0; c0 < j; c0 += kDualChunk) {
-    const int cnt = j - c0 < kDualChunk ? j - c0 : kDualChunk;
-    cpx<double> acc[2 * kDualChunk];
+    __syncthreads();
 #pragma unroll
-    for (int v = 0; v < 2 * kDualChunk; ++v) acc[v] = {0.0, 0.0};
-    for (size_t i = (size_t)blockIdx.x * kRedThreads + threadIdx.x; i < npts; i += stride) {
-      const cpx<double> u = U[i], w = W[i];
+    for (int sl = 0; sl < kDotsSlots; ++sl) {
+      const int k = q + NW * sl;
+      if (k >= j) break;
+      const cpx<double>* vk = Vr + (size_t)k * npts + t0;
+      for (int p0 = 0; p0 < n; p0 += 64 * kDotsBatch) {
+        cpx<double> x[kDotsBatch];
+        if (p0 + 64 * kDotsBatch <= n) {
 #pragma unroll
-      for (int v = 0; v < kDualChunk; ++v) {
-        if (v < cnt) {
-          const cpx<double> x = Vr[(size_t)(c0 + v) * npts + i];
-          acc[v].re += x.re * u.re + x.im * u.im;                  // conj(v) u
-          acc[v].im += x.re * u.im - x.im * u.re;
-          acc[kDualChunk + v].re += x.re * w.re + x.im * w.im;     // conj(v) w
-          acc[kDualChunk + v].im += x.re * w.im - x.im * w.re;
+          for (int b = 0; b < kDotsBatch; ++b) x[b] = vk[p0 + lane + 64 * b];
+        } else {
+#pragma unroll
+          for (int b = 0; b < kDotsBatch; ++b) {
+            const int p = p0 + lane + 64 * b;
+            x[b] = p < n ? vk[p] : cpx<double>{0.0, 0.0};
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < kDotsBatch; ++b) {
+          int p = p0 + lane + 64 * b;
+          p = p < n ? p : 0;   // x[b] is zero there
+          const cpx<double> u = su[p], w = sw[p];
+          acc[2 * sl].re += x[b].re * u.re + x[b].im * u.im;     // conj(v) u
+          acc[2 * sl].im += x[b].re * u.im - x[b].im * u.re;
+          acc[2 * sl + 1].re += x[b].re * w.re + x[b].im * w.im; // conj(v) w
+          acc[2 * sl + 1].im += x[b].re * w.im - x[b].im * w.re;
         }
       }
     }
-    // slots: a at c0.., b at j + c0..
-    cpx<double> aa[kDualChunk], bb[kDualChunk];
+    __syncthreads();
+  }
+  // slots: a = V^H u_j at [0, j), b = V^H w at [j, 2j), then ||u_j||^2, u_j^H w, ||w||^2
 #pragma unroll
-    for (int v = 0; v < kDualChunk; ++v) { aa[v] = acc[v]; bb[v] = acc[kDualChunk + v]; }
-    block_reduce_write<kDualChunk>(aa, cnt, pr + (size_t)c0 * kRedBlocks);
-    block_reduce_write<kDualChunk>(bb, cnt, pr + (size_t)(j + c0) * kRedBlocks);
+  for (int sl = 0; sl < kDotsSlots; ++sl) {
+    const int k = q + NW * sl;
+    if (k >= j) break;
+    const double ar = wave_sum(acc[2 * sl].re), ai = wave_sum(acc[2 * sl].im);
+    const double br = wave_sum(acc[2 * sl + 1].re), bi = wave_sum(acc[2 * sl + 1].im);
+    if (lane == 0) {
+      pr[(size_t)k * kRedBlocks] = {ar, ai};
+      pr[(size_t)(j + k) * kRedBlocks] = {br, bi};
+    }
+  }
+  uu = wave_sum(uu);
+  uwr = wave_sum(uwr);
+  uwi = wave_sum(uwi);
+  ww = wave_sum(ww);
+  if (lane == 0) {
+    red[q][0] = uu; red[q][1] = uwr; red[q][2] = uwi; red[q][3] = ww;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int w = 0; w < NW; ++w) { s0 += red[w][0]; s1 += red[w][1]; s2 += red[w][2]; s3 += red[w][3]; }
+    pr[(size_t)(2 * j) * kRedBlocks] = {s0, 0.0};
+    pr[(size_t)(2 * j + 1) * kRedBlocks] = {s1, s2};
+    pr[(size_t)(2 * j + 2) * kRedBlocks] = {s3, 0.0};
   }
 }
 
@@ -940,6 +1019,20 @@ __global__ __launch_bounds__(1024) void k_arnoldi_fin(const cpx<double>* __restr
 
 // slot j <- v_j = (u_j - V a) / sigma ; slot j+1 <- u_{j+1} = w / sigma - V cv - cu u_j.
 // Runs for right-hand sides still in the cycle, and for the step that ended it.
+// Each thread updates kUpdPts points (256 apart) per iteration and reads the
+// basis in chunks of kUpdChunk vectors with every load issued: past v_{j-1} the
+// index is clamped and the coefficient (zero in LDS) cancels the term.
+constexpr int kUpdPts = 4;
+constexpr int kUpdChunk = 4;
+
+__device__ __forceinline__ void update_point(cpx<double>* U, cpx<double>* W, size_t i, cpx<double> sa,
+                                             cpx<double> sc, double isg, cpx<double> cu) {
+  const cpx<double> u = U[i], w = W[i];
+  U[i] = cscale(csub(u, sa), isg);
+  const cpx<double> cuu = cmul(cu, u);
+  W[i] = {w.re * isg - sc.re - cuu.re, w.im * isg - sc.im - cuu.im};
+}
+
 __global__ __launch_bounds__(256) void k_arnoldi_update(cpx<double>* __restrict__ V, size_t npts, size_t vrs,
                                                         const KState* __restrict__ state,
                                                         const int* __restrict__ skip_step, int j) {
@@ -957,25 +1050,50 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(cpx<double>* __restrict_
   cpx<double>* Vr = V + (size_t)rhs * vrs;
   cpx<double>* U = Vr + (size_t)j * npts;
   cpx<double>* W = Vr + (size_t)(j + 1) * npts;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < npts; i += (size_t)gridDim.x * 256) {
-    const cpx<double> u = U[i], w = W[i];
-    cpx<double> sa = {0.0, 0.0}, sc = {0.0, 0.0};
-    for (int v0 = 0; v0 < j; v0 += 8) {
-      cpx<double> x[8];
+  constexpr size_t span = 256 * kUpdPts;
+  for (size_t base = (size_t)blockIdx.x * span; base < npts; base += (size_t)gridDim.x * span) {
+    const size_t i0 = base + threadIdx.x;
+    if (base + span <= npts) {
+      cpx<double> sa[kUpdPts], sc[kUpdPts];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) x[t] = (v0 + t < j) ? Vr[(size_t)(v0 + t) * npts + i] : cpx<double>{0.0, 0.0};
+      for (int p = 0; p < kUpdPts; ++p) { sa[p] = {0.0, 0.0}; sc[p] = {0.0, 0.0}; }
+      for (int v0 = 0; v0 < j; v0 += kUpdChunk) {
+        cpx<double> x[kUpdChunk][kUpdPts];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const cpx<double> p = ca[v0 + t], q = cc[v0 + t];
-        sa.re += p.re * x[t].re - p.im * x[t].im;
-        sa.im += p.re * x[t].im + p.im * x[t].re;
-        sc.re += q.re * x[t].re - q.im * x[t].im;
-        sc.im += q.re * x[t].im + q.im * x[t].re;
+        for (int t = 0; t < kUpdChunk; ++t) {
+          const int k = v0 + t < j ? v0 + t : j - 1;
+#pragma unroll
+          for (int p = 0; p < kUpdPts; ++p) x[t][p] = Vr[(size_t)k * npts + i0 + 256 * p];
+        }
+#pragma unroll
+        for (int t = 0; t < kUpdChunk; ++t) {
+          const cpx<double> a = ca[v0 + t], c = cc[v0 + t];
+#pragma unroll
+          for (int p = 0; p < kUpdPts; ++p) {
+            sa[p].re += a.re * x[t][p].re - a.im * x[t][p].im;
+            sa[p].im += a.re * x[t][p].im + a.im * x[t][p].re;
+            sc[p].re += c.re * x[t][p].re - c.im * x[t][p].im;
+            sc[p].im += c.re * x[t][p].im + c.im * x[t][p].re;
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < kUpdPts; ++p) update_point(U, W, i0 + 256 * p, sa[p], sc[p], isg, cu);
+    } else {
+      for (int p = 0; p < kUpdPts; ++p) {
+        const size_t i = i0 + 256 * p;
+        if (i >= npts) break;
+        cpx<double> sa = {0.0, 0.0}, sc = {0.0, 0.0};
+        for (int k = 0; k < j; ++k) {
+          const cpx<double> x = Vr[(size_t)k * npts + i], a = ca[k], c = cc[k];
+          sa.re += a.re * x.re - a.im * x.im;
+          sa.im += a.re * x.im + a.im * x.re;
+          sc.re += c.re * x.re - c.im * x.im;
+          sc.im += c.re * x.im + c.im * x.re;
+        }
+        update_point(U, W, i, sa, sc, isg, cu);
       }
     }
-    U[i] = cscale(csub(u, sa), isg);
-    const cpx<double> cuu = cmul(cu, u);
-    W[i] = {w.re * isg - sc.re - cuu.re, w.im * isg - sc.im - cuu.im};
   }
 }
 
@@ -1205,15 +1323,22 @@ hipError_t launch_scale_v0(const KrylovArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs,
-                     a.part, (const int*)a.skip_step, j);
+  if (j <= 4 * kDotsSlots)
+    hipLaunchKernelGGL(k_arnoldi_dots<4>, dim3(kRedBlocks, a.nrhs), dim3(4 * 64), 0, st, a.V, a.npts, a.vrs,
+                       a.part, (const int*)a.skip_step, j);
+  else if (j <= 8 * kDotsSlots)
+    hipLaunchKernelGGL(k_arnoldi_dots<8>, dim3(kRedBlocks, a.nrhs), dim3(8 * 64), 0, st, a.V, a.npts, a.vrs,
+                       a.part, (const int*)a.skip_step, j);
+  else
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(1024), 0, st, (const cpx<double>*)a.part, a.skip_step,
                      a.state, j, a.restart, a.host_stop);
   return hipGetLastError();
 }
 
 hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_update, dim3(stream_blocks(a.npts), a.nrhs), dim3(256), 0, st, a.V, a.npts, a.vrs,
+  const size_t ub = (a.npts + 256 * kUpdPts - 1) / (256 * kUpdPts);
+  hipLaunchKernelGGL(k_arnoldi_update, dim3((unsigned)(ub < 1024 ? ub : 1024), a.nrhs), dim3(256), 0, st, a.V, a.npts, a.vrs,
                      a.state, a.skip_step, j);
   return hipGetLastError();
 }
