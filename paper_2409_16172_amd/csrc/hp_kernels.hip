@@ -78,9 +78,6 @@ template <typename R, int N>
 using SymCfg = ColCfg<R, N, HP_SYM_MAXT, HP_SYM_SEG, sym_elems<R>(N)>;
 template <typename R, int N, int MODE>
 using ColsCfg = std::conditional_t<MODE == 1, SymCfg<R, N>, ColCfg<R, N, 1024>>;
-#ifndef HP_SYM_TW_RELOAD
-#define HP_SYM_TW_RELOAD 0
-#endif
 #ifndef HP_XCD_REMAP
 #define HP_XCD_REMAP 1
 #endif
@@ -150,15 +147,8 @@ __device__ __forceinline__ void symbol_mul(const cpx<R> (&vh)[E], cpx<R> (&x)[E]
   }
 }
 
-#ifndef HP_SYM_WAVES
-#define HP_SYM_WAVES 0
-#endif
 template <typename R, typename TI, int N, int DIR, int MODE>
-__global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS))
-#if HP_SYM_WAVES
-__attribute__((amdgpu_waves_per_eu(HP_SYM_WAVES, HP_SYM_WAVES)))
-#endif
-void k_cols(
+__global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
     const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
     size_t out_rs, size_t in_fs, size_t out_fs, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip, const double* __restrict__ lam_ax, const double* __restrict__ lam_in,
@@ -185,6 +175,14 @@ void k_cols(
   const size_t obase = (size_t)blockIdx.y * N * S + c;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
   cpx<R>* lg = lds + g;   // the TC columns are interleaved in LDS
+  // Symbol pass: the store masks of all nodes are staged in LDS up front, so that
+  // the node loop issues no global load (waiting for one would also wait for the
+  // previous node's stores: vector memory operations retire in order).
+  __shared__ uint16_t smask[MODE == 1 ? kMaxNodes * C::T : 1];
+  if constexpr (MODE == 1) {
+    for (int i = threadIdx.x; i < K * C::T; i += C::THREADS) smask[i] = store_mask[i];
+    __syncthreads();
+  }
   cpx<R> x[C::E];
 #pragma unroll
   for (int s = 0; s < C::E; ++s)
@@ -208,16 +206,10 @@ void k_cols(
     }
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
     for (int n = 0; n < K; ++n) {
-      const cpx<R>* twn = tw;
-#if HP_SYM_TW_RELOAD
-      // reload the (cached) twiddles for every node instead of keeping all of
-      // them live across the node loop: fewer registers, more waves per SIMD
-      asm volatile("" : "+s"(twn));
-#endif
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
-      fft_e<R, N, C::E, +1, false, C::TC>(x, lg, j, twn);
+      fft_e<R, N, C::E, +1, false, C::TC>(x, lg, j, tw);
       // bit s: some point of axis-0 index j + T*s uses node n (else the row is never read)
-      const uint32_t m = act ? (uint32_t)store_mask[n * C::T + j] : 0u;
+      const uint32_t m = act ? (uint32_t)smask[n * C::T + j] : 0u;
 #pragma unroll
       for (int s = 0; s < C::E; ++s)
         if ((m >> s) & 1u) dst[(size_t)n * out_fs + (size_t)(j + C::T * s) * S] = x[s];
