@@ -134,37 +134,87 @@ static cx* twiddles(int n, int sign) {
     return w;
 }
 
-int or_fft1d(int n, cx* x, int sign) {
-    if (!is_pow2(n)) return OR_E_SHAPE;
-    cx* w = twiddles(n, sign);
-    if (!w) return OR_E_NOMEM;
-    fft1d_tab(n, x, w);
-    free(w);
+/* Lengths that are not powers of two (the grids N = 180 * 2^k etc. of Example 1,
+ * Section 5.1): recursive decimation in time on the smallest prime factor p of n.
+ * With m = n/p and X_r the m-point transform of x[r], x[r+p], x[r+2p], ...,
+ *     X[k + q m] = sum_{r<p} exp(sign 2 pi i r (k + q m) / n) X_r[k],
+ * for k < m, q < p.  `w` holds exp(sign 2 pi i j / ntop) for j < ntop, and a
+ * sub-transform of length n reads it with step ntop/n. */
+static int smallest_factor(int n) {
+    for (int f = 2; f * f <= n; ++f) if (n % f == 0) return f;
+    return n;
+}
+
+static int fft_mixed(int n, const cx* in, long is, cx* out, const cx* w, int ntop) {
+    if (n == 1) { out[0] = in[0]; return OR_OK; }
+    int p = smallest_factor(n), m = n / p;
+    for (int r = 0; r < p; ++r) {
+        int rc = fft_mixed(m, in + (long)r * is, is * p, out + (long)r * m, w, ntop);
+        if (rc) return rc;
+    }
+    cx* tmp = (cx*)malloc(sizeof(cx) * (size_t)n);
+    if (!tmp) return OR_E_NOMEM;
+    long step = ntop / n;
+    for (int k = 0; k < m; ++k)
+        for (int q = 0; q < p; ++q) {
+            cx acc = 0;
+            for (int r = 0; r < p; ++r) acc += w[(((long)r * (k + (long)q * m)) % n) * step] * out[(long)r * m + k];
+            tmp[k + (long)q * m] = acc;
+        }
+    memcpy(out, tmp, sizeof(cx) * (size_t)n);
+    free(tmp);
     return OR_OK;
+}
+
+/* One line of length n in place: radix-2 for powers of two, else mixed radix. */
+static int fft_line(int n, cx* x, int sign) {
+    if (is_pow2(n)) {
+        cx* w = twiddles(n, sign);
+        if (!w) return OR_E_NOMEM;
+        fft1d_tab(n, x, w);
+        free(w);
+        return OR_OK;
+    }
+    cx* w = (cx*)malloc(sizeof(cx) * (size_t)n);
+    cx* y = (cx*)malloc(sizeof(cx) * (size_t)n);
+    if (!w || !y) { free(w); free(y); return OR_E_NOMEM; }
+    for (int j = 0; j < n; ++j) {
+        double ang = sign * 2.0 * M_PI * (double)j / (double)n;
+        w[j] = cos(ang) + I * sin(ang);
+    }
+    int rc = fft_mixed(n, x, 1, y, w, n);
+    if (!rc) memcpy(x, y, sizeof(cx) * (size_t)n);
+    free(w);
+    free(y);
+    return rc;
+}
+
+int or_fft1d(int n, cx* x, int sign) {
+    if (n < 1) return OR_E_SHAPE;
+    return fft_line(n, x, sign);
 }
 
 /* d-dimensional transform, one axis at a time.  inverse != 0 applies the
  * 1/N^d factor so that the inverse undoes the forward transform. */
 int or_fftnd(int dim, const int* n, cx* x, int inverse) {
     long tot = 1;
-    for (int d = 0; d < dim; ++d) { if (!is_pow2(n[d])) return OR_E_SHAPE; tot *= n[d]; }
+    for (int d = 0; d < dim; ++d) { if (n[d] < 1) return OR_E_SHAPE; tot *= n[d]; }
     int sign = inverse ? +1 : -1;
     for (int ax = 0; ax < dim; ++ax) {
         int len = n[ax];
         long stride = 1;
         for (int d = ax + 1; d < dim; ++d) stride *= n[d];
         long outer = tot / (stride * len);
-        cx* w = twiddles(len, sign);
         cx* line = (cx*)malloc(sizeof(cx) * (size_t)len);
-        if (!w || !line) { free(w); free(line); return OR_E_NOMEM; }
+        if (!line) return OR_E_NOMEM;
         for (long o = 0; o < outer; ++o)
             for (long s = 0; s < stride; ++s) {
                 cx* base = x + o * stride * len + s;
                 for (int i = 0; i < len; ++i) line[i] = base[(long)i * stride];
-                fft1d_tab(len, line, w);
+                int rc = fft_line(len, line, sign);
+                if (rc) { free(line); return rc; }
                 for (int i = 0; i < len; ++i) base[(long)i * stride] = line[i];
             }
-        free(w);
         free(line);
     }
     if (inverse) {
@@ -293,7 +343,8 @@ void or_point_weights(const or_setup_t* s, double c0, double cval, double zval, 
 int or_setup(const or_problem* p, or_setup_t* s) {
     memset(s, 0, sizeof(*s));
     if (p->dim < 1 || p->dim > 3) return OR_E_SHAPE;
-    for (int d = 0; d < p->dim; ++d) if (!is_pow2(p->n[d]) || !(p->len[d] > 0)) return OR_E_SHAPE;
+    /* even lengths (the frequency range -N/2..N/2-1 of reading A3) */
+    for (int d = 0; d < p->dim; ++d) if (p->n[d] < 2 || p->n[d] % 2 || !(p->len[d] > 0)) return OR_E_SHAPE;
     long np = npoints(p);
     s->cmin = INFINITY; s->cmax = -INFINITY; s->zmax = 0.0;
     for (long i = 0; i < np; ++i) {

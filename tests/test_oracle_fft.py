@@ -1,6 +1,7 @@
 """Pins of the oracle's Fourier transforms (pin T1).
 
-The radix-2 FFT is checked against the O(N^2) DFT written out, against
+The radix-2 FFT (and the mixed-radix transform used for lengths such as the
+N = 180 * 2^k of Example 1) is checked against the O(N^2) DFT written out, against
 numpy's FFT (an independent library routine), and against identities of the
 DFT (inverse, Parseval, a single mode maps to a delta).  The sign convention
 is the one of the paper's Fourier transform (Eqn. FT): exp(-i x.xi) forward.
@@ -56,3 +57,28 @@ def test_nd_axis_order(orc):
     assert abs(X[1, 3] - n0 * n1) < 1e-10
     X[1, 3] = 0
     assert np.abs(X).max() < 1e-10
+
+
+@pytest.mark.parametrize("n", [3, 6, 7, 12, 15, 30, 45, 60, 90, 180])
+def test_mixed_radix_matches_naive_dft(orc, n):
+    rng = np.random.default_rng(100 + n)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for sign in (-1, +1):
+        assert rel(orc.fft1d(x, sign), orc.dft1d_naive(x, sign)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [360, 2400])
+def test_mixed_radix_matches_numpy(orc, n):
+    rng = np.random.default_rng(n + 3)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    assert rel(orc.fft1d(x, -1), np.fft.fft(x)) < 1e-13
+    assert rel(orc.fft1d(x, +1), np.fft.ifft(x) * n) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(12, 30), (20, 18, 10)])
+def test_mixed_radix_nd_matches_numpy(orc, shape):
+    rng = np.random.default_rng(sum(shape) + 7)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    X = orc.fftnd(x)
+    assert rel(X, np.fft.fftn(x)) < 1e-13
+    assert rel(orc.fftnd(X, inverse=True), x) < 1e-14

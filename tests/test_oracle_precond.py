@@ -89,7 +89,8 @@ def test_node_placement_contains_background(orc):
 
 
 # ---------------------------------------------------------------- T4
-@pytest.mark.parametrize("shape,k", [((16, 32), (3, -5)), ((32, 32), (0, 7)), ((8, 8, 16), (1, -2, 5))])
+@pytest.mark.parametrize("shape,k", [((16, 32), (3, -5)), ((32, 32), (0, 7)), ((8, 8, 16), (1, -2, 5)),
+                                     ((24, 36), (5, -11)), ((12, 20, 10), (-3, 4, 2))])
 def test_fourier_mode_closed_form(orc, shape, k):
     n = shape[0]
     xs = inputs.mesh(shape)
@@ -239,3 +240,11 @@ def test_error_paths(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.Problem(shape, 2 * np.pi, c, None, None, m_real=1).apply(np.ones(shape))
     assert e.value.code == orc.E_MEDIA
+
+
+def test_odd_lengths_rejected(orc):
+    """Grid lengths must be even (the frequency range -N/2..N/2-1 of the transform)."""
+    c = np.ones((15, 16))
+    with pytest.raises(orc.OracleError):
+        orc.Problem((15, 16), 10.0, c, None, None, m_real=2).setup()
+    orc.Problem((18, 16), 10.0, np.ones((18, 16)), None, None, m_real=2, a_floor=1.0).setup()
