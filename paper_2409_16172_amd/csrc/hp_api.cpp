@@ -209,7 +209,11 @@ hp_status check_grid(const hp_grid* g, int prec) {
   if (!g || (g->dim != 2 && g->dim != 3)) return HP_E_SHAPE;
   const int hi = prec == HP_FP64 ? 2048 : 4096;
   for (int d = 0; d < g->dim; ++d) {
-    if (!pow2_in(g->n[d], 8, hi)) return HP_E_SHAPE;
+    // powers of two, or even products of 2, 3 and 5 (mixed-radix lines held in LDS)
+    hp::GenPlan gp;
+    const int n = g->n[d];
+    const bool ok = pow2_in(n, 8, hi) || (n >= 8 && n % 2 == 0 && hp::make_gen_plan(n, &gp));
+    if (!ok) return HP_E_SHAPE;
     if (!(g->len[d] > 0) || !std::isfinite(g->len[d])) return HP_E_INVALID;
   }
   return HP_OK;
@@ -465,13 +469,18 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     for (int k = 0; k < P->K; ++k)
       if ((m >> k) & 1ull) { need[(size_t)k * n0 + i0] = 1; P->slabs_used += 1.0; }
   }
-  const int Tb = hp::symbol_pass_line_threads(P->real_kind(), n0);
-  const int Eb = n0 / Tb;
-  std::vector<uint16_t> smask((size_t)P->K * Tb, 0);
-  for (int k = 0; k < P->K; ++k)
-    for (int j = 0; j < Tb; ++j)
-      for (int e2 = 0; e2 < Eb; ++e2)
-        if (need[(size_t)k * n0 + j + (size_t)Tb * e2]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e2);
+  // store masks of the power-of-two symbol pass: bit e of thread j = axis-0 index
+  // j + Tb*e (mixed-radix lengths read `need` directly)
+  std::vector<uint16_t> smask(1, 0);
+  if (hp::is_pow2_len(n0)) {
+    const int Tb = hp::symbol_pass_line_threads(P->real_kind(), n0);
+    const int Eb = n0 / Tb;
+    smask.assign((size_t)P->K * Tb, 0);
+    for (int k = 0; k < P->K; ++k)
+      for (int j = 0; j < Tb; ++j)
+        for (int e2 = 0; e2 < Eb; ++e2)
+          if (need[(size_t)k * n0 + j + (size_t)Tb * e2]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e2);
+  }
 
   if ((e = upload(P->nodes, nc)) != hipSuccess) return failc(from_hip(e));
   if ((e = upload(P->grpmask, gm)) != hipSuccess) return failc(from_hip(e));
@@ -574,6 +583,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   b.lam_ax = (const double*)P->lam_ax.p; b.lam_in = (const double*)P->lam_in.p;
   b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
   b.store_mask = (const uint16_t*)P->storemask.p;
+  b.store_need = (const uint8_t*)P->slabneed.p;
   for (int r = 0; r < reps; ++r)
     if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
   if ((e = mark(3)) != hipSuccess) return e;

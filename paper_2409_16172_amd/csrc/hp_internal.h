@@ -51,6 +51,19 @@ constexpr int kRedThreads = HP_RED_THREADS;  // threads per block of the reducti
 constexpr int kRedBlocks = HP_RED_BLOCKS;    // blocks per right-hand side (fixed: deterministic sums)
 constexpr int kPartSlots = 2 * kMaxRestart + 4;
 
+// Mixed-radix lines (N = 2^a 3^b 5^c, not a power of two): stage radices in
+// order and the threads per line.  Each thread holds at most kGenE elements.
+constexpr int kGenE = 16;
+constexpr int kGenMaxStages = 24;
+constexpr int kGenMaxN = 4800;
+struct GenPlan {
+  int n, nst, nthr;
+  int radix[kGenMaxStages];
+};
+// Fills *gp for length n; false if n is not a product of 2, 3 and 5 within kGenMaxN.
+bool make_gen_plan(int n, GenPlan* gp);
+inline bool is_pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
 // ---- launchers (all enqueue on `st`, return the launch status) ----
 
 // Pass A: forward transform along the contiguous axis.
@@ -77,6 +90,7 @@ struct ColsArgs {
   double scale;
   const uint16_t* store_mask;   // mode 1: [K][T] bit s = axis-0 index j + T*s uses node n
   const uint8_t* slab_need;     // mode 0 over node fields: [K][outer] != 0 if the slab uses node n
+  const uint8_t* store_need;    // mode 1, mixed-radix lengths: [K][n] != 0 if axis-0 index p uses node n
 };
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st);
 

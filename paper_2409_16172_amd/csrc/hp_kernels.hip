@@ -325,6 +325,253 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
   }
 }
 
+// ---------------------------------------------------------------- mixed-radix lines
+// Line lengths N = 2^a 3^b 5^c that are not powers of two (the grids of Example 1,
+// Section 5.1).  One line per workgroup, held in LDS (dynamic shared memory, N
+// elements) and transformed by Stockham stages of radix 2, 3, 4 or 5 with a
+// barrier between the reads and the writes of a stage.  In a stage of radix R
+// thread t handles butterflies t, t + T, ... of the N/R (at most kGenE/R of them,
+// which the host's choice of T guarantees) and keeps their outputs in registers
+// until every thread has read its inputs.
+
+// exp(DIR 2 pi i m / RAD) for the small radices.
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ cpx<R> unit_root(int m) {
+  constexpr double c3 = -0.5, s3 = 0.86602540378443864676;                       // 2 pi / 3
+  constexpr double c5a = 0.30901699437494742410, s5a = 0.95105651629515357212;  // 2 pi / 5
+  constexpr double c5b = -0.80901699437494742410, s5b = 0.58778525229247312917; // 4 pi / 5
+  double c = 1.0, sn = 0.0;
+  if constexpr (RAD == 2) { c = m ? -1.0 : 1.0; }
+  else if constexpr (RAD == 3) { if (m) { c = c3; sn = m == 1 ? s3 : -s3; } }
+  else if constexpr (RAD == 4) { const double cc[4] = {1, 0, -1, 0}, ss[4] = {0, 1, 0, -1}; c = cc[m]; sn = ss[m]; }
+  else {
+    const double cc[5] = {1, c5a, c5b, c5b, c5a}, ss[5] = {0, s5a, s5b, -s5b, -s5a};
+    c = cc[m]; sn = ss[m];
+  }
+  return {(R)c, (R)(DIR * sn)};
+}
+
+// out[k] = sum_t v[t] exp(DIR 2 pi i t k / RAD), written out term by term.
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ void dft_small(cpx<R> (&v)[RAD]) {
+  cpx<R> o[RAD];
+#pragma unroll
+  for (int k = 0; k < RAD; ++k) {
+    cpx<R> acc = v[0];
+#pragma unroll
+    for (int t = 1; t < RAD; ++t) acc = cadd(acc, cmul(v[t], unit_root<R, RAD, DIR>((t * k) % RAD)));
+    o[k] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < RAD; ++k) v[k] = o[k];
+}
+
+template <typename R, int RAD, int DIR>
+__device__ void gen_stage(cpx<R>* buf, int ilv, int n, int ns, const cpx<R>* __restrict__ tw, int tid, int nthr) {
+  constexpr int MB = kGenE / RAD;
+  const int nb = n / RAD;
+  cpx<R> o[MB][RAD];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nb) {
+      const int k = b % ns;
+#pragma unroll
+      for (int t = 0; t < RAD; ++t) o[i][t] = buf[(size_t)(b + t * nb) * ilv];
+      if (ns > 1) {
+        const int step = n / (ns * RAD);
+#pragma unroll
+        for (int t = 1; t < RAD; ++t) {
+          const cpx<R> w = tw[k * t * step];
+          o[i][t] = DIR < 0 ? cmul(o[i][t], w) : cmulc(o[i][t], w);
+        }
+      }
+      dft_small<R, RAD, DIR>(o[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int b = tid + i * nthr;
+    if (b < nb) {
+      const int k = b % ns;
+      const int base = (b / ns) * ns * RAD + k;
+#pragma unroll
+      for (int t = 0; t < RAD; ++t) buf[(size_t)(base + t * ns) * ilv] = o[i][t];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place transform of the line in buf (element p at buf[p * ilv]); every thread
+// of the workgroup calls it after a barrier that follows the writes of the line.
+template <typename R, int DIR>
+__device__ void fft_gen(cpx<R>* buf, int ilv, const GenPlan& gp, const cpx<R>* __restrict__ tw, int tid) {
+  int ns = 1;
+  for (int s = 0; s < gp.nst; ++s) {
+    switch (gp.radix[s]) {
+      case 2: gen_stage<R, 2, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      case 3: gen_stage<R, 3, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      case 4: gen_stage<R, 4, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      default: gen_stage<R, 5, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+    }
+    ns *= gp.radix[s];
+  }
+}
+
+// Pass A: forward transform of rows of length gp.n.
+template <typename R, typename TI>
+__global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out,
+                                                       size_t in_rs, size_t out_rs, GenPlan gp,
+                                                       const cpx<R>* __restrict__ tw, const int* __restrict__ skip) {
+  extern __shared__ char dyn_lds[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
+  const int rhs = blockIdx.y;
+  if (skip != nullptr && skip[rhs] != 0) return;
+  const int n = gp.n, tid = threadIdx.x;
+  const size_t row = blockIdx.x;
+  const cpx<TI>* src = in + (size_t)rhs * in_rs + row * n;
+  for (int i = tid; i < n; i += gp.nthr) buf[i] = cvt<R>(src[i]);
+  __syncthreads();
+  fft_gen<R, -1>(buf, 1, gp, tw, tid);
+  cpx<R>* dst = out + (size_t)rhs * out_rs + row * n;
+  for (int i = tid; i < n; i += gp.nthr) dst[i] = buf[i];
+}
+
+// Strided axis, one column per workgroup: element (o, p, c) at o*n*S + p*S + c.
+// MODE 0: plain transform (slabs that no point of node field `fld` uses are skipped);
+// MODE 1: forward transform, then for every node symbol multiply and inverse
+// transform, storing the axis-0 indices whose rows use the node (need[n][p]).
+template <typename R, int DIR, int MODE>
+__global__ __launch_bounds__(512) void k_cols_gen(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int S,
+                                                   int nfields, size_t in_rs, size_t out_rs, size_t in_fs,
+                                                   size_t out_fs, GenPlan gp, const cpx<R>* __restrict__ tw,
+                                                   const int* __restrict__ skip, const double* __restrict__ lam_ax,
+                                                   const double* __restrict__ lam_in,
+                                                   const NodeConst* __restrict__ nodes, int K, double scale,
+                                                   const uint8_t* __restrict__ need) {
+  extern __shared__ char dyn_lds[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
+  const int z = blockIdx.z;
+  const int rhs = (MODE == 0) ? z / nfields : z;
+  const int fld = (MODE == 0) ? z % nfields : 0;
+  if (skip != nullptr && skip[rhs] != 0) return;
+  if (MODE == 0 && need != nullptr && need[(size_t)fld * gridDim.y + blockIdx.y] == 0) return;
+  const int n = gp.n, tid = threadIdx.x, nthr = gp.nthr;
+  const int c = blockIdx.x;
+  const size_t obase = (size_t)blockIdx.y * n * S + c;
+  const cpx<R>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
+  for (int p = tid; p < n; p += nthr) buf[p] = src[(size_t)p * S];
+  __syncthreads();
+  if constexpr (MODE == 0) {
+    fft_gen<R, DIR>(buf, 1, gp, tw, tid);
+    cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)fld * out_fs + obase;
+    for (int p = tid; p < n; p += nthr) dst[(size_t)p * S] = buf[p];
+  } else {
+    fft_gen<R, -1>(buf, 1, gp, tw, tid);
+    // the spectrum and lambda of this thread's elements p = tid + nthr * i
+    cpx<R> vh[kGenE];
+    double lam[kGenE];
+    const double lc = lam_in[c];
+#pragma unroll
+    for (int i = 0; i < kGenE; ++i) {
+      const int p = tid + i * nthr;
+      vh[i] = p < n ? buf[p] : cpx<R>{0, 0};
+      lam[i] = p < n ? lam_ax[p] + lc : 0.0;
+    }
+    cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
+    for (int nd = 0; nd < K; ++nd) {
+      const NodeConst nc = nodes[nd];
+#pragma unroll
+      for (int i = 0; i < kGenE; ++i) {
+        const int p = tid + i * nthr;
+        if (p < n) {
+          const double dre = nc.are - nc.gre * lam[i];
+          const double dim = nc.aim - nc.gim * lam[i];
+          cpx<R> q;
+          if constexpr (sizeof(R) == 8) {
+            const double inv = scale * recip(dre * dre + dim * dim);
+            q = {dre * inv, -dim * inv};
+          } else {
+            const float fr = (float)dre, fi = (float)dim;
+            const float inv = (float)scale * recip(fr * fr + fi * fi);
+            q = {fr * inv, -fi * inv};
+          }
+          buf[p] = cmul(vh[i], q);
+        }
+      }
+      __syncthreads();
+      fft_gen<R, +1>(buf, 1, gp, tw, tid);
+      const uint8_t* nn = need + (size_t)nd * n;
+      for (int p = tid; p < n; p += nthr)
+        if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[p];
+    }
+  }
+}
+
+// Pass C: inverse transform along rows of every node the row uses, and the
+// hat-weighted combine (weights 1-t on node A, t on node B of each point).
+template <typename R, typename TO, bool ACC>
+__global__ __launch_bounds__(512) void k_rows_combine_gen(const cpx<R>* __restrict__ fields, size_t fs,
+                                                           size_t frs, const double* __restrict__ pos,
+                                                           const uint64_t* __restrict__ rowmask,
+                                                           cpx<TO>* __restrict__ out, size_t out_rs, int K, int M,
+                                                           int Mt, int mo, GenPlan gp,
+                                                           const cpx<R>* __restrict__ tw,
+                                                           const int* __restrict__ skip) {
+  extern __shared__ char dyn_lds[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
+  const int rhs = blockIdx.y;
+  if (skip != nullptr && skip[rhs] != 0) return;
+  const int n = gp.n, tid = threadIdx.x, nthr = gp.nthr;
+  const size_t row = blockIdx.x, rbase = row * n;
+  int ab[kGenE];
+  R tt[kGenE];
+  cpx<R> acc[kGenE];
+#pragma unroll
+  for (int i = 0; i < kGenE; ++i) {
+    const int p = tid + i * nthr;
+    int A = -1, B = -1;
+    double t = 0.0;
+    if (p < n) decode_pos(pos[rbase + p], M, Mt, mo, A, B, t);
+    ab[i] = (A & 0xff) | ((B & 0xff) << 8);
+    tt[i] = (R)t;
+    acc[i] = {0, 0};
+  }
+  const uint64_t rm = rowmask[row];
+  const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
+  for (int nd = 0; nd < K; ++nd) {
+    if (((rm >> nd) & 1ull) == 0) continue;
+    for (int p = tid; p < n; p += nthr) buf[p] = fr[(size_t)nd * fs + p];
+    __syncthreads();
+    fft_gen<R, +1>(buf, 1, gp, tw, tid);
+#pragma unroll
+    for (int i = 0; i < kGenE; ++i) {
+      const int p = tid + i * nthr;
+      if (p < n) {
+        const int A = ab[i] & 0xff, B = (ab[i] >> 8) & 0xff;
+        const R w = (A == nd ? (R)1 - tt[i] : (R)0) + (B == nd ? tt[i] : (R)0);
+        const cpx<R> x = buf[p];
+        acc[i].re += w * x.re;
+        acc[i].im += w * x.im;
+      }
+    }
+  }
+  cpx<TO>* dst = out + (size_t)rhs * out_rs + rbase;
+#pragma unroll
+  for (int i = 0; i < kGenE; ++i) {
+    const int p = tid + i * nthr;
+    if (p < n) {
+      if constexpr (ACC) {
+        const cpx<TO> o = dst[p];
+        dst[p] = {o.re + (TO)acc[i].re, o.im + (TO)acc[i].im};
+      } else {
+        dst[p] = cvt<TO>(acc[i]);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- dispatch
 template <template <int> class F, typename... Args>
 hipError_t dispatch_n(int n, Args... args) {
@@ -358,9 +605,96 @@ struct RowsFwdL {
   };
 };
 
+// ---- mixed-radix launch helpers
+bool make_gen_plan(int n, GenPlan* gp) {
+  if (n < 2 || n > kGenMaxN) return false;
+  GenPlan g{};
+  g.n = n;
+  int m = n;
+  auto take = [&](int r) {
+    while (m % r == 0 && g.nst < kGenMaxStages) { g.radix[g.nst++] = r; m /= r; }
+  };
+  take(4);
+  take(2);
+  take(3);
+  take(5);
+  if (m != 1) return false;
+  for (int t = 64; t <= 512; t += 64) {   // within the kernels' launch bounds
+    bool ok = (size_t)t * kGenE >= (size_t)n;
+    for (int s = 0; s < g.nst && ok; ++s) {
+      const int r = g.radix[s];
+      ok = (n / r + t - 1) / t <= kGenE / r;
+    }
+    if (ok) { g.nthr = t; *gp = g; return true; }
+  }
+  return false;
+}
+
+template <typename K>
+static void allow_dynamic_lds(K kernel, size_t bytes) {
+  // lines longer than 64 KiB of LDS need the limit raised once per kernel
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename R, typename TI>
+static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int rows, size_t in_rs, size_t out_rs,
+                               int nrhs, const void* tw, const int* skip, hipStream_t st) {
+  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
+  allow_dynamic_lds(k_rows_fwd_gen<R, TI>, lds);
+  hipLaunchKernelGGL((k_rows_fwd_gen<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
+                     (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st) {
+  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
+  dim3 grid(a.S, a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
+  const cpx<R>* in = (const cpx<R>*)a.in;
+  cpx<R>* out = (cpx<R>*)a.out;
+  const cpx<R>* tw = (const cpx<R>*)a.tw;
+  if (a.mode == 1) {
+    allow_dynamic_lds(k_cols_gen<R, -1, 1>, lds);
+    hipLaunchKernelGGL((k_cols_gen<R, -1, 1>), grid, dim3(gp.nthr), lds, st, in, out, a.S, a.nfields, a.in_rs,
+                       a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
+                       a.store_need);
+  } else if (a.dir < 0) {
+    allow_dynamic_lds(k_cols_gen<R, -1, 0>, lds);
+    hipLaunchKernelGGL((k_cols_gen<R, -1, 0>), grid, dim3(gp.nthr), lds, st, in, out, a.S, a.nfields, a.in_rs,
+                       a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
+                       a.slab_need);
+  } else {
+    allow_dynamic_lds(k_cols_gen<R, +1, 0>, lds);
+    hipLaunchKernelGGL((k_cols_gen<R, +1, 0>), grid, dim3(gp.nthr), lds, st, in, out, a.S, a.nfields, a.in_rs,
+                       a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
+                       a.slab_need);
+  }
+  return hipGetLastError();
+}
+
+template <typename R, typename TO, bool ACC>
+static hipError_t combine_gen(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
+  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
+  allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC>, lds);
+  hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
+                     (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
+                     a.Mt, a.mo, gp, (const cpx<R>*)a.tw, a.skip);
+  return hipGetLastError();
+}
+
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
                            size_t in_rs, size_t out_rs, int nrhs, const void* tw, const int* skip,
                            hipStream_t st) {
+  if (!is_pow2_len(n)) {
+    GenPlan gp;
+    if (!make_gen_plan(n, &gp)) return hipErrorInvalidValue;
+    if (real_kind == 0) {
+      if (in_kind != 0) return hipErrorInvalidValue;
+      return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+    }
+    if (in_kind == 0) return rows_fwd_gen<float, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+    return rows_fwd_gen<float, float>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+  }
   if (real_kind == 0) {
     if (in_kind != 0) return hipErrorInvalidValue;
     return dispatch_n<RowsFwdL<double, double>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
@@ -404,6 +738,11 @@ struct ColsL {
 };
 
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st) {
+  if (!is_pow2_len(a.n)) {
+    GenPlan gp;
+    if (!make_gen_plan(a.n, &gp)) return hipErrorInvalidValue;
+    return a.real_kind == 0 ? cols_gen<double>(gp, a, st) : cols_gen<float>(gp, a, st);
+  }
   if (a.real_kind == 0) return dispatch_n<ColsL<double>::F>(a.n, a, st);
   return dispatch_n<ColsL<float>::F>(a.n, a, st);
 }
@@ -424,6 +763,18 @@ struct CombineL {
 };
 
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
+  if (!is_pow2_len(a.n)) {
+    GenPlan gp;
+    if (!make_gen_plan(a.n, &gp)) return hipErrorInvalidValue;
+    if (a.real_kind == 0) {
+      if (a.out_kind != 0) return hipErrorInvalidValue;
+      return a.accumulate ? combine_gen<double, double, true>(gp, a, st) : combine_gen<double, double, false>(gp, a, st);
+    }
+    if (a.out_kind == 0)
+      return a.accumulate ? combine_gen<float, double, true>(gp, a, st) : combine_gen<float, double, false>(gp, a, st);
+    if (a.accumulate) return hipErrorInvalidValue;
+    return combine_gen<float, float, false>(gp, a, st);
+  }
   if (a.real_kind == 0) {
     if (a.out_kind != 0) return hipErrorInvalidValue;
     if (a.accumulate) return dispatch_n<CombineL<double, double, true>::F>(a.n, a, st);
@@ -496,11 +847,14 @@ __global__ __launch_bounds__(256) void k_stencil(const cpx<TI>* __restrict__ u, 
   if (i >= npts) return;
   const cpx<TI>* ur = u + (size_t)rhs * u_rs;
   cpx<R> lap;
+  // periodic neighbours (any length)
+  auto nxt = [](int k, int n) { return k + 1 == n ? 0 : k + 1; };
+  auto prv = [](int k, int n) { return k == 0 ? n - 1 : k - 1; };
   if constexpr (DIM == 2) {
     const int i1 = (int)(i % n1), i0 = (int)(i / n1);
     const size_t r0 = (size_t)i0 * n1;
-    const size_t up = (size_t)((i0 + 1) & (n0 - 1)) * n1, dn = (size_t)((i0 - 1) & (n0 - 1)) * n1;
-    const cpx<R> a = cvt<R>(ur[r0 + ((i1 + 1) & (n1 - 1))]), b = cvt<R>(ur[r0 + ((i1 - 1) & (n1 - 1))]);
+    const size_t up = (size_t)nxt(i0, n0) * n1, dn = (size_t)prv(i0, n0) * n1;
+    const cpx<R> a = cvt<R>(ur[r0 + nxt(i1, n1)]), b = cvt<R>(ur[r0 + prv(i1, n1)]);
     const cpx<R> c = cvt<R>(ur[up + i1]), d = cvt<R>(ur[dn + i1]);
     lap = {(a.re + b.re) * ih1 + (c.re + d.re) * ih0, (a.im + b.im) * ih1 + (c.im + d.im) * ih0};
   } else {
@@ -509,11 +863,11 @@ __global__ __launch_bounds__(256) void k_stencil(const cpx<TI>* __restrict__ u, 
     const int i0 = (int)(i / ((size_t)n1 * n2));
     const size_t s1 = n2, s0 = (size_t)n1 * n2;
     const size_t b0 = (size_t)i0 * s0, b1 = (size_t)i1 * s1;
-    const cpx<R> a = cvt<R>(ur[b0 + b1 + ((i2 + 1) & (n2 - 1))]), b = cvt<R>(ur[b0 + b1 + ((i2 - 1) & (n2 - 1))]);
-    const cpx<R> c = cvt<R>(ur[b0 + (size_t)((i1 + 1) & (n1 - 1)) * s1 + i2]);
-    const cpx<R> d = cvt<R>(ur[b0 + (size_t)((i1 - 1) & (n1 - 1)) * s1 + i2]);
-    const cpx<R> e = cvt<R>(ur[(size_t)((i0 + 1) & (n0 - 1)) * s0 + b1 + i2]);
-    const cpx<R> q = cvt<R>(ur[(size_t)((i0 - 1) & (n0 - 1)) * s0 + b1 + i2]);
+    const cpx<R> a = cvt<R>(ur[b0 + b1 + nxt(i2, n2)]), b = cvt<R>(ur[b0 + b1 + prv(i2, n2)]);
+    const cpx<R> c = cvt<R>(ur[b0 + (size_t)nxt(i1, n1) * s1 + i2]);
+    const cpx<R> d = cvt<R>(ur[b0 + (size_t)prv(i1, n1) * s1 + i2]);
+    const cpx<R> e = cvt<R>(ur[(size_t)nxt(i0, n0) * s0 + b1 + i2]);
+    const cpx<R> q = cvt<R>(ur[(size_t)prv(i0, n0) * s0 + b1 + i2]);
     lap = {(a.re + b.re) * ih2 + (c.re + d.re) * ih1 + (e.re + q.re) * ih0,
            (a.im + b.im) * ih2 + (c.im + d.im) * ih1 + (e.im + q.im) * ih0};
   }

@@ -207,6 +207,24 @@ def _grf_3d(n: int, n_lambda: float, nrhs: int, seed: int, width: int = 24) -> W
                     info={"seed": seed, "n_lambda": n_lambda, "layer_cells": width, "nrhs": nrhs})
 
 
+def _inclusion_2d(n: int, ppw: float, delta: float, eta: float, a: float, m_real: int, precision: str,
+                  restart: int) -> Workload:
+    """Example 1 (Section 5.1): periodic unit square, background c_o = 1, a circular
+    inclusion of radius 0.05 at the centre with c = c_o + delta H_eta(0.05 - r)
+    (Eqn. WS), constant damping a, plane-wave source exp(i omega x_1 / c_o)
+    (Eqn. Source), omega from the points per wavelength PPW = 2 pi c_o N / (L omega).
+    No absorbing layer."""
+    shape = (n, n)
+    omega = 2.0 * math.pi * n / ppw
+    xs = mesh(shape)
+    r = np.sqrt(xs[0] ** 2 + xs[1] ** 2)
+    c = 1.0 + delta * smooth_heaviside(0.05 - r, eta)
+    f = np.exp(1j * omega * xs[0])[None]
+    return Workload(f"2d_{n}_inclusion", shape, 1.0, omega, c, np.full(shape, float(a)), None, f, m_real, 0,
+                    precision=precision, restart=restart,
+                    info={"ppw": ppw, "delta": delta, "eta": eta, "a": a, "n_lambda": n / ppw})
+
+
 def workload(name: str, **kw) -> Workload:
     """Named synthetic workloads.
 
@@ -217,8 +235,16 @@ def workload(name: str, **kw) -> Workload:
     2d_2048_grf       2048^2, 200 wavelengths, same recipe, 24 + 3 nodes, mixed precision.
     3d_256_grf        256^3, 25 wavelengths, 3-D random field (12 cells) plus a c = 1.4 sphere,
                       24-cell layer, 16 + 3 nodes, 16 right-hand sides, mixed precision.
+    2d_inclusion      Example 1 of the paper: N^2 (default 2400^2 = 200 wavelengths at 12 points
+                      per wavelength), circular inclusion with contrast delta = 1 and smoothness
+                      eta = 1/800, a = 20, plane-wave source, 8 nodes, no layer, GMRES(10), FP64.
+                      Overrides: n, ppw, delta, eta, a, m_real, precision, restart.
     Smaller variants take keyword overrides (n=..., n_lambda=..., nrhs=...).
     """
+    if name == "2d_inclusion":
+        return _inclusion_2d(kw.get("n", 2400), kw.get("ppw", 12.0), kw.get("delta", 1.0), kw.get("eta", 1.0 / 800),
+                             kw.get("a", 20.0), kw.get("m_real", 8), kw.get("precision", "fp64"),
+                             kw.get("restart", 10))
     idx = {"2d_64_bump": 0, "2d_1024_grf": 1, "2d_2048_grf": 2, "3d_256_grf": 3}
     if name not in idx:
         raise KeyError(name)

@@ -297,9 +297,11 @@ def test_plan_error_paths(hp, dev):
         with pytest.raises(hp.HelmpreError) as e:
             hp.Plan(shape, 10.0, cc, args.pop("a"), args.pop("zeta"), **args)
         assert e.value.code == code, (kw.keys(), e.value)
-    with pytest.raises(hp.HelmpreError) as e:
-        hp.Plan((12, 16), 10.0, np.ones((12, 16)))
-    assert e.value.code == hp.HP_E_SHAPE
+    # lengths must be even products of 2, 3 and 5, at least 8 and at most 4800
+    for bad in [(14, 16), (15, 16), (16, 4), (9600, 8), (4802, 8)]:
+        with pytest.raises(hp.HelmpreError) as e:
+            hp.Plan(bad, 10.0, np.ones(bad))
+        assert e.value.code == hp.HP_E_SHAPE, bad
     # a = 0 with no floor and omega = c |xi| on a grid mode: zero symbol denominator
     with pytest.raises(hp.HelmpreError) as e:
         hp.Plan(shape, 2 * np.pi, c, None, None, m_real=1, a_floor=0.0)
