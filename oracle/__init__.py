@@ -49,7 +49,7 @@ class _Setup(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_true_residual", C.c_double),
-                ("status", C.c_int)]
+                ("status", C.c_int), ("rel_prec_residual", C.c_double)]
 
 
 _lib = None
@@ -193,7 +193,8 @@ class Problem:
         if rc not in (OK, E_NOT_CONVERGED):
             raise OracleError(rc, "gmres")
         res = {"iters": info.iters, "cycles": info.cycles, "rel_true_residual": info.rel_true_residual,
-               "status": info.status, "history": hist[:max(1, info.cycles + 1)]}
+               "rel_prec_residual": info.rel_prec_residual, "status": info.status,
+               "history": hist[:max(1, info.cycles + 1)]}
         return x, res
 
 

@@ -567,6 +567,8 @@ typedef struct {
     int cycles;
     double rel_true_residual;
     int status;
+    double rel_prec_residual;   /* residual of the system GMRES is applied to:
+                                   ||Q(f - P x)|| / ||Q f|| for left, else the true one */
 } or_solve_info;
 
 /* Operator of the Krylov space: side 0: P Q, side 1: Q P, side 2: P. */
@@ -631,16 +633,19 @@ int or_gmres(const or_problem* p, int side, int m, int max_cycles, double rtol,
     }
     int nh = 0;
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
-        /* true residual r = f - P x */
+        /* true residual r = f - P x; with left preconditioning GMRES works on the
+         * system Q P x = Q f (Eqn. MainDiscretePrecond), whose residual Q r decides */
         rc = or_matvec(p, 1, x, tmp); if (rc) goto done;
         for (long i = 0; i < np; ++i) r[i] = f[i] - tmp[i];
         double rel = nrm2(np, r) / fn;
         info->rel_true_residual = rel;
-        if (hist && nh < hist_len) hist[nh++] = rel;
-        if (rel <= rtol) { info->status = OR_OK; goto done; }
-        info->cycles++;
         if (side == 1) { rc = or_apply(p, 1, r, tmp); if (rc) goto done; memcpy(r, tmp, sizeof(cx) * (size_t)np); }
         double beta = nrm2(np, r);
+        double trel = side == 1 ? beta / qfn : rel;
+        info->rel_prec_residual = trel;
+        if (hist && nh < hist_len) hist[nh++] = trel;
+        if (trel <= rtol) { info->status = OR_OK; goto done; }
+        info->cycles++;
         double target = rtol * (side == 1 ? qfn : fn);
         for (long i = 0; i < np; ++i) V[i] = r[i] / beta;
         for (int i = 0; i <= m; ++i) g[i] = 0;
@@ -698,8 +703,13 @@ int or_gmres(const or_problem* p, int side, int m, int max_cycles, double rtol,
     rc = or_matvec(p, 1, x, tmp); if (rc) goto done;
     for (long i = 0; i < np; ++i) r[i] = f[i] - tmp[i];
     info->rel_true_residual = nrm2(np, r) / fn;
-    if (hist && nh < hist_len) hist[nh++] = info->rel_true_residual;
-    info->status = info->rel_true_residual <= rtol ? OR_OK : OR_E_NOT_CONVERGED;
+    info->rel_prec_residual = info->rel_true_residual;
+    if (side == 1) {
+        rc = or_apply(p, 1, r, tmp); if (rc) goto done;
+        info->rel_prec_residual = nrm2(np, tmp) / qfn;
+    }
+    if (hist && nh < hist_len) hist[nh++] = info->rel_prec_residual;
+    info->status = info->rel_prec_residual <= rtol ? OR_OK : OR_E_NOT_CONVERGED;
     rc = info->status;
 done:
     free(V); free(r); free(tmp); free(H); free(g); free(cs); free(sn); free(y);

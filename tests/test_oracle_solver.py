@@ -80,7 +80,9 @@ def test_gmres_matches_dense_lu_16(orc, side):
     p = orc.Problem(shape, omega, c, a, zeta, m_real=4, a_floor=0.05 * omega)
     f = inputs.gaussian_source(shape, 2.0, (0.05, -0.1))
     x, info = p.gmres(f, rtol=1e-13, restart=30, side=side)
-    assert info["status"] == 0 and info["rel_true_residual"] <= 1e-13
+    # left: GMRES on Q P x = Q f stops on that system's residual (Eqn. MainDiscretePrecond)
+    assert info["status"] == 0 and info["rel_prec_residual"] <= 1e-13
+    assert info["rel_true_residual"] <= (1e-13 if side == "right" else 1e-11)
     xd = np.linalg.solve(_dense(p, shape), f.ravel()).reshape(shape)
     assert rel(x, xd) < 1e-10
 
