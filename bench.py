@@ -170,6 +170,65 @@ def batch3d(args, dev):
     print(json.dumps(out))
 
 
+def example1(args, dev):
+    """Example 1 of the paper (Section 5.1) on the GPU.
+
+    Table 1: event-timed Q_{N,M} applies for N = 180 * 2^k (k = 0..4) and M = 2, 4, 8
+    on the inclusion medium (delta = 4, eta = 1/800, a = 20, PPW = 12), normalised to
+    (N, M) = (180, 2), and the observed order beta of T ~ M N^(2 beta) log N fitted per M
+    and over all values.
+    GMRES comparison: 100 iterations of GMRES(10) with and without Q_8 on
+    N = 2400, 3600, 4800 (omega = 400 pi, 600 pi, 800 pi; delta = 1), FP64 true residuals."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    rng = np.random.default_rng(0)
+    table = {}
+    for n in args.ex1_sizes:
+        w = inputs.workload("2d_inclusion", n=n, delta=4.0)
+        v = torch.from_numpy(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape))[None].to(dev)
+        for m in (2, 4, 8):
+            p = binding.plan_from_workload(w, m_real=m)
+            p.profile_apply(v, reps=2)
+            ms, by = p.profile_apply(v, reps=10)
+            table[(n, m)] = sum(ms)
+            print(f"[bench] example1 apply N={n} M={m} K={p.info()['K']} {sum(ms) * 1e3:.1f} us "
+                  f"{sum(by) / (sum(ms) * 1e-3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+            p.close()
+    t0 = table[(args.ex1_sizes[0], 2)]
+    norm = {f"N={n},M={m}": t / t0 for (n, m), t in table.items()}
+
+    def beta(keys):
+        x = np.array([np.log(n) for n, m in keys])
+        y = np.array([np.log(table[(n, m)] / (m * np.log(n))) for n, m in keys])
+        return float(np.polyfit(x, y, 1)[0] / 2.0)
+
+    betas = {f"M={m}": beta([(n, m) for n in args.ex1_sizes]) for m in (2, 4, 8)}
+    betas["all"] = beta(list(table.keys()))
+    gm = []
+    for n in args.ex1_gmres:
+        w = inputs.workload("2d_inclusion", n=n, delta=1.0)
+        p = binding.plan_from_workload(w)
+        f = torch.from_numpy(w.f).to(dev)
+        row = {"N": n, "omega_over_pi": w.omega / np.pi, "dof": n * n}
+        for pre in (True, False):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = p.solve(f, rtol=1e-15, restart=10, max_cycles=10, side="right" if pre else "none")
+            torch.cuda.synchronize()
+            key = "precond" if pre else "plain"
+            row[key] = {"iters": info[0].iters, "rel_true_residual": info[0].rel_true_residual,
+                        "seconds": time.perf_counter() - t}
+            del x
+        row["orders_smaller"] = float(np.log10(row["plain"]["rel_true_residual"] / row["precond"]["rel_true_residual"]))
+        print(f"[bench] example1 GMRES N={n}: precond {row['precond']['rel_true_residual']:.2e} plain "
+              f"{row['plain']['rel_true_residual']:.2e} after 100 iterations", file=sys.stderr, flush=True)
+        gm.append(row)
+        p.close()
+    print(json.dumps({"mode": "example1", "table1_normalised_time": norm,
+                      "table1_apply_ms": {f"N={n},M={m}": t for (n, m), t in table.items()},
+                      "beta": betas, "gmres_100_iterations": gm}))
+
+
 def apply_only(args, w, plan, dev):
     import numpy as np
     import torch
@@ -208,9 +267,12 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--n3d", type=int, default=256)
     ap.add_argument("--nrhs3d", type=int, default=16)
-    ap.add_argument("--mode", choices=["solve", "apply", "batch3d"], default="solve",
+    ap.add_argument("--ex1-sizes", type=int, nargs="+", default=[180, 360, 720, 1440, 2880])
+    ap.add_argument("--ex1-gmres", type=int, nargs="*", default=[2400, 3600, 4800])
+    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1"], default="solve",
                     help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
-                         "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch")
+                         "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch; "
+                         "example1: the paper's Example 1 (Table 1 complexity, GMRES comparison)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -226,6 +288,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.mode == "batch3d":
         batch3d(args, dev)
+        return
+    if args.mode == "example1":
+        example1(args, dev)
         return
     w = inputs.workload(args.workload)
     if args.precision:

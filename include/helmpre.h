@@ -93,20 +93,30 @@ typedef struct {
   int max_nrhs;
 } hp_plan_opts;
 
-/* Right-preconditioned restarted GMRES(restart): solves P_N Q y = f, x = Q y,
- * starting from the x passed in.  Stops when the FP64 true residual
- * ||f - P_N x||_2 <= rtol ||f||_2 at a restart, or after max_cycles cycles. */
+/* Restarted GMRES(restart) on P_N x = f, starting from the x passed in.
+ *   side HP_RIGHT (default, 0): P_N Q y = f, x = Q y; stops when the FP64 true
+ *        residual ||f - P_N x||_2 <= rtol ||f||_2 at a restart.
+ *   side HP_LEFT: Q P_N x = Q f (Eqn. MainDiscretePrecond as written); stops when
+ *        the preconditioned residual ||Q (f - P_N x)|| <= rtol ||Q f|| at a restart.
+ *   side HP_NONE: plain GMRES on P_N x = f (FP64), the unpreconditioned
+ *        reference of the GMRES comparison of Section 5.1.
+ * Every side stops after max_cycles cycles. */
+enum { HP_RIGHT = 0, HP_LEFT = 1, HP_NONE = 2 };
 typedef struct {
   int restart;       /* 1..64                 */
   int max_cycles;    /* >= 1                  */
   double rtol;       /* > 0                   */
+  int side;          /* HP_RIGHT, HP_LEFT, HP_NONE */
 } hp_solve_opts;
 
 typedef struct {
-  int iters;                 /* Arnoldi steps taken                    */
-  int cycles;                /* restart cycles run                     */
-  double rel_true_residual;  /* ||f - P_N x|| / ||f|| at return (FP64) */
-  int status;                /* HP_OK or HP_E_NOT_CONVERGED            */
+  int iters;                 /* Arnoldi steps taken                                  */
+  int cycles;                /* restart cycles run                                   */
+  double rel_true_residual;  /* ||f - P_N x|| / ||f|| at return (FP64)               */
+  int status;                /* HP_OK or HP_E_NOT_CONVERGED                          */
+  double rel_prec_residual;  /* the residual the stopping test used: the true one for
+                                HP_RIGHT and HP_NONE, ||Q(f - P_N x)|| / ||Q f|| for
+                                HP_LEFT                                              */
 } hp_solve_info;
 
 /* Read-only description of a plan (for tests and reports). */

@@ -42,13 +42,16 @@ class HpPlanOpts(C.Structure):
                 ("symbol", C.c_int), ("precision", C.c_int), ("max_nrhs", C.c_int)]
 
 
+SIDES = {"right": 0, "left": 1, "none": 2}   # HP_RIGHT, HP_LEFT, HP_NONE
+
+
 class HpSolveOpts(C.Structure):
-    _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double)]
+    _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double), ("side", C.c_int)]
 
 
 class HpSolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("rel_true_residual", C.c_double),
-                ("status", C.c_int)]
+                ("status", C.c_int), ("rel_prec_residual", C.c_double)]
 
 
 class HpPlanInfo(C.Structure):
@@ -147,6 +150,7 @@ class SolveInfo:
     cycles: int
     rel_true_residual: float
     status: int
+    rel_prec_residual: float = float("nan")   # the residual the stopping test used (left: preconditioned)
 
 
 class Plan:
@@ -249,20 +253,22 @@ class Plan:
                                         _stream(stream)), "hp_matvec")
         return y
 
-    def solve(self, f, x=None, *, restart=30, max_cycles=200, rtol=1e-8, stream=None, raise_on_fail=False):
-        """Right-preconditioned restarted GMRES.  f (and x) complex128; returns (x, [SolveInfo])."""
+    def solve(self, f, x=None, *, restart=30, max_cycles=200, rtol=1e-8, stream=None, raise_on_fail=False,
+              side="right"):
+        """Restarted GMRES preconditioned by Q_M on the right (default) or left, or plain
+        (side="none").  f (and x) complex128; returns (x, [SolveInfo])."""
         import torch
         nr = self._fields(f, torch.complex128, "f")
         if x is None:
             x = torch.zeros_like(f)
         self._fields(x, torch.complex128, "x")
-        o = HpSolveOpts(int(restart), int(max_cycles), float(rtol))
+        o = HpSolveOpts(int(restart), int(max_cycles), float(rtol), SIDES[side])
         infos = (HpSolveInfo * nr)()
         code = load_library().hp_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()), nr,
                                        C.byref(o), infos, _stream(stream))
         if code not in (HP_OK, HP_E_NOT_CONVERGED) or (raise_on_fail and code != HP_OK):
             raise HelmpreError(code, "hp_solve")
-        return x, [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status) for i in infos]
+        return x, [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status, i.rel_prec_residual) for i in infos]
 
     def profile_apply(self, v, out=None, reps=20, stream=None):
         """Event-timed applies: (ms per launch of the 5 pass slots, algorithmic bytes per pass)."""
@@ -292,10 +298,10 @@ class Solver:
     advance() without blocking until finished, then result().  The Krylov state
     stays on the GPU."""
 
-    def __init__(self, plan, nrhs=1, *, restart=30, max_cycles=200, rtol=1e-8):
+    def __init__(self, plan, nrhs=1, *, restart=30, max_cycles=200, rtol=1e-8, side="right"):
         self.plan = plan
         self.nrhs = int(nrhs)
-        self._opts = HpSolveOpts(int(restart), int(max_cycles), float(rtol))
+        self._opts = HpSolveOpts(int(restart), int(max_cycles), float(rtol), SIDES[side])
         h = C.c_void_p()
         _check(load_library().hp_solver_create(C.byref(h), plan._h, self.nrhs, C.byref(self._opts)),
                "hp_solver_create")
@@ -325,7 +331,7 @@ class Solver:
         code = load_library().hp_solver_wait(self._h, infos)
         if code not in (HP_OK, HP_E_NOT_CONVERGED):
             raise HelmpreError(code, "hp_solver_wait")
-        return self._keep[1], [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status) for i in infos]
+        return self._keep[1], [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status, i.rel_prec_residual) for i in infos]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -756,14 +756,25 @@ struct Session {
     j = 0;
     hipError_t e;
     if ((e = hp::launch_fill_zero(W->flags.p, W->flags.bytes, st)) != hipSuccess) return e;
-    if ((e = hp::launch_fnorm(K, f, np, o.rtol, st)) != hipSuccess) return e;
+    if (o.side == HP_LEFT) {   // the stopping test uses ||Q f||; ||f|| for the reported true residual
+      cpx<double>* qf = (cpx<double>*)W->tvec.p;
+      if ((e = run_apply(P, f, 0, np, qf, 0, np, false, nrhs, nullptr, st)) != hipSuccess) return e;
+      if ((e = hp::launch_fnorm(K, qf, np, o.rtol, st)) != hipSuccess) return e;
+      if ((e = hp::launch_plain_norm(K, f, np, 0, st)) != hipSuccess) return e;
+    } else if ((e = hp::launch_fnorm(K, f, np, o.rtol, st)) != hipSuccess) {
+      return e;
+    }
     return enqueue_cycle_start();
   }
 
-  // true residual r = f - P_N x into v_0, its norm and the convergence test
+  // residual r = f - P_N x into v_0 (Q r for a left-preconditioned solve), its
+  // norm and the convergence test
   hipError_t enqueue_cycle_start() {
     hipError_t e;
     if ((e = run_stencil(P, 3, x, P->npts, K.V, vrs, f, nrhs, K.done, st)) != hipSuccess) return e;
+    if (o.side == HP_LEFT &&
+        (e = run_apply(P, K.V, 0, vrs, K.V, 0, vrs, false, nrhs, K.done, st)) != hipSuccess)
+      return e;
     if ((e = hp::launch_cycle_start(K, o.rtol, st)) != hipSuccess) return e;
     if ((e = hipEventRecord(W->cyc_ev, st)) != hipSuccess) return e;
     phase = kCycleStart;
@@ -776,11 +787,18 @@ struct Session {
     cpx<double>* vj = K.V + (size_t)j * np;
     cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
     hipError_t e;
-    // w = P_N Q u_j
-    if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st)) != hipSuccess)
-      return e;
-    if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess)
-      return e;
+    if (o.side == HP_NONE) {          // w = P_N u_j (plain GMRES, FP64)
+      if ((e = run_stencil(P, 0, vj, vrs, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess) return e;
+    } else if (o.side == HP_LEFT) {   // w = Q P_N u_j (P_N in FP64)
+      cpx<double>* pv = (cpx<double>*)W->tvec.p;
+      if ((e = run_stencil(P, 0, vj, vrs, pv, np, nullptr, nrhs, K.skip_step, st)) != hipSuccess) return e;
+      if ((e = run_apply(P, pv, 0, np, vj1, 0, vrs, false, nrhs, K.skip_step, st)) != hipSuccess) return e;
+    } else {                          // w = P_N Q u_j
+      if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st)) != hipSuccess)
+        return e;
+      if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess)
+        return e;
+    }
     if ((e = hp::launch_arnoldi_dots(K, j, st)) != hipSuccess) return e;
     if ((e = hp::launch_arnoldi_update(K, j, st)) != hipSuccess) return e;
     if ((e = hipEventRecord(W->step_ev[j % (SolverWs::kLag + 1)], st)) != hipSuccess) return e;
@@ -792,8 +810,12 @@ struct Session {
   hipError_t enqueue_cycle_end() {
     hipError_t e;
     if ((e = hp::launch_backsolve(K, st)) != hipSuccess) return e;
-    if ((e = hp::launch_lincomb(K, (cpx<double>*)W->tvec.p, P->npts, st)) != hipSuccess) return e;
-    if ((e = run_apply(P, W->tvec.p, 0, P->npts, x, 0, P->npts, true, nrhs, K.done, st)) != hipSuccess) return e;
+    if (o.side != HP_RIGHT) {   // x += V_k y
+      if ((e = hp::launch_lincomb(K, x, P->npts, true, st)) != hipSuccess) return e;
+    } else {
+      if ((e = hp::launch_lincomb(K, (cpx<double>*)W->tvec.p, P->npts, false, st)) != hipSuccess) return e;
+      if ((e = run_apply(P, W->tvec.p, 0, P->npts, x, 0, P->npts, true, nrhs, K.done, st)) != hipSuccess) return e;
+    }
     ++cycles_run;
     return enqueue_cycle_start();
   }
@@ -828,6 +850,11 @@ struct Session {
         if (!ready(W->cyc_ev, block, e)) return e;
         if (all(K.host_done) || cycles_run >= o.max_cycles) {
           phase = kFinished;
+          if (o.side == HP_LEFT) {   // the true residual of the returned x
+            cpx<double>* r = (cpx<double>*)W->tvec.p;
+            if ((e = run_stencil(P, 3, x, P->npts, r, P->npts, f, nrhs, nullptr, st)) != hipSuccess) return e;
+            if ((e = hp::launch_plain_norm(K, r, P->npts, 1, st)) != hipSuccess) return e;
+          }
           return hipSuccess;
         }
         if ((e = hp::launch_scale_v0(K, st)) != hipSuccess) return e;
@@ -866,7 +893,8 @@ struct Session {
       const bool ok = W->pinned[r] != 0;
       info[r].iters = hs[r].iters;
       info[r].cycles = hs[r].cycles;
-      info[r].rel_true_residual = hs[r].relres;
+      info[r].rel_true_residual = o.side == HP_LEFT ? hs[r].relres_plain : hs[r].relres;
+      info[r].rel_prec_residual = hs[r].relres;
       info[r].status = ok ? HP_OK : HP_E_NOT_CONVERGED;
       if (!ok) ret = HP_E_NOT_CONVERGED;
     }
@@ -911,7 +939,8 @@ extern "C" {
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts, hp_solve_info* info,
                    void* stream) {
   if (!p || !f || !x || !opts || !info || nrhs < 0) return HP_E_INVALID;
-  if (opts->restart < 1 || opts->restart > hp::kMaxRestart || opts->max_cycles < 1 || !(opts->rtol > 0))
+  if (opts->restart < 1 || opts->restart > hp::kMaxRestart || opts->max_cycles < 1 || !(opts->rtol > 0) ||
+      opts->side < HP_RIGHT || opts->side > HP_NONE)
     return HP_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
   hp_status ret = HP_OK;
@@ -929,7 +958,8 @@ hp_status hp_solver_create(hp_solver* out, hp_plan p, int nrhs, const hp_solve_o
   if (!out) return HP_E_INVALID;
   *out = nullptr;
   if (!p || !opts || nrhs < 1 || nrhs > p->max_nrhs) return HP_E_INVALID;
-  if (opts->restart < 1 || opts->restart > hp::kMaxRestart || opts->max_cycles < 1 || !(opts->rtol > 0))
+  if (opts->restart < 1 || opts->restart > hp::kMaxRestart || opts->max_cycles < 1 || !(opts->rtol > 0) ||
+      opts->side < HP_RIGHT || opts->side > HP_NONE)
     return HP_E_INVALID;
   hp_solver_s* s = new (std::nothrow) hp_solver_s();
   if (!s) return HP_E_NOMEM;

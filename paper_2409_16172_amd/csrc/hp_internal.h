@@ -34,6 +34,7 @@ struct KState {
   cpx<double> av[kMaxRestart + 1];     // second-projection coefficients a of u_j
   cpx<double> cu;                      // update coefficient on u_j
   double fnorm, target, beta, inv_sigma, relres;
+  double fnorm_plain, relres_plain;   // ||f|| and ||f - P x|| / ||f|| (left-preconditioned solves)
   int k;        // columns finished in the current cycle
   int stop_at;  // step at which the current cycle ends (-1: not yet)
   int iters;    // Arnoldi steps in total
@@ -153,7 +154,10 @@ hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st);
 // Arnoldi step j: slot j <- v_j, slot j+1 <- u_{j+1}.
 hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, hipStream_t st);
 hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);
-hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, hipStream_t st);
+// ||w||^2 of each right-hand side into KState::fnorm_plain (which = 0) or, divided
+// by it, into KState::relres_plain (which = 1); all right-hand sides.
+hipError_t launch_plain_norm(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int which, hipStream_t st);
+hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, bool accumulate, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // ---- plan set-up on the device (FP64) ----

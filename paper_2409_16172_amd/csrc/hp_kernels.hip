@@ -1038,7 +1038,7 @@ __device__ __forceinline__ void publish_stop(int* host_stop, int rhs, int v) {
 }
 
 // What the last block does with the sums.
-enum DotsMode { kDotsFnorm = 0, kDotsCycle = 1 };
+enum DotsMode { kDotsFnorm = 0, kDotsCycle = 1, kDotsPlain = 2 };
 
 struct DotsCtl {
   KState* state;
@@ -1065,7 +1065,11 @@ __device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs
     c.skip_step[rhs] = c.done[rhs];
     publish_stop(c.host_stop, rhs, c.skip_step[rhs]);
     publish_stop(c.host_done, rhs, c.done[rhs]);
-  } else if (c.mode == kDotsCycle) {     // cycle start: beta = ||r||, true-residual test
+  } else if (c.mode == kDotsPlain) {     // unpreconditioned norms of a left-preconditioned solve
+    const double nrm = sqrt(sums[0].re);
+    if (c.j == 0) S.fnorm_plain = nrm;
+    else S.relres_plain = S.fnorm_plain > 0.0 ? nrm / S.fnorm_plain : 0.0;
+  } else if (c.mode == kDotsCycle) {     // cycle start: beta = ||r||, residual test
     const double beta = sqrt(sums[0].re);
     S.beta = beta;
     S.relres = S.fnorm > 0.0 ? beta / S.fnorm : 0.0;
@@ -1472,7 +1476,7 @@ __global__ __launch_bounds__(256) void k_backsolve(KState* state, const int* don
 // out = sum_{i<k} y_i v_i
 __global__ __launch_bounds__(256) void k_lincomb(const cpx<double>* __restrict__ V, size_t npts, size_t vrs,
                                                  const KState* __restrict__ state, cpx<double>* __restrict__ out,
-                                                 size_t out_rs, const int* __restrict__ done) {
+                                                 size_t out_rs, int accumulate, const int* __restrict__ done) {
   __shared__ cpx<double> y[kMaxRestart];
   const int rhs = blockIdx.y;
   if (done[rhs]) return;
@@ -1495,6 +1499,7 @@ __global__ __launch_bounds__(256) void k_lincomb(const cpx<double>* __restrict__
         a.im += c.re * b[u].im + c.im * b[u].re;
       }
     }
+    if (accumulate) a = cadd(a, o[i]);
     o[i] = a;
   }
 }
@@ -1654,6 +1659,14 @@ hipError_t launch_fnorm(const KrylovArgs& a, const cpx<double>* f, size_t frs, d
   return hipGetLastError();
 }
 
+hipError_t launch_plain_norm(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int which, hipStream_t st) {
+  const DotsCtl c = dots_ctl(a, kDotsPlain, which, 0.0);
+  hipLaunchKernelGGL(k_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs, w, wrs, 0,
+                     a.part, (const int*)nullptr, c);
+  hipLaunchKernelGGL(k_dots_fin, dim3(a.nrhs), dim3(1024), 0, st, (const cpx<double>*)a.part, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_cycle_start(const KrylovArgs& a, double rtol, hipStream_t st) {
   const DotsCtl c = dots_ctl(a, kDotsCycle, 0, rtol);
   hipLaunchKernelGGL(k_dots, dim3(kRedBlocks, a.nrhs), dim3(kRedThreads), 0, st, a.V, a.npts, a.vrs, a.V, a.vrs, 0,
@@ -1694,9 +1707,9 @@ hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, hipStream_t st) {
+hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, bool accumulate, hipStream_t st) {
   hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(a.npts), a.nrhs), dim3(256), 0, st, a.V, a.npts, a.vrs,
-                     a.state, out, out_rs, a.done);
+                     a.state, out, out_rs, accumulate ? 1 : 0, a.done);
   return hipGetLastError();
 }
 

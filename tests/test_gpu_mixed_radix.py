@@ -118,3 +118,28 @@ def test_matvec_mixed_radix(orc, hp, dev, shape, prec, tol):
         u = u.astype(np.complex64).astype(np.complex128)
     y = plan.matvec(torch.from_numpy(u).to(dev).to(dt)).cpu().numpy()
     assert rel(y, ref.matvec(u)) < tol
+
+
+def test_plain_and_left_gmres_match_oracle(orc, hp, dev):
+    """side="none": plain restarted GMRES(10) on P_N x = f (the unpreconditioned reference of the
+    GMRES comparison in Section 5.1) and side="left": Q P_N x = Q f as Eqn. MainDiscretePrecond
+    is written, both against the oracle's GMRES on the same side."""
+    _case("plain_left_gmres", n=36)
+    w = inputs.workload("2d_inclusion", n=36, ppw=6.0)
+    plan = hp.plan_from_workload(w)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    for side, rtol in (("none", 1e-6), ("left", 1e-9)):
+        x, info = plan.solve(f, rtol=rtol, restart=10, max_cycles=400, side=side)
+        xr, res = ref.gmres(w.f[0], restart=10, rtol=rtol, max_cycles=400, side=side)
+        assert info[0].status == 0 and res["status"] == 0, side
+        true = rel(ref.matvec(x.cpu().numpy()[0]), w.f[0])
+        assert abs(info[0].rel_true_residual - true) <= 1e-6 * true + 1e-15, (side, info[0], true)
+        if side == "none":
+            assert true <= rtol * 1.001
+        assert abs(info[0].iters - res["iters"]) <= max(3, res["iters"] // 20), (side, info[0].iters, res["iters"])
+    # a fixed budget of 30 steps: the preconditioned residual is far below the plain one
+    _, ip = plan.solve(f, rtol=1e-15, restart=10, max_cycles=3)
+    _, iq = plan.solve(f, rtol=1e-15, restart=10, max_cycles=3, side="none")
+    assert ip[0].iters == iq[0].iters == 30
+    assert ip[0].rel_true_residual < 1e-2 * iq[0].rel_true_residual
