@@ -177,8 +177,9 @@ def example1(args, dev):
     on the inclusion medium (delta = 4, eta = 1/800, a = 20, PPW = 12), normalised to
     (N, M) = (180, 2), and the observed order beta of T ~ M N^(2 beta) log N fitted per M
     and over all values.
-    GMRES comparison: 100 iterations of GMRES(10) with and without Q_8 on
-    N = 2400, 3600, 4800 (omega = 400 pi, 600 pi, 800 pi; delta = 1), FP64 true residuals."""
+    GMRES comparison: 100 iterations of GMRES(10) with Q_8 on the left (the system
+    Q P x = Q f, whose residual the paper plots), on the right, and without a
+    preconditioner, on N = 2400, 3600, 4800 (omega = 400 pi, 600 pi, 800 pi; delta = 1)."""
     import torch
     from paper_2409_16172_amd import binding, inputs
     rng = np.random.default_rng(0)
@@ -210,18 +211,22 @@ def example1(args, dev):
         p = binding.plan_from_workload(w)
         f = torch.from_numpy(w.f).to(dev)
         row = {"N": n, "omega_over_pi": w.omega / np.pi, "dof": n * n}
-        for pre in (True, False):
+        for side in ("left", "right", "none"):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            x, info = p.solve(f, rtol=1e-15, restart=10, max_cycles=10, side="right" if pre else "none")
+            x, info = p.solve(f, rtol=1e-15, restart=10, max_cycles=10, side=side)
             torch.cuda.synchronize()
-            key = "precond" if pre else "plain"
-            row[key] = {"iters": info[0].iters, "rel_true_residual": info[0].rel_true_residual,
-                        "seconds": time.perf_counter() - t}
+            row[side] = {"iters": info[0].iters, "rel_true_residual": info[0].rel_true_residual,
+                         "rel_system_residual": info[0].rel_prec_residual, "seconds": time.perf_counter() - t}
             del x
-        row["orders_smaller"] = float(np.log10(row["plain"]["rel_true_residual"] / row["precond"]["rel_true_residual"]))
-        print(f"[bench] example1 GMRES N={n}: precond {row['precond']['rel_true_residual']:.2e} plain "
-              f"{row['plain']['rel_true_residual']:.2e} after 100 iterations", file=sys.stderr, flush=True)
+        row["orders_smaller_left_system"] = float(np.log10(row["none"]["rel_true_residual"] /
+                                                           row["left"]["rel_system_residual"]))
+        row["orders_smaller_right_true"] = float(np.log10(row["none"]["rel_true_residual"] /
+                                                          row["right"]["rel_true_residual"]))
+        print(f"[bench] example1 GMRES(10) N={n}, 100 iterations: left ||Q r||/||Q f|| "
+              f"{row['left']['rel_system_residual']:.2e} (true {row['left']['rel_true_residual']:.2e}), right "
+              f"{row['right']['rel_true_residual']:.2e}, plain {row['none']['rel_true_residual']:.2e}",
+              file=sys.stderr, flush=True)
         gm.append(row)
         p.close()
     print(json.dumps({"mode": "example1", "table1_normalised_time": norm,

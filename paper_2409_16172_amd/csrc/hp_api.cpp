@@ -210,9 +210,8 @@ hp_status check_grid(const hp_grid* g, int prec) {
   const int hi = prec == HP_FP64 ? 2048 : 4096;
   for (int d = 0; d < g->dim; ++d) {
     // powers of two, or even products of 2, 3 and 5 (mixed-radix lines held in LDS)
-    hp::GenPlan gp;
     const int n = g->n[d];
-    const bool ok = pow2_in(n, 8, hi) || (n >= 8 && n % 2 == 0 && hp::make_gen_plan(n, &gp));
+    const bool ok = pow2_in(n, 8, hi) || (n >= 8 && n % 2 == 0 && hp::gen_length_ok(n));
     if (!ok) return HP_E_SHAPE;
     if (!(g->len[d] > 0) || !std::isfinite(g->len[d])) return HP_E_INVALID;
   }

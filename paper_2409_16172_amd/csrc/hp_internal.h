@@ -53,16 +53,25 @@ constexpr int kRedBlocks = HP_RED_BLOCKS;    // blocks per right-hand side (fixe
 constexpr int kPartSlots = 2 * kMaxRestart + 4;
 
 // Mixed-radix lines (N = 2^a 3^b 5^c, not a power of two): stage radices in
-// order and the threads per line.  Each thread holds at most kGenE elements.
-constexpr int kGenE = 16;
+// order, threads per line and (column passes) lines per workgroup.  A thread
+// holds at most E elements of a line: kGenRowE in pass A, gen_e<R>() in the
+// column passes and in pass C.
+constexpr int kGenRowE = 16;
+// column passes and pass C: FP64 lines with 12 elements per thread and at most 512
+// threads (up to 256 VGPRs), FP32 lines with 8 and at most 1024
+template <typename R> constexpr int gen_e() { return sizeof(R) == 8 ? 12 : 8; }
+template <typename R> constexpr int gen_maxthr() { return sizeof(R) == 8 ? 512 : 1024; }
 constexpr int kGenMaxStages = 24;
 constexpr int kGenMaxN = 4800;
 struct GenPlan {
-  int n, nst, nthr;
+  int n, nst, nthr, tc;
   int radix[kGenMaxStages];
 };
-// Fills *gp for length n; false if n is not a product of 2, 3 and 5 within kGenMaxN.
-bool make_gen_plan(int n, GenPlan* gp);
+// Fills *gp for length n, E elements per thread and at most maxthr threads per
+// line; false if n is not a product of 2, 3 and 5 within kGenMaxN or does not fit.
+bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp);
+// Every mixed-radix kernel can take lines of length n.
+bool gen_length_ok(int n);
 inline bool is_pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // ---- launchers (all enqueue on `st`, return the launch status) ----

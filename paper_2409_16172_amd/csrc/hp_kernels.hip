@@ -330,7 +330,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
 // Section 5.1).  One line per workgroup, held in LDS (dynamic shared memory, N
 // elements) and transformed by Stockham stages of radix 2, 3, 4 or 5 with a
 // barrier between the reads and the writes of a stage.  In a stage of radix R
-// thread t handles butterflies t, t + T, ... of the N/R (at most kGenE/R of them,
+// thread t handles butterflies t, t + T, ... of the N/R (at most E/R of them,
 // which the host's choice of T guarantees) and keeps their outputs in registers
 // until every thread has read its inputs.
 
@@ -366,9 +366,9 @@ __device__ __forceinline__ void dft_small(cpx<R> (&v)[RAD]) {
   for (int k = 0; k < RAD; ++k) v[k] = o[k];
 }
 
-template <typename R, int RAD, int DIR>
+template <typename R, int RAD, int DIR, int E>
 __device__ void gen_stage(cpx<R>* buf, int ilv, int n, int ns, const cpx<R>* __restrict__ tw, int tid, int nthr) {
-  constexpr int MB = kGenE / RAD;
+  constexpr int MB = E / RAD;
   const int nb = n / RAD;
   cpx<R> o[MB][RAD];
 #pragma unroll
@@ -405,15 +405,15 @@ __device__ void gen_stage(cpx<R>* buf, int ilv, int n, int ns, const cpx<R>* __r
 
 // In-place transform of the line in buf (element p at buf[p * ilv]); every thread
 // of the workgroup calls it after a barrier that follows the writes of the line.
-template <typename R, int DIR>
+template <typename R, int DIR, int E>
 __device__ void fft_gen(cpx<R>* buf, int ilv, const GenPlan& gp, const cpx<R>* __restrict__ tw, int tid) {
   int ns = 1;
   for (int s = 0; s < gp.nst; ++s) {
     switch (gp.radix[s]) {
-      case 2: gen_stage<R, 2, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
-      case 3: gen_stage<R, 3, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
-      case 4: gen_stage<R, 4, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
-      default: gen_stage<R, 5, DIR>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      case 2: gen_stage<R, 2, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      case 3: gen_stage<R, 3, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      case 4: gen_stage<R, 4, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+      default: gen_stage<R, 5, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
     }
     ns *= gp.radix[s];
   }
@@ -433,58 +433,67 @@ __global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict_
   const cpx<TI>* src = in + (size_t)rhs * in_rs + row * n;
   for (int i = tid; i < n; i += gp.nthr) buf[i] = cvt<R>(src[i]);
   __syncthreads();
-  fft_gen<R, -1>(buf, 1, gp, tw, tid);
+  fft_gen<R, -1, kGenRowE>(buf, 1, gp, tw, tid);
   cpx<R>* dst = out + (size_t)rhs * out_rs + row * n;
   for (int i = tid; i < n; i += gp.nthr) dst[i] = buf[i];
 }
 
-// Strided axis, one column per workgroup: element (o, p, c) at o*n*S + p*S + c.
+// Strided axis, gp.tc adjacent columns per workgroup (their lines interleaved
+// in LDS: element p of column g at p*tc + g, so that loads and stores of a
+// wavefront touch tc consecutive columns): element (o, p, c) at o*n*S + p*S + c.
 // MODE 0: plain transform (slabs that no point of node field `fld` uses are skipped);
 // MODE 1: forward transform, then for every node symbol multiply and inverse
 // transform, storing the axis-0 indices whose rows use the node (need[n][p]).
 template <typename R, int DIR, int MODE>
-__global__ __launch_bounds__(512) void k_cols_gen(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int S,
+__global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int S,
                                                    int nfields, size_t in_rs, size_t out_rs, size_t in_fs,
                                                    size_t out_fs, GenPlan gp, const cpx<R>* __restrict__ tw,
                                                    const int* __restrict__ skip, const double* __restrict__ lam_ax,
                                                    const double* __restrict__ lam_in,
                                                    const NodeConst* __restrict__ nodes, int K, double scale,
                                                    const uint8_t* __restrict__ need) {
+  constexpr int E = gen_e<R>();
   extern __shared__ char dyn_lds[];
-  cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
   const int z = blockIdx.z;
   const int rhs = (MODE == 0) ? z / nfields : z;
   const int fld = (MODE == 0) ? z % nfields : 0;
   if (skip != nullptr && skip[rhs] != 0) return;
   if (MODE == 0 && need != nullptr && need[(size_t)fld * gridDim.y + blockIdx.y] == 0) return;
-  const int n = gp.n, tid = threadIdx.x, nthr = gp.nthr;
-  const int c = blockIdx.x;
-  const size_t obase = (size_t)blockIdx.y * n * S + c;
+  const int n = gp.n, tc = gp.tc, nthr = gp.nthr;
+  const int g = threadIdx.x % tc, tl = threadIdx.x / tc;
+  int tile = blockIdx.x;
+  if ((gridDim.x & 7) == 0) tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);   // XCD-aware
+  const int c = tile * tc + g;
+  const bool act = c < S;
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds) + g;
+  const size_t obase = (size_t)blockIdx.y * n * S + (act ? c : 0);
   const cpx<R>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
-  for (int p = tid; p < n; p += nthr) buf[p] = src[(size_t)p * S];
+  for (int p = tl; p < n; p += nthr) buf[(size_t)p * tc] = act ? src[(size_t)p * S] : cpx<R>{0, 0};
   __syncthreads();
   if constexpr (MODE == 0) {
-    fft_gen<R, DIR>(buf, 1, gp, tw, tid);
-    cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)fld * out_fs + obase;
-    for (int p = tid; p < n; p += nthr) dst[(size_t)p * S] = buf[p];
+    fft_gen<R, DIR, E>(buf, tc, gp, tw, tl);
+    if (act) {
+      cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)fld * out_fs + obase;
+      for (int p = tl; p < n; p += nthr) dst[(size_t)p * S] = buf[(size_t)p * tc];
+    }
   } else {
-    fft_gen<R, -1>(buf, 1, gp, tw, tid);
-    // the spectrum and lambda of this thread's elements p = tid + nthr * i
-    cpx<R> vh[kGenE];
-    double lam[kGenE];
-    const double lc = lam_in[c];
+    fft_gen<R, -1, E>(buf, tc, gp, tw, tl);
+    // the spectrum and lambda of this thread's elements p = tl + nthr * i
+    cpx<R> vh[E];
+    double lam[E];
+    const double lc = act ? lam_in[c] : 0.0;
 #pragma unroll
-    for (int i = 0; i < kGenE; ++i) {
-      const int p = tid + i * nthr;
-      vh[i] = p < n ? buf[p] : cpx<R>{0, 0};
+    for (int i = 0; i < E; ++i) {
+      const int p = tl + i * nthr;
+      vh[i] = p < n ? buf[(size_t)p * tc] : cpx<R>{0, 0};
       lam[i] = p < n ? lam_ax[p] + lc : 0.0;
     }
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
     for (int nd = 0; nd < K; ++nd) {
       const NodeConst nc = nodes[nd];
 #pragma unroll
-      for (int i = 0; i < kGenE; ++i) {
-        const int p = tid + i * nthr;
+      for (int i = 0; i < E; ++i) {
+        const int p = tl + i * nthr;
         if (p < n) {
           const double dre = nc.are - nc.gre * lam[i];
           const double dim = nc.aim - nc.gim * lam[i];
@@ -497,14 +506,16 @@ __global__ __launch_bounds__(512) void k_cols_gen(const cpx<R>* __restrict__ in,
             const float inv = (float)scale * recip(fr * fr + fi * fi);
             q = {fr * inv, -fi * inv};
           }
-          buf[p] = cmul(vh[i], q);
+          buf[(size_t)p * tc] = cmul(vh[i], q);
         }
       }
       __syncthreads();
-      fft_gen<R, +1>(buf, 1, gp, tw, tid);
-      const uint8_t* nn = need + (size_t)nd * n;
-      for (int p = tid; p < n; p += nthr)
-        if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[p];
+      fft_gen<R, +1, E>(buf, tc, gp, tw, tl);
+      if (act) {
+        const uint8_t* nn = need + (size_t)nd * n;
+        for (int p = tl; p < n; p += nthr)
+          if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[(size_t)p * tc];
+      }
     }
   }
 }
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(512) void k_cols_gen(const cpx<R>* __restrict__ in,
 // Pass C: inverse transform along rows of every node the row uses, and the
 // hat-weighted combine (weights 1-t on node A, t on node B of each point).
 template <typename R, typename TO, bool ACC>
-__global__ __launch_bounds__(512) void k_rows_combine_gen(const cpx<R>* __restrict__ fields, size_t fs,
+__global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<R>* __restrict__ fields, size_t fs,
                                                            size_t frs, const double* __restrict__ pos,
                                                            const uint64_t* __restrict__ rowmask,
                                                            cpx<TO>* __restrict__ out, size_t out_rs, int K, int M,
@@ -525,11 +536,11 @@ __global__ __launch_bounds__(512) void k_rows_combine_gen(const cpx<R>* __restri
   if (skip != nullptr && skip[rhs] != 0) return;
   const int n = gp.n, tid = threadIdx.x, nthr = gp.nthr;
   const size_t row = blockIdx.x, rbase = row * n;
-  int ab[kGenE];
-  R tt[kGenE];
-  cpx<R> acc[kGenE];
+  int ab[gen_e<R>()];
+  R tt[gen_e<R>()];
+  cpx<R> acc[gen_e<R>()];
 #pragma unroll
-  for (int i = 0; i < kGenE; ++i) {
+  for (int i = 0; i < gen_e<R>(); ++i) {
     const int p = tid + i * nthr;
     int A = -1, B = -1;
     double t = 0.0;
@@ -544,9 +555,9 @@ __global__ __launch_bounds__(512) void k_rows_combine_gen(const cpx<R>* __restri
     if (((rm >> nd) & 1ull) == 0) continue;
     for (int p = tid; p < n; p += nthr) buf[p] = fr[(size_t)nd * fs + p];
     __syncthreads();
-    fft_gen<R, +1>(buf, 1, gp, tw, tid);
+    fft_gen<R, +1, gen_e<R>()>(buf, 1, gp, tw, tid);
 #pragma unroll
-    for (int i = 0; i < kGenE; ++i) {
+    for (int i = 0; i < gen_e<R>(); ++i) {
       const int p = tid + i * nthr;
       if (p < n) {
         const int A = ab[i] & 0xff, B = (ab[i] >> 8) & 0xff;
@@ -559,7 +570,7 @@ __global__ __launch_bounds__(512) void k_rows_combine_gen(const cpx<R>* __restri
   }
   cpx<TO>* dst = out + (size_t)rhs * out_rs + rbase;
 #pragma unroll
-  for (int i = 0; i < kGenE; ++i) {
+  for (int i = 0; i < gen_e<R>(); ++i) {
     const int p = tid + i * nthr;
     if (p < n) {
       if constexpr (ACC) {
@@ -606,10 +617,11 @@ struct RowsFwdL {
 };
 
 // ---- mixed-radix launch helpers
-bool make_gen_plan(int n, GenPlan* gp) {
+bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp) {
   if (n < 2 || n > kGenMaxN) return false;
   GenPlan g{};
   g.n = n;
+  g.tc = 1;
   int m = n;
   auto take = [&](int r) {
     while (m % r == 0 && g.nst < kGenMaxStages) { g.radix[g.nst++] = r; m /= r; }
@@ -619,15 +631,34 @@ bool make_gen_plan(int n, GenPlan* gp) {
   take(3);
   take(5);
   if (m != 1) return false;
-  for (int t = 64; t <= 512; t += 64) {   // within the kernels' launch bounds
-    bool ok = (size_t)t * kGenE >= (size_t)n;
+  for (int t = 64; t <= maxthr; t += 64) {
+    bool ok = (size_t)t * E >= (size_t)n;
     for (int s = 0; s < g.nst && ok; ++s) {
       const int r = g.radix[s];
-      ok = (n / r + t - 1) / t <= kGenE / r;
+      ok = (n / r + t - 1) / t <= E / r;
     }
     if (ok) { g.nthr = t; *gp = g; return true; }
   }
   return false;
+}
+
+bool gen_length_ok(int n) {
+  GenPlan a, b, c;
+  return make_gen_plan(n, kGenRowE, 512, &a) && make_gen_plan(n, gen_e<double>(), gen_maxthr<double>(), &b) &&
+         make_gen_plan(n, gen_e<float>(), gen_maxthr<float>(), &c);
+}
+
+// Column passes: as many adjacent columns per workgroup as the thread limit and
+// the LDS (here up to 144 KiB, one workgroup per CU at most) allow, at most 8.
+template <typename R>
+static bool make_col_plan(int n, int S, GenPlan* gp) {
+  if (!make_gen_plan(n, gen_e<R>(), gen_maxthr<R>(), gp)) return false;
+  int tc = 1;
+  while (tc < 8 && (tc * 2) * gp->nthr <= gen_maxthr<R>() &&
+         (size_t)(tc * 2) * n * sizeof(cpx<R>) <= (size_t)144 * 1024 && tc * 2 <= S)
+    tc *= 2;
+  gp->tc = tc;
+  return true;
 }
 
 template <typename K>
@@ -648,24 +679,24 @@ static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int
 
 template <typename R>
 static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
-  dim3 grid(a.S, a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
+  const size_t lds = (size_t)gp.n * gp.tc * sizeof(cpx<R>);
+  dim3 grid((a.S + gp.tc - 1) / gp.tc, a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
   const cpx<R>* in = (const cpx<R>*)a.in;
   cpx<R>* out = (cpx<R>*)a.out;
   const cpx<R>* tw = (const cpx<R>*)a.tw;
   if (a.mode == 1) {
     allow_dynamic_lds(k_cols_gen<R, -1, 1>, lds);
-    hipLaunchKernelGGL((k_cols_gen<R, -1, 1>), grid, dim3(gp.nthr), lds, st, in, out, a.S, a.nfields, a.in_rs,
+    hipLaunchKernelGGL((k_cols_gen<R, -1, 1>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
                        a.store_need);
   } else if (a.dir < 0) {
     allow_dynamic_lds(k_cols_gen<R, -1, 0>, lds);
-    hipLaunchKernelGGL((k_cols_gen<R, -1, 0>), grid, dim3(gp.nthr), lds, st, in, out, a.S, a.nfields, a.in_rs,
+    hipLaunchKernelGGL((k_cols_gen<R, -1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
                        a.slab_need);
   } else {
     allow_dynamic_lds(k_cols_gen<R, +1, 0>, lds);
-    hipLaunchKernelGGL((k_cols_gen<R, +1, 0>), grid, dim3(gp.nthr), lds, st, in, out, a.S, a.nfields, a.in_rs,
+    hipLaunchKernelGGL((k_cols_gen<R, +1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
                        a.slab_need);
   }
@@ -687,7 +718,7 @@ hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, vo
                            hipStream_t st) {
   if (!is_pow2_len(n)) {
     GenPlan gp;
-    if (!make_gen_plan(n, &gp)) return hipErrorInvalidValue;
+    if (!make_gen_plan(n, kGenRowE, 512, &gp)) return hipErrorInvalidValue;
     if (real_kind == 0) {
       if (in_kind != 0) return hipErrorInvalidValue;
       return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
@@ -740,8 +771,8 @@ struct ColsL {
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st) {
   if (!is_pow2_len(a.n)) {
     GenPlan gp;
-    if (!make_gen_plan(a.n, &gp)) return hipErrorInvalidValue;
-    return a.real_kind == 0 ? cols_gen<double>(gp, a, st) : cols_gen<float>(gp, a, st);
+    if (a.real_kind == 0) return make_col_plan<double>(a.n, a.S, &gp) ? cols_gen<double>(gp, a, st) : hipErrorInvalidValue;
+    return make_col_plan<float>(a.n, a.S, &gp) ? cols_gen<float>(gp, a, st) : hipErrorInvalidValue;
   }
   if (a.real_kind == 0) return dispatch_n<ColsL<double>::F>(a.n, a, st);
   return dispatch_n<ColsL<float>::F>(a.n, a, st);
@@ -765,7 +796,9 @@ struct CombineL {
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
   if (!is_pow2_len(a.n)) {
     GenPlan gp;
-    if (!make_gen_plan(a.n, &gp)) return hipErrorInvalidValue;
+    if (a.real_kind == 0 ? !make_gen_plan(a.n, gen_e<double>(), gen_maxthr<double>(), &gp)
+                         : !make_gen_plan(a.n, gen_e<float>(), gen_maxthr<float>(), &gp))
+      return hipErrorInvalidValue;
     if (a.real_kind == 0) {
       if (a.out_kind != 0) return hipErrorInvalidValue;
       return a.accumulate ? combine_gen<double, double, true>(gp, a, st) : combine_gen<double, double, false>(gp, a, st);
