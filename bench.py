@@ -205,6 +205,9 @@ def example1(args, dev):
 
     betas = {f"M={m}": beta([(n, m) for n in args.ex1_sizes]) for m in (2, 4, 8)}
     betas["all"] = beta(list(table.keys()))
+    if len(args.ex1_sizes) >= 2:   # the two largest grids, where the GPU is full
+        big = sorted(args.ex1_sizes)[-2:]
+        betas.update({f"M={m},N>={big[0]}": beta([(n, m) for n in big]) for m in (2, 4, 8)})
     gm = []
     for n in args.ex1_gmres:
         w = inputs.workload("2d_inclusion", n=n, delta=1.0)
