@@ -37,14 +37,14 @@ class _Problem(C.Structure):
                 ("omega", C.c_double), ("c", C.c_void_p), ("a", C.c_void_p), ("zeta", C.c_void_p),
                 ("c0", C.c_double), ("m_real", C.c_int), ("m_layer", C.c_int), ("symbol", C.c_int),
                 ("a_floor", C.c_double), ("nodes_real", C.c_void_p), ("nodes_zeta", C.c_void_p),
-                ("a_nodes", C.c_void_p)]
+                ("a_nodes", C.c_void_p), ("interp_order", C.c_int)]
 
 
 class _Setup(C.Structure):
     _fields_ = [("M", C.c_int), ("Mt", C.c_int), ("K", C.c_int), ("mo", C.c_int),
                 ("cmin", C.c_double), ("cmax", C.c_double), ("zmax", C.c_double),
                 ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
-                ("gre", C.c_double * 64), ("gim", C.c_double * 64)]
+                ("gre", C.c_double * 64), ("gim", C.c_double * 64), ("order", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -87,7 +87,7 @@ class Problem:
 
     def __init__(self, shape, omega, c, a=None, zeta=None, length=1.0, c0=1.0, m_real=8,
                  m_layer=3, symbol="continuous", a_floor=0.0, nodes_real=None,
-                 nodes_zeta=None, a_nodes=None):
+                 nodes_zeta=None, a_nodes=None, interp_order=1):
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
         self.c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.shape)
@@ -109,6 +109,7 @@ class Problem:
         p.symbol = {"continuous": 0, "discrete": 1}[symbol]
         p.a_floor = float(a_floor)
         p.nodes_real, p.nodes_zeta, p.a_nodes = _addr(self.nodes_real), _addr(self.nodes_zeta), _addr(self.a_nodes)
+        p.interp_order = int(interp_order)
         self._p = p
         self.omega = float(omega)
         self.length = float(length)

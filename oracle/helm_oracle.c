@@ -62,6 +62,8 @@ typedef struct {
     const double* nodes_real;  /* optional explicit real nodes (length m_real)  */
     const double* nodes_zeta;  /* optional explicit zeta nodes (length m_layer) */
     const double* a_nodes;     /* optional damping at the real nodes            */
+    int interp_order;          /* real-axis interpolation: 1 (or 0) piecewise linear, 2 or 3
+                                  piecewise Lagrange of that degree                */
 } or_problem;
 
 /* Derived quantities of the preconditioner (filled by or_setup). */
@@ -75,6 +77,7 @@ typedef struct {
     double znode[65];      /* zeta_0 = 0, zeta_1..zeta_Mt     */
     double ahat[64];       /* symbol damping per node (K)     */
     double gre[64], gim[64]; /* gamma_n per node (K)          */
+    int order;             /* real-axis interpolation degree (1, 2 or 3) */
 } or_setup_t;
 
 static long npoints(const or_problem* p) {
@@ -320,13 +323,39 @@ static double hat(const double* t, int m, int idx, double x) {
     return 0.0;
 }
 
-/* Weights of all K nodes at one point, following Eqn. 405 with piecewise
- * linear bases phi_m (real nodes, functions of Re gamma) and varphi_j (layer
- * nodes, functions of Im gamma on the nodes -c_o zeta_j). */
+/* Higher-degree piecewise Lagrange basis on nodes t[0..m-1] (the other
+ * polynomial strategies the paper mentions in Sections 1 and 4.3): on the
+ * segment [t_s, t_{s+1}] holding x (clamped, s in [0, m-2]) the interpolant is the
+ * degree-p polynomial through the p+1 consecutive nodes starting at
+ * clamp(s - (p-1)/2, 0, m-1-p); basis function idx is its Lagrange factor for
+ * node idx (zero if idx is not among them).  Every such polynomial takes the node
+ * values at its nodes, so the interpolant is continuous and reproduces the nodes. */
+static double lagrange(const double* t, int m, int p, int idx, double x) {
+    if (m == 1) return 1.0;
+    if (p > m - 1) p = m - 1;
+    if (p <= 1) return hat(t, m, idx, x);
+    if (x < t[0]) x = t[0];
+    if (x > t[m - 1]) x = t[m - 1];
+    int sg = 0;
+    while (sg < m - 2 && t[sg + 1] <= x) ++sg;
+    int st = sg - (p - 1) / 2;
+    if (st < 0) st = 0;
+    if (st > m - 1 - p) st = m - 1 - p;
+    if (idx < st || idx > st + p) return 0.0;
+    double l = 1.0;
+    for (int k = st; k <= st + p; ++k)
+        if (k != idx) l *= (x - t[k]) / (t[idx] - t[k]);
+    return l;
+}
+
+/* Weights of all K nodes at one point, following Eqn. 405 with bases phi_m
+ * (real nodes, functions of Re gamma: piecewise linear, or Lagrange of degree
+ * s->order) and piecewise linear varphi_j (layer nodes, functions of Im gamma on
+ * the nodes -c_o zeta_j). */
 void or_point_weights(const or_setup_t* s, double c0, double cval, double zval, double* w) {
     double re = cval, im = -cval * zval;
     if (s->Mt == 0) {
-        for (int m = 0; m < s->M; ++m) w[m] = hat(s->cnode, s->M, m, re);
+        for (int m = 0; m < s->M; ++m) w[m] = lagrange(s->cnode, s->M, s->order, m, re);
         return;
     }
     /* varphi_j live on Im gamma in [-c_o zeta_max, 0]; use increasing nodes. */
@@ -334,14 +363,16 @@ void or_point_weights(const or_setup_t* s, double c0, double cval, double zval, 
     double tz[65];
     for (int j = 0; j < nz; ++j) tz[j] = -c0 * s->znode[nz - 1 - j];
     double phi0 = hat(tz, nz, nz - 1, im);
-    for (int m = 0; m < s->M; ++m) w[m] = hat(s->cnode, s->M, m, re) * phi0;
-    double phimo = hat(s->cnode, s->M, s->mo, re);
+    for (int m = 0; m < s->M; ++m) w[m] = lagrange(s->cnode, s->M, s->order, m, re) * phi0;
+    double phimo = lagrange(s->cnode, s->M, s->order, s->mo, re);
     for (int j = 1; j <= s->Mt; ++j) w[s->M + j - 1] = phimo * hat(tz, nz, nz - 1 - j, im);
 }
 
 /* Set up nodes, per-node damping and per-node complex speed. */
 int or_setup(const or_problem* p, or_setup_t* s) {
     memset(s, 0, sizeof(*s));
+    if (p->interp_order < 0 || p->interp_order > 3) return OR_E_INVALID;
+    s->order = p->interp_order < 1 ? 1 : p->interp_order;
     if (p->dim < 1 || p->dim > 3) return OR_E_SHAPE;
     /* even lengths (the frequency range -N/2..N/2-1 of reading A3) */
     for (int d = 0; d < p->dim; ++d) if (p->n[d] < 2 || p->n[d] % 2 || !(p->len[d] > 0)) return OR_E_SHAPE;

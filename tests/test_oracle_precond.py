@@ -248,3 +248,52 @@ def test_odd_lengths_rejected(orc):
     with pytest.raises(orc.OracleError):
         orc.Problem((15, 16), 10.0, c, None, None, m_real=2).setup()
     orc.Problem((18, 16), 10.0, np.ones((18, 16)), None, None, m_real=2, a_floor=1.0).setup()
+
+
+# ---------------------------------------------------------------- higher-degree interpolation
+@pytest.mark.parametrize("order", [2, 3])
+def test_lagrange_weights_reproduce_polynomials(orc, order):
+    """Degree-p piecewise Lagrange weights: node values are reproduced, every polynomial in
+    Re gamma of degree <= p is reproduced exactly, the weights are continuous across the
+    segment ends, and in the layer (Re gamma = c_o, a node) they equal the linear ones."""
+    shape, c, zeta = _layer_medium()
+    omega = 2 * np.pi * 4
+    kw = dict(m_real=7, m_layer=3)
+    p = orc.Problem(shape, omega, c, np.full(shape, 3.0), zeta, interp_order=order, **kw)
+    lin = orc.Problem(shape, omega, c, np.full(shape, 3.0), zeta, **kw)
+    st = p.setup()
+    M, K, nodes = st["M"], st["K"], st["cnode"]
+    for m, cn in enumerate(nodes):
+        e = np.zeros(K)
+        e[m] = 1
+        assert np.abs(p.weights(cn, 0.0) - e).max() < 1e-14
+    rng = np.random.default_rng(order)
+    for cv in rng.uniform(st["cmin"], st["cmax"], 200):
+        w = p.weights(cv, 0.0)[:M]
+        assert np.count_nonzero(w) <= order + 1
+        for deg in range(order + 1):
+            assert abs(np.dot(w, nodes ** deg) - cv ** deg) < 1e-13 * max(1.0, cv ** deg), (deg, cv)
+    for cn in nodes[1:-1]:
+        d = np.abs(p.weights(cn - 1e-12, 0.0) - p.weights(cn + 1e-12, 0.0)).max()
+        assert d < 1e-9, (cn, d)
+    for zv in rng.uniform(0, st["zmax"], 20):
+        assert np.abs(p.weights(1.0, zv) - lin.weights(1.0, zv)).max() < 1e-15
+
+
+@pytest.mark.parametrize("order,lo,hi", [(2, 5.0, 11.0), (3, 10.0, 22.0)])
+def test_lagrange_interpolation_error_rate(orc, order, lo, hi):
+    """The interpolation error of Q_M against the exact operator Q falls by about 2^(p+1) per
+    halving of the node spacing for degree-p pieces (Lemma 3's argument at higher degree)."""
+    n = 32
+    shape = (n, n)
+    xs = inputs.mesh(shape)
+    c = 1.0 + 0.3 * np.exp(-(xs[0] ** 2 + xs[1] ** 2) / 0.05)
+    omega = 2 * np.pi * 4
+    a = np.full(shape, 0.5 * omega)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    Qv = orc.Problem(shape, omega, c, a, m_real=2).exact_psdo(v)
+    Ms = [5, 9, 17]
+    err = [rel(orc.Problem(shape, omega, c, a, m_real=M, interp_order=order).apply(v), Qv) for M in Ms]
+    ratios = np.array(err[:-1]) / np.array(err[1:])
+    assert np.all(ratios > lo) and np.all(ratios < hi), (order, err, ratios)
