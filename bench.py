@@ -237,6 +237,38 @@ def example1(args, dev):
                       "beta": betas, "gmres_100_iterations": gm}))
 
 
+def interp_compare(args, dev):
+    """Real-axis interpolation degree against node count on the 1024^2 random medium (FP64,
+    rtol 1e-8): piecewise linear with 16 real nodes (the paper's basis) against piecewise
+    quadratic and cubic Lagrange with fewer nodes; apply time, iterations, solves/s."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    w = inputs.workload("2d_1024_grf")
+    f = torch.from_numpy(w.f).to(dev)
+    rng = np.random.default_rng(0)
+    v = torch.from_numpy(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape))[None].to(dev)
+    rows = []
+    for order, m in [(1, 16), (1, 8), (2, 8), (3, 8), (3, 6), (3, 4)]:
+        p = binding.plan_from_workload(w, m_real=m, interp_order=order)
+        p.solve(f)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            x, info = p.solve(f)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / 3
+        ms, by = p.profile_apply(v, reps=10)
+        row = {"order": order, "m_real": m, "K": p.info()["K"], "iters": info[0].iters,
+               "rel_true_residual": info[0].rel_true_residual, "solves_per_s": 1.0 / dt,
+               "apply_us": sum(ms) * 1e3, "pass_us": [round(t_ * 1e3, 1) for t_ in ms]}
+        print(f"[bench] interp order {order} M={m}: {row['iters']} iters, {row['solves_per_s']:.1f} solves/s, "
+              f"apply {row['apply_us']:.0f} us", file=sys.stderr, flush=True)
+        rows.append(row)
+        p.close()
+        del x
+    print(json.dumps({"mode": "interp", "workload": w.name, "rows": rows}))
+
+
 def apply_only(args, w, plan, dev):
     import numpy as np
     import torch
@@ -277,10 +309,11 @@ def main():
     ap.add_argument("--nrhs3d", type=int, default=16)
     ap.add_argument("--ex1-sizes", type=int, nargs="+", default=[180, 360, 720, 1440, 2880])
     ap.add_argument("--ex1-gmres", type=int, nargs="*", default=[2400, 3600, 4800])
-    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp"], default="solve",
                     help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
                          "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch; "
-                         "example1: the paper's Example 1 (Table 1 complexity, GMRES comparison)")
+                         "example1: the paper's Example 1 (Table 1 complexity, GMRES comparison); "
+                         "interp: interpolation degree against node count")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -299,6 +332,9 @@ def main():
         return
     if args.mode == "example1":
         example1(args, dev)
+        return
+    if args.mode == "interp":
+        interp_compare(args, dev)
         return
     w = inputs.workload(args.workload)
     if args.precision:

@@ -80,7 +80,11 @@ typedef struct {
  *              Arnoldi stencil in FP32; orthogonalisation, least squares, true
  *              residual and set-up in FP64)
  *   max_nrhs   largest batch one apply/matvec call processes at once (>= 1);
- *              larger batches are processed in chunks                          */
+ *              larger batches are processed in chunks
+ *   interp_order  real-axis interpolation: 0 or 1 piecewise linear (Section
+ *              4.1), 2 or 3 piecewise Lagrange of that degree through
+ *              consecutive nodes (the other polynomial bases of Sections 1
+ *              and 4.3; capped at M - 1); the layer leg stays linear           */
 typedef struct {
   int m_real;
   int m_layer;
@@ -91,6 +95,7 @@ typedef struct {
   int symbol;
   int precision;
   int max_nrhs;
+  int interp_order;
 } hp_plan_opts;
 
 /* Restarted GMRES(restart) on P_N x = f, starting from the x passed in.
@@ -130,6 +135,7 @@ typedef struct {
   double gamma_re[64], gamma_im[64];  /* node speeds gamma_n (K) */
   size_t workspace_bytes;    /* device bytes held by the plan for apply/matvec */
   int precision;
+  int interp_order;          /* real-axis interpolation degree in effect */
 } hp_plan_info;
 
 /* Build a plan: upload and validate the media, place the nodes, and compute in

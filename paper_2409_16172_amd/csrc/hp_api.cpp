@@ -55,6 +55,8 @@ struct hp_plan_s {
   double cnode[64] = {0}, znode[65] = {0}, ahat[64] = {0}, gre[64] = {0}, gim[64] = {0};
   // device data
   DevBuf nodes, pos, grpmask, rowmask, slabneed, storemask, coef64, coef32, lam_ax, lam_in, tw64[3], tw32[3];
+  int order = 1;   // real-axis interpolation degree in effect
+  DevBuf lagtab;   // Lagrange table of CombineArgs::lag (order >= 2)
   // node usage counts for the byte model of the passes
   double rows_used = 0;    // sum over pass-C rows of the nodes the row uses
   double slabs_used = 0;   // sum over nodes of the axis-0 indices that use the node
@@ -66,7 +68,8 @@ struct hp_plan_s {
   size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
   const void* tw(int axis) const { return prec == HP_FP64 ? tw64[axis].p : tw32[axis].p; }
   void release_all() {
-    for (DevBuf* b : {&nodes, &pos, &grpmask, &rowmask, &slabneed, &storemask, &coef64, &coef32, &lam_ax, &lam_in, &t, &fields})
+    for (DevBuf* b : {&nodes, &pos, &grpmask, &rowmask, &slabneed, &storemask, &coef64, &coef32, &lam_ax, &lam_in, &t,
+                      &fields, &lagtab})
       b->release();
     for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
     release_solver_ws();
@@ -356,13 +359,35 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     if (layer_bad) return failc(HP_E_LAYER);
   }
   P->K = P->M + P->Mt;
+  // real-axis interpolation: piecewise linear (Section 4.1), or piecewise Lagrange of
+  // degree 2 or 3 on consecutive nodes (at most M - 1)
+  if (opts->interp_order < 0 || opts->interp_order > 3) return failc(HP_E_INVALID);
+  P->order = std::max(1, std::min(opts->interp_order, P->M - 1));
   hp::NodeTable T{};
   T.M = P->M;
   T.Mt = P->Mt;
   T.mo = P->mo;
   T.has_layer = has_layer ? 1 : 0;
+  T.order = P->order;
   for (int i = 0; i < P->M; ++i) T.cnode[i] = P->cnode[i];
   for (int i = 0; i <= P->Mt; ++i) T.znode[i] = P->znode[i];
+  {
+    // node positions, then 1 / prod_{k != n} (c_n - c_k) over the stencil starting at n - r
+    std::vector<double> lag(hp::kLagTable, 0.0);
+    for (int i = 0; i < P->M; ++i) lag[i] = P->cnode[i];
+    if (P->order >= 2) {
+      for (int nn = 0; nn < P->M; ++nn)
+        for (int r = 0; r <= P->order; ++r) {
+          const int a = nn - r;
+          if (a < 0 || a > P->M - 1 - P->order) continue;
+          double den = 1.0;
+          for (int k = a; k <= a + P->order; ++k)
+            if (k != nn) den *= P->cnode[nn] - P->cnode[k];
+          lag[hp::kMaxNodes + 4 * nn + r] = 1.0 / den;
+        }
+    }
+    if ((e = upload(P->lagtab, lag)) != hipSuccess) return failc(from_hip(e));
+  }
 
   // per-point records and stencil coefficients {gamma^2, beta} (Section 5 with
   // the complex speed of Section 4.4), in FP64 on the device
@@ -534,6 +559,7 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info) {
   for (int i = 0; i < 65; ++i) info->znode[i] = p->znode[i];
   info->workspace_bytes = p->t.bytes + p->fields.bytes + p->pos.bytes + p->coef64.bytes + p->coef32.bytes;
   info->precision = p->prec;
+  info->interp_order = p->order;
   return HP_OK;
 }
 
@@ -600,6 +626,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   c.fields = P->fields.p; c.fs = np; c.frs = np * P->K; c.pos = (const double*)P->pos.p;
   c.grpmask = (const uint64_t*)P->grpmask.p; c.rowmask = (const uint64_t*)P->rowmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
   c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
+  c.order = P->order; c.lag = (const double*)P->lagtab.p;
   for (int r = 0; r < (acc ? 1 : reps); ++r)
     if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
   return mark(5);

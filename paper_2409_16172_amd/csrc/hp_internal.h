@@ -118,7 +118,11 @@ struct CombineArgs {
   int rows, K, M, Mt, mo, nrhs;
   const void* tw;
   const int* skip;
+  int order;           // real-axis interpolation degree in effect (1 = piecewise linear)
+  const double* lag;   // order >= 2: real nodes [0, kMaxNodes), then for node n and stencil
+                       // start n - r the inverse Lagrange denominator at kMaxNodes + 4n + r
 };
+constexpr int kLagTable = kMaxNodes * 5;
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
 int combine_group_rows(int real_kind, int n);        // rows per workgroup of pass C
 int symbol_pass_line_threads(int real_kind, int n);  // threads per line T of pass B
@@ -184,6 +188,7 @@ hipError_t launch_media_scan(const double* c, const double* a, const double* zet
 
 struct NodeTable {
   int M, Mt, mo, has_layer;
+  int order;   // real-axis interpolation degree in effect (1 = piecewise linear, else Lagrange)
   double cnode[kMaxNodes];
   double znode[kMaxNodes + 1];
 };

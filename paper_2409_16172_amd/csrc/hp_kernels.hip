@@ -239,16 +239,57 @@ __device__ __forceinline__ void decode_pos(double p, int M, int Mt, int mo, int&
   }
 }
 
-template <typename R, typename TO, int N, bool ACC>
+// Per-point record for the combine: `ab` packs nodes A, B (piecewise linear:
+// weights 1-t, t) or, for a real-axis point under Lagrange interpolation of degree
+// ord >= 2, the first node A of its ord+1-node stencil and a flag; `tt` holds t,
+// or the point's speed x for the Lagrange weights.  lag: the table of CombineArgs.
+template <typename R, bool LAG>
+__device__ __forceinline__ void interp_record(double pv, int M, int Mt, int mo, int ord, const double* lag, int& ab,
+                                              R& tt) {
+  int A = -1, B = -1;
+  double t = 0.0;
+  decode_pos(pv, M, Mt, mo, A, B, t);
+  if (LAG && pv >= 0.0 && M > 1) {
+    int a = A - (ord - 1) / 2;
+    a = a < 0 ? 0 : (a > M - 1 - ord ? M - 1 - ord : a);
+    ab = a | (1 << 16);
+    tt = (R)(lag[A] + t * (lag[A + 1] - lag[A]));
+  } else {
+    ab = (A & 0xff) | ((B & 0xff) << 8);
+    tt = (R)t;
+  }
+}
+
+// Weight of node n at a point with record (ab, tt).
+template <typename R, bool LAG>
+__device__ __forceinline__ R interp_weight(int ab, R tt, int n, int ord, const double* lag) {
+  const int A = ab & 0xff;
+  if (LAG && (ab >> 16)) {
+    if (n < A || n > A + ord) return (R)0;
+    R w = (R)lag[kMaxNodes + 4 * n + (n - A)];
+    for (int k = A; k <= A + ord; ++k)
+      if (k != n) w *= tt - (R)lag[k];
+    return w;
+  }
+  const int B = (ab >> 8) & 0xff;
+  return (A == n ? (R)1 - tt : (R)0) + (B == n ? tt : (R)0);
+}
+
+template <typename R, typename TO, int N, bool ACC, bool LAG>
 __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
     const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
     size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
-    const int* __restrict__ skip) {
+    const int* __restrict__ skip, int ord, const double* __restrict__ lag) {
   using C = CombCfg<R, N>;
   __shared__ cpx<R> lds[C::LDS];
+  __shared__ double slag[LAG ? kLagTable : 1];
   const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
+  if constexpr (LAG) {
+    for (int i = threadIdx.x; i < kLagTable; i += C::THREADS) slag[i] = lag[i];
+    __syncthreads();
+  }
   const int g = threadIdx.x / C::T, j = threadIdx.x % C::T;
   const int row = blockIdx.x * C::G + g;
   const bool act = row < rows;
@@ -258,11 +299,9 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
   cpx<R> acc[C::E];
 #pragma unroll
   for (int s = 0; s < C::E; ++s) {
-    int A = -1, B = -1;
-    double t = 0.0;
-    if (act) decode_pos(pos[rbase + j + C::T * s], M, Mt, mo, A, B, t);
-    ab[s] = (A & 0xff) | ((B & 0xff) << 8);
-    tt[s] = (R)t;
+    ab[s] = 0xffff;
+    tt[s] = (R)0;
+    if (act) interp_record<R, LAG>(pos[rbase + j + C::T * s], M, Mt, mo, ord, slag, ab[s], tt[s]);
     acc[s] = {0, 0};
   }
   const uint64_t mask = grpmask[blockIdx.x];
@@ -304,8 +343,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
     fft<R, N, +1, true>(x, lg, j, tw);
 #pragma unroll
     for (int s = 0; s < C::E; ++s) {
-      const int A = ab[s] & 0xff, B = (ab[s] >> 8) & 0xff;
-      const R w = (A == n ? (R)1 - tt[s] : (R)0) + (B == n ? tt[s] : (R)0);
+      const R w = interp_weight<R, LAG>(ab[s], tt[s], n, ord, slag);
       acc[s].re += w * x[s].re;
       acc[s].im += w * x[s].im;
     }
@@ -522,19 +560,25 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
 
 // Pass C: inverse transform along rows of every node the row uses, and the
 // hat-weighted combine (weights 1-t on node A, t on node B of each point).
-template <typename R, typename TO, bool ACC>
+template <typename R, typename TO, bool ACC, bool LAG>
 __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<R>* __restrict__ fields, size_t fs,
                                                            size_t frs, const double* __restrict__ pos,
                                                            const uint64_t* __restrict__ rowmask,
                                                            cpx<TO>* __restrict__ out, size_t out_rs, int K, int M,
                                                            int Mt, int mo, GenPlan gp,
                                                            const cpx<R>* __restrict__ tw,
-                                                           const int* __restrict__ skip) {
+                                                           const int* __restrict__ skip, int ord,
+                                                           const double* __restrict__ lag) {
   extern __shared__ char dyn_lds[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
+  __shared__ double slag[LAG ? kLagTable : 1];
   const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
   const int n = gp.n, tid = threadIdx.x, nthr = gp.nthr;
+  if constexpr (LAG) {
+    for (int i = tid; i < kLagTable; i += nthr) slag[i] = lag[i];
+    __syncthreads();
+  }
   const size_t row = blockIdx.x, rbase = row * n;
   int ab[gen_e<R>()];
   R tt[gen_e<R>()];
@@ -542,11 +586,9 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
 #pragma unroll
   for (int i = 0; i < gen_e<R>(); ++i) {
     const int p = tid + i * nthr;
-    int A = -1, B = -1;
-    double t = 0.0;
-    if (p < n) decode_pos(pos[rbase + p], M, Mt, mo, A, B, t);
-    ab[i] = (A & 0xff) | ((B & 0xff) << 8);
-    tt[i] = (R)t;
+    ab[i] = 0xffff;
+    tt[i] = (R)0;
+    if (p < n) interp_record<R, LAG>(pos[rbase + p], M, Mt, mo, ord, slag, ab[i], tt[i]);
     acc[i] = {0, 0};
   }
   const uint64_t rm = rowmask[row];
@@ -560,8 +602,7 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
     for (int i = 0; i < gen_e<R>(); ++i) {
       const int p = tid + i * nthr;
       if (p < n) {
-        const int A = ab[i] & 0xff, B = (ab[i] >> 8) & 0xff;
-        const R w = (A == nd ? (R)1 - tt[i] : (R)0) + (B == nd ? tt[i] : (R)0);
+        const R w = interp_weight<R, LAG>(ab[i], tt[i], nd, ord, slag);
         const cpx<R> x = buf[p];
         acc[i].re += w * x.re;
         acc[i].im += w * x.im;
@@ -703,14 +744,18 @@ static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st)
   return hipGetLastError();
 }
 
+template <typename R, typename TO, bool ACC, bool LAG>
+static hipError_t combine_gen_l(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
+  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
+  allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC, LAG>, lds);
+  hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC, LAG>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
+                     (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
+                     a.Mt, a.mo, gp, (const cpx<R>*)a.tw, a.skip, a.order, a.lag);
+  return hipGetLastError();
+}
 template <typename R, typename TO, bool ACC>
 static hipError_t combine_gen(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
-  allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC>, lds);
-  hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
-                     (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
-                     a.Mt, a.mo, gp, (const cpx<R>*)a.tw, a.skip);
-  return hipGetLastError();
+  return a.order >= 2 ? combine_gen_l<R, TO, ACC, true>(gp, a, st) : combine_gen_l<R, TO, ACC, false>(gp, a, st);
 }
 
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
@@ -785,9 +830,14 @@ struct CombineL {
     static hipError_t run(const CombineArgs& a, hipStream_t st) {
       using C = CombCfg<R, N>;
       dim3 grid((a.rows + C::G - 1) / C::G, a.nrhs);
-      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC>), grid, dim3(C::THREADS), 0, st,
-                         (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
-                         a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip);
+      if (a.order >= 2)
+        hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, true>), grid, dim3(C::THREADS), 0, st,
+                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                           a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag);
+      else
+        hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, false>), grid, dim3(C::THREADS), 0, st,
+                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                           a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag);
       return hipGetLastError();
     }
   };
@@ -1631,7 +1681,14 @@ __global__ __launch_bounds__(256) void k_row_masks(const double* __restrict__ po
   for (int i = threadIdx.x; i < nl; i += 256) {
     int A, B;
     double t;
-    decode_pos(pos[row * nl + i], T.M, T.Mt, T.mo, A, B, t);
+    const double pv = pos[row * nl + i];
+    decode_pos(pv, T.M, T.Mt, T.mo, A, B, t);
+    if (T.order >= 2 && pv >= 0.0 && T.M > 1) {   // the whole Lagrange stencil
+      int a = A - (T.order - 1) / 2;
+      a = a < 0 ? 0 : (a > T.M - 1 - T.order ? T.M - 1 - T.order : a);
+      for (int k = a; k <= a + T.order; ++k) m |= 1ull << k;
+      continue;
+    }
     if (A == B || t != 1.0) m |= 1ull << A;
     if (A != B && t != 0.0) m |= 1ull << B;
   }
