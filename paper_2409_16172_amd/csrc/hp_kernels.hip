@@ -11,6 +11,7 @@
 //           non-zero piecewise-linear weights of each point  K fields -> u
 // d = 3 adds the forward and inverse transforms along the middle axis as plain
 // strided passes (A' and M) between A/B and B/C.
+#include <algorithm>
 #include <type_traits>
 
 #include "hp_internal.h"
@@ -25,7 +26,7 @@ __device__ __forceinline__ cpx<R> cvt(cpx<S> a) {
 // Rows (contiguous axis): G lines of length N per workgroup of 256 threads
 // (one line per workgroup when a line needs 256 threads or more).
 #ifndef HP_ROWC_THREADS
-#define HP_ROWC_THREADS 128
+#define HP_ROWC_THREADS 64
 #endif
 #ifndef HP_PREFETCH_C
 #define HP_PREFETCH_C 0
@@ -172,7 +173,10 @@ __global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
 #endif
   const int c = tile * C::TC + g;
   const bool act = c < S;
-  const size_t obase = (size_t)blockIdx.y * N * S + c;
+  // MODE 0: blockIdx.y is the outer (slab) index.  MODE 1 (outer = 1): blockIdx.y
+  // is the node group; small grids split the nodes over several workgroups per
+  // column tile (each redoes the forward transform) so that the launch fills the GPU.
+  const size_t obase = (MODE == 0 ? (size_t)blockIdx.y * N * S : 0) + c;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
   cpx<R>* lg = lds + g;   // the TC columns are interleaved in LDS
   // Symbol pass: the store masks of all nodes are staged in LDS up front, so that
@@ -205,7 +209,8 @@ __global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
       lam[s] = lam_ax[j + C::T * s] + lc;
     }
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
-    for (int n = 0; n < K; ++n) {
+    const int n_lo = (int)(((long)blockIdx.y * K) / gridDim.y), n_hi = (int)(((long)(blockIdx.y + 1) * K) / gridDim.y);
+    for (int n = n_lo; n < n_hi; ++n) {
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
       fft_e<R, N, C::E, +1, false, C::TC>(x, lg, j, tw);
       // bit s: some point of axis-0 index j + T*s uses node n (else the row is never read)
@@ -791,7 +796,10 @@ struct ColsL {
         return hipErrorInvalidValue;   // the FP64 column tile would not fit in LDS
       } else {
         const int TC = a.mode == 1 ? C1::TC : C0::TC;
-        dim3 grid((a.S + TC - 1) / TC, a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
+        const int tiles = (a.S + TC - 1) / TC;
+        // symbol pass: node groups so that at least ~512 workgroups run (small grids)
+        const int ng = a.mode == 1 ? std::max(1, std::min(a.K, (512 + tiles - 1) / tiles)) : 1;
+        dim3 grid(tiles, a.mode == 1 ? ng : a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
         const cpx<R>* in = (const cpx<R>*)a.in;
         cpx<R>* out = (cpx<R>*)a.out;
         const cpx<R>* tw = (const cpx<R>*)a.tw;
