@@ -172,12 +172,12 @@ class Problem:
             raise OracleError(rc, "exact_psdo")
         return u
 
-    def arnoldi(self, v0, m, side="right"):
+    def arnoldi(self, v0, m, side="right", reorth=False):
         v0 = np.ascontiguousarray(v0, dtype=np.complex128).reshape(self.shape)
         V = np.zeros((m + 1,) + self.shape, dtype=np.complex128)
         H = np.zeros((m + 1, m), dtype=np.complex128)
         steps = C.c_int(0)
-        rc = lib().or_arnoldi(C.byref(self._p), C.c_int(_SIDE[side]), C.c_int(m), _ptr(v0),
+        rc = lib().or_arnoldi(C.byref(self._p), C.c_int(_SIDE[side]), C.c_int(m), C.c_int(int(reorth)), _ptr(v0),
                               _ptr(V), _ptr(H), C.byref(steps))
         if rc:
             raise OracleError(rc, "arnoldi")

@@ -612,8 +612,13 @@ static int krylov_op(const or_problem* p, int side, const cx* v, cx* w, cx* tmp)
 
 /* One Arnoldi process of m steps from v0 (normalised inside); returns the
  * basis V (m+1 vectors) and the (m+1) x m Hessenberg H (row-major, ld m).
- * Used directly by the invariant tests. */
-int or_arnoldi(const or_problem* p, int side, int m, const cx* v0, cx* V, cx* H, int* steps) {
+ * reorth = 1 repeats the Gram-Schmidt sweep once against the whole basis and
+ * adds its coefficients to H (unconditional reorthogonalisation, as the
+ * Arnoldi eigensolvers behind the condition numbers of Eqn. Cond use): the
+ * basis then stays orthonormal to rounding after Ritz values have converged,
+ * where one modified Gram-Schmidt sweep loses orthogonality.
+ * Used directly by the invariant tests and the spectral diagnostics. */
+int or_arnoldi(const or_problem* p, int side, int m, int reorth, const cx* v0, cx* V, cx* H, int* steps) {
     long np = npoints(p);
     cx* tmp = (cx*)malloc(sizeof(cx) * (size_t)np);
     if (!tmp) return OR_E_NOMEM;
@@ -629,6 +634,13 @@ int or_arnoldi(const or_problem* p, int side, int m, const cx* v0, cx* V, cx* H,
             cx hij = dotc(np, V + (long)i * np, w);
             H[(long)i * m + j] = hij;
             for (long t = 0; t < np; ++t) w[t] -= hij * V[(long)i * np + t];
+        }
+        if (reorth) {
+            for (int i = 0; i <= j; ++i) {
+                cx d = dotc(np, V + (long)i * np, w);
+                H[(long)i * m + j] += d;
+                for (long t = 0; t < np; ++t) w[t] -= d * V[(long)i * np + t];
+            }
         }
         double hn = nrm2(np, w);
         H[(long)(j + 1) * m + j] = hn;
