@@ -269,6 +269,86 @@ def interp_compare(args, dev):
     print(json.dumps({"mode": "interp", "workload": w.name, "rows": rows}))
 
 
+def spectrum(args, dev):
+    """Spectral condition numbers of Eqn. Cond (Section 5) on the Example 1 media, the
+    sweeps of Tables 2-6: frequency (PPW 12), points per wavelength (omega = 80 pi),
+    contrast delta, smoothness eta and damping a (N = 480, omega = 80 pi), each for P_N and
+    Q_{N,M} P_N with the real node counts args.spec_nodes, on grids up to args.spec_max_n.  Both ends of
+    the spectrum by explicitly restarted GPU Arnoldi runs from a seeded random start: the
+    largest modulus from runs of args.spec_m steps on the operator, the smallest from runs
+    of args.spec_m_inv steps on its inverse (inner GMRES solves), each restarted from the
+    wanted Ritz vector until its relative residual is <= args.spec_tol or after
+    args.spec_restarts restarts; non-converged ends are flagged.  For P_N (no layer, real
+    c, constant a) every eigenvalue has imaginary part omega a (c^2 times the Laplacian is
+    similar to a real symmetric matrix), so omega a bounds the smallest modulus from below;
+    P_N's row reports max |lambda| / (omega a), an upper bound on its condition number,
+    unless args.spec_pn_inverse asks for inverse runs (slow: its smallest eigenvalues are
+    clustered)."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    m = args.spec_m
+    base = dict(ppw=12.0, delta=4.0, eta=1.0 / 800, a=20.0)
+    sweeps = {
+        "table2_frequency": [(f"omega={k}pi", dict(n=6 * k)) for k in (20, 40, 80, 160, 320)],
+        "table3_ppw": [(f"PPW={q}", dict(n=40 * q, ppw=float(q))) for q in (4, 6, 12, 24, 48)],
+        "table4_contrast": [(f"delta={d}", dict(n=480, delta=float(d))) for d in (1, 2, 4, 8, 16)],
+        "table5_smoothness": [(f"eta=1/{e}", dict(n=480, eta=1.0 / e)) for e in (200, 400, 800, 1600, 3200)],
+        "table6_damping": [(f"a={a}", dict(n=480, a=float(a))) for a in (5, 10, 20, 40, 80)],
+    }
+    rows = [("P_N", 1, "none")] + [(f"Q_{mm}P_N", mm, "left") for mm in args.spec_nodes]
+    out = {}
+    total_t = 0.0
+    runs = 0
+    for tname, cols in sweeps.items():
+        if args.spec_tables and tname.split("_")[0] not in args.spec_tables:
+            continue
+        tab = {}
+        for cname, over in cols:
+            if over["n"] > args.spec_max_n:
+                continue
+            kw = dict(base)
+            kw.update(over)
+            w = inputs.workload("2d_inclusion", m_real=1, **kw)
+            rng = np.random.default_rng(7)
+            v0 = torch.from_numpy(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape)).to(dev)
+            for rname, mm, side in rows:
+                # P_N's own spectrum does not depend on the plan's nodes; 8 of them speed up
+                # the inner solves of its inverse
+                p = binding.plan_from_workload(w, m_real=mm if side != "none" else 8)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                hi = p.extreme_eigenvalue(v0, False, side, m, args.spec_restarts, args.spec_tol)
+                if side == "none" and not args.spec_pn_inverse:
+                    # every eigenvalue of P_N has imaginary part omega a: min |lambda| >= omega a
+                    lo = (complex(0.0, w.omega * kw["a"]), float("nan"), 0, False)
+                else:
+                    lo = p.extreme_eigenvalue(v0, True, side, args.spec_m_inv, args.spec_restarts, args.spec_tol)
+                dt = time.perf_counter() - t
+                cond = abs(hi[0]) / abs(lo[0])
+                det = {"max": hi[0], "min": lo[0], "max_rel_resid": hi[1], "min_rel_resid": lo[1],
+                       "runs": hi[2] + lo[2], "converged": hi[3] and lo[3]}
+                total_t += dt
+                runs += det["runs"]
+                e = {"cond": cond, "max_abs": abs(det["max"]), "min_abs": abs(det["min"]),
+                     "max_rel_resid": det["max_rel_resid"], "min_rel_resid": det["min_rel_resid"],
+                     "converged": det["converged"], "arnoldi_runs": det["runs"], "seconds": dt}
+                if side == "none":
+                    e["omega_a"] = w.omega * kw["a"]
+                    e["cond_upper_bound"] = abs(det["max"]) / e["omega_a"]
+                    e["min_is_bound"] = not args.spec_pn_inverse
+                tab.setdefault(rname, {})[cname] = e
+                print(f"[bench] spectrum {tname} {cname} N={w.shape[0]} {rname}: cond {cond:.3g} "
+                      f"(|lambda| in [{e['min_abs']:.4g}, {e['max_abs']:.4g}], residuals "
+                      f"{e['min_rel_resid']:.1e}/{e['max_rel_resid']:.1e}, {det['runs']} runs, {dt:.2f} s)",
+                      file=sys.stderr, flush=True)
+                p.close()
+            del v0
+        out[tname] = tab
+    print(json.dumps({"mode": "spectrum", "arnoldi_steps": m, "tol": args.spec_tol,
+                      "max_restarts": args.spec_restarts, "arnoldi_runs": runs, "seconds": total_t,
+                      "estimates": out}))
+
+
 def apply_only(args, w, plan, dev):
     import numpy as np
     import torch
@@ -309,11 +389,22 @@ def main():
     ap.add_argument("--nrhs3d", type=int, default=16)
     ap.add_argument("--ex1-sizes", type=int, nargs="+", default=[180, 360, 720, 1440, 2880])
     ap.add_argument("--ex1-gmres", type=int, nargs="*", default=[2400, 3600, 4800])
-    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp"], default="solve",
+    ap.add_argument("--spec-m", type=int, default=64, help="Arnoldi steps per run")
+    ap.add_argument("--spec-tol", type=float, default=1e-4, help="relative residual of a converged end")
+    ap.add_argument("--spec-restarts", type=int, default=10)
+    ap.add_argument("--spec-m-inv", type=int, default=16, help="Arnoldi steps per run on the inverse")
+    ap.add_argument("--spec-max-n", type=int, default=480, help="largest grid of the sweeps")
+    ap.add_argument("--spec-pn-inverse", action="store_true",
+                    help="estimate min |lambda(P_N)| by inverse runs instead of the bound omega a")
+    ap.add_argument("--spec-nodes", type=int, nargs="+", default=[1, 2, 4, 8])
+    ap.add_argument("--spec-tables", nargs="*", default=[], help="subset of table2..table6")
+    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp", "spectrum"],
+                    default="solve",
                     help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
                          "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch; "
                          "example1: the paper's Example 1 (Table 1 complexity, GMRES comparison); "
-                         "interp: interpolation degree against node count")
+                         "interp: interpolation degree against node count; "
+                         "spectrum: condition-number estimates of Tables 2-6 from GPU Arnoldi runs")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -335,6 +426,9 @@ def main():
         return
     if args.mode == "interp":
         interp_compare(args, dev)
+        return
+    if args.mode == "spectrum":
+        spectrum(args, dev)
         return
     w = inputs.workload(args.workload)
     if args.precision:

@@ -107,6 +107,10 @@ typedef struct {
  *        reference of the GMRES comparison of Section 5.1.
  * Every side stops after max_cycles cycles. */
 enum { HP_RIGHT = 0, HP_LEFT = 1, HP_NONE = 2 };
+/* Operators of hp_arnoldi only (spectral diagnostics): (Q P_N)^{-1} and P_N^{-1}, each
+ * application an inner restarted GMRES(64) solve to 1e-10 relative residual (Q P_N x = v
+ * with v as the given right-hand side; P_N x = v preconditioned on the right). */
+enum { HP_LEFT_INVERSE = 3, HP_NONE_INVERSE = 4 };
 typedef struct {
   int restart;       /* 1..64                 */
   int max_cycles;    /* >= 1                  */
@@ -180,6 +184,52 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
  * stopped above rtol (x and info are filled in any case). */
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts,
                    hp_solve_info* info, void* stream);
+
+/* Spectral diagnostics: the two ends of the spectrum that define the condition
+ * numbers of Eqn. Cond (Section 5).
+ *
+ * hp_arnoldi: m Arnoldi steps (1..64) of the operator P_N Q (HP_RIGHT), Q P_N (HP_LEFT),
+ * P_N (HP_NONE), (Q P_N)^{-1} (HP_LEFT_INVERSE) or P_N^{-1} (HP_NONE_INVERSE) from v0
+ * (device complex128, N^d; normalised first, no preconditioner applied to it), in FP64
+ * with the orthogonalisation of hp_solve (classical Gram-Schmidt with a second
+ * projection); the preconditioner runs at the plan's precision.  Returns
+ * HP_E_NOT_CONVERGED (H filled in) if an inner solve of an inverse operator stopped
+ * above its tolerance.
+ * H: host array (m+1) x m complex128, row-major, receives the upper Hessenberg matrix
+ * with A V_k = V_{k+1} H[:k+1, :k]; *steps = k (fewer than m only on an invariant
+ * subspace; 0 for v0 = 0).  The basis V_k stays in the plan's solver workspace until the
+ * next hp_arnoldi or hp_solve on the plan.  Allocates a temporary device vector; blocks. */
+hp_status hp_arnoldi(hp_plan p, const void* v0, int m, int side, void* H, int* steps, void* stream);
+
+/* out = V_k y (device complex128, N^d) from the basis the last hp_arnoldi on this plan
+ * left (y: host, k complex128, 1 <= k <= its steps): a Ritz vector, or the start of a
+ * restarted run.  HP_E_INVALID if no such basis is held.  Blocks. */
+hp_status hp_arnoldi_vector(hp_plan p, const void* y, int k, void* out, void* stream);
+
+/* Ritz pairs of the k x k leading block H_k of an Arnoldi Hessenberg matrix H (host,
+ * (m+1) x m complex128 row-major as hp_arnoldi returns it, 1 <= k <= m <= 64).
+ * harmonic = 0: the Ritz values eig(H_k), which approach the eigenvalues of largest
+ * modulus; harmonic = 1: the harmonic Ritz values eig(H_k + |h_{k+1,k}|^2 H_k^{-H} e_k
+ * e_k^T), which approach those nearest zero.  theta: host k complex128, unordered.
+ * Y (host k x k complex128, row i = unit vector y_i of theta_i) and resid (host k
+ * doubles, ||A V_k y_i - theta_i V_k y_i|| for the orthonormal basis) may be NULL.
+ * Host only (no device work).  Errors: HP_E_INVALID (bad sizes; H_k singular for
+ * harmonic = 1), HP_E_NONFINITE, HP_E_NOT_CONVERGED (the QR iteration did not deflate). */
+hp_status hp_ritz_values(const void* H, int m, int k, int harmonic, void* theta, void* Y, double* resid);
+
+/* One end of the spectrum of the operator of `side` (HP_RIGHT, HP_LEFT, HP_NONE): the
+ * eigenvalue of largest (smallest = 0) or smallest (smallest = 1) modulus, by explicitly
+ * restarted Arnoldi runs of m steps (2..64) from v0 (device complex128, N^d), each
+ * restarted from the wanted Ritz vector, until its residual relative to the Ritz value
+ * is <= tol or after max_restarts restarts.  The smallest end is the largest Ritz value
+ * of the inverse operator (HP_LEFT_INVERSE for HP_LEFT and HP_RIGHT, whose operators are
+ * similar; HP_NONE_INVERSE for HP_NONE), inverted.  lambda: host complex128;
+ * *rel_resid: that relative residual (of the inverse operator's pair for the smallest
+ * end); *runs: Arnoldi runs made.  Returns HP_E_NOT_CONVERGED (with the last estimate
+ * filled in) if tol was not reached or an inner solve stopped above its tolerance.
+ * Uses the plan's solver workspaces; allocates a temporary device vector; blocks. */
+hp_status hp_extreme_eigenvalue(hp_plan p, const void* v0, int m, int side, int smallest, int max_restarts,
+                                double tol, void* lambda, double* rel_resid, int* runs, void* stream);
 
 /* Resumable solves, for callers that interleave several solves (a serving
  * loop).  A solver owns the Krylov workspace of nrhs right-hand sides

@@ -25,7 +25,8 @@ PRECISIONS = {"fp64": HP_FP64, "mixed": HP_MIXED}
 EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_bytes", "hp_plan_query",
             "hp_apply_precond", "hp_matvec", "hp_solve", "hp_profile_apply", "hp_plan_destroy",
             "hp_status_str", "hp_last_error", "hp_solver_create", "hp_solver_start", "hp_solver_advance",
-            "hp_solver_wait", "hp_solver_destroy"]
+            "hp_solver_wait", "hp_solver_destroy", "hp_arnoldi", "hp_ritz_values",
+            "hp_arnoldi_vector", "hp_extreme_eigenvalue"]
 
 
 class HpGrid(C.Structure):
@@ -42,7 +43,9 @@ class HpPlanOpts(C.Structure):
                 ("symbol", C.c_int), ("precision", C.c_int), ("max_nrhs", C.c_int), ("interp_order", C.c_int)]
 
 
-SIDES = {"right": 0, "left": 1, "none": 2}   # HP_RIGHT, HP_LEFT, HP_NONE
+SIDES = {"right": 0, "left": 1, "none": 2}
+# operators of the spectral diagnostics: the sides, plus (Q P_N)^{-1} and P_N^{-1}
+ARNOLDI_OPS = dict(SIDES, left_inverse=3, none_inverse=4)   # HP_RIGHT, HP_LEFT, HP_NONE
 
 
 class HpSolveOpts(C.Structure):
@@ -95,6 +98,14 @@ def load_library(path: str = LIB_PATH):
     lib.hp_solve.restype = i
     lib.hp_profile_apply.argtypes = [vp, vp, vp, i, i, C.POINTER(d), C.POINTER(d), vp]
     lib.hp_profile_apply.restype = i
+    lib.hp_arnoldi.argtypes = [vp, vp, i, i, vp, C.POINTER(i), vp]
+    lib.hp_arnoldi.restype = i
+    lib.hp_ritz_values.argtypes = [vp, i, i, i, vp, vp, C.POINTER(d)]
+    lib.hp_ritz_values.restype = i
+    lib.hp_arnoldi_vector.argtypes = [vp, vp, i, vp, vp]
+    lib.hp_arnoldi_vector.restype = i
+    lib.hp_extreme_eigenvalue.argtypes = [vp, vp, i, i, i, i, d, vp, C.POINTER(d), C.POINTER(i), vp]
+    lib.hp_extreme_eigenvalue.restype = i
     lib.hp_solver_create.argtypes = [C.POINTER(vp), vp, i, C.POINTER(HpSolveOpts)]
     lib.hp_solver_create.restype = i
     lib.hp_solver_start.argtypes = [vp, vp, vp, vp]
@@ -271,6 +282,57 @@ class Plan:
             raise HelmpreError(code, "hp_solve")
         return x, [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status, i.rel_prec_residual) for i in infos]
 
+    def arnoldi(self, v0, m, side="left", stream=None):
+        """m Arnoldi steps of Q P_N (left), P_N Q (right), P_N (none), (Q P_N)^{-1}
+        (left_inverse) or P_N^{-1} (none_inverse) from v0 (complex128, one field,
+        normalised); returns (H (m+1, m) complex128 numpy array, steps)."""
+        import torch
+        nr = self._fields(v0, torch.complex128, "v0")
+        if nr != 1:
+            raise ValueError("arnoldi takes one field")
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        steps = C.c_int(0)
+        _check(load_library().hp_arnoldi(self._h, C.c_void_p(v0.data_ptr()), int(m), ARNOLDI_OPS[side],
+                                         C.c_void_p(H.ctypes.data), C.byref(steps), _stream(stream)), "hp_arnoldi")
+        return H, steps.value
+
+    def arnoldi_vector(self, y, out=None, stream=None):
+        """V_k y from the basis of the last arnoldi() on this plan (y: k complex numbers)."""
+        import torch
+        y = np.ascontiguousarray(y, dtype=np.complex128)
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex128, device="cuda")
+        self._fields(out, torch.complex128, "out")
+        _check(load_library().hp_arnoldi_vector(self._h, C.c_void_p(y.ctypes.data), int(y.size),
+                                                C.c_void_p(out.data_ptr()), _stream(stream)), "hp_arnoldi_vector")
+        return out
+
+    def extreme_eigenvalue(self, v0, smallest=False, side="left", m=64, max_restarts=20, tol=1e-6,
+                           stream=None):
+        """Eigenvalue of largest (or smallest) modulus of Q P_N / P_N Q / P_N by restarted
+        Arnoldi; returns (lambda, relative residual, Arnoldi runs, converged)."""
+        import torch
+        self._fields(v0, torch.complex128, "v0")
+        lam = np.zeros(1, dtype=np.complex128)
+        rr = C.c_double(0.0)
+        runs = C.c_int(0)
+        code = load_library().hp_extreme_eigenvalue(self._h, C.c_void_p(v0.data_ptr()), int(m), SIDES[side],
+                                                    int(bool(smallest)), int(max_restarts), float(tol),
+                                                    C.c_void_p(lam.ctypes.data), C.byref(rr), C.byref(runs),
+                                                    _stream(stream))
+        if code not in (0, 8):
+            _check(code, "hp_extreme_eigenvalue")
+        return complex(lam[0]), rr.value, runs.value, code == 0
+
+    def spectral_cond(self, v0, side="left", m=64, max_restarts=20, tol=1e-6, stream=None):
+        """Spectral condition number of Eqn. Cond, max |lambda| / min |lambda|, of the
+        operator of `side`; returns (cond, details dict)."""
+        hi = self.extreme_eigenvalue(v0, False, side, m, max_restarts, tol, stream)
+        lo = self.extreme_eigenvalue(v0, True, side, m, max_restarts, tol, stream)
+        det = {"max": hi[0], "min": lo[0], "max_rel_resid": hi[1], "min_rel_resid": lo[1],
+               "runs": hi[2] + lo[2], "converged": hi[3] and lo[3]}
+        return abs(hi[0]) / abs(lo[0]), det
+
     def profile_apply(self, v, out=None, reps=20, stream=None):
         """Event-timed applies: (ms per launch of the 5 pass slots, algorithmic bytes per pass)."""
         import torch
@@ -344,6 +406,45 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def ritz_values(H, steps, harmonic=False):
+    """Ritz (harmonic=False) or harmonic Ritz values of the leading steps x steps block of
+    an Arnoldi Hessenberg matrix H ((m+1, m) complex128, as Plan.arnoldi returns it)."""
+    H = np.ascontiguousarray(H, dtype=np.complex128)
+    m = H.shape[1]
+    if H.shape != (m + 1, m):
+        raise ValueError("H must be (m+1, m)")
+    theta = np.zeros(int(steps), dtype=np.complex128)
+    _check(load_library().hp_ritz_values(C.c_void_p(H.ctypes.data), int(m), int(steps), int(bool(harmonic)),
+                                         C.c_void_p(theta.ctypes.data), None, None), "hp_ritz_values")
+    return theta
+
+
+def ritz_pairs(H, steps, harmonic=False):
+    """(theta, Y, resid): Ritz or harmonic Ritz values, unit vectors y_i (rows of Y) and the
+    residual norms ||A V y_i - theta_i V y_i|| of the Arnoldi relation."""
+    H = np.ascontiguousarray(H, dtype=np.complex128)
+    m = H.shape[1]
+    if H.shape != (m + 1, m):
+        raise ValueError("H must be (m+1, m)")
+    k = int(steps)
+    theta = np.zeros(k, dtype=np.complex128)
+    Y = np.zeros((k, k), dtype=np.complex128)
+    res = np.zeros(k, dtype=np.float64)
+    _check(load_library().hp_ritz_values(C.c_void_p(H.ctypes.data), int(m), k, int(bool(harmonic)),
+                                         C.c_void_p(theta.ctypes.data), C.c_void_p(Y.ctypes.data),
+                                         res.ctypes.data_as(C.POINTER(C.c_double))), "hp_ritz_values")
+    return theta, Y, res
+
+
+def cond_estimate(H, steps):
+    """(max |Ritz value|, min |harmonic Ritz value|, their ratio): an estimate of the
+    spectral condition number of Eqn. Cond from one Arnoldi run (both ends approached
+    from inside the spectrum)."""
+    hi = float(np.abs(ritz_values(H, steps)).max())
+    lo = float(np.abs(ritz_values(H, steps, harmonic=True)).min())
+    return hi, lo, hi / lo
 
 
 def workspace_bytes(shape, precision, K, nrhs=1, restart=30):

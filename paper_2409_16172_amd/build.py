@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhelmpre.so")
-SOURCES = ["hp_kernels.hip", "hp_api.cpp"]
+SOURCES = ["hp_kernels.hip", "hp_api.cpp", "hp_spectrum.cpp"]
 ARCH = os.environ.get("HP_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept off: the compiler would otherwise form them

@@ -63,6 +63,8 @@ struct hp_plan_s {
   DevBuf t, fields;                  // apply workspace
   // solver workspace of hp_solve (sessions created with hp_solver_create own theirs)
   struct SolverWs* solver_ws_ptr = nullptr;
+  int arnoldi_k = -1;   // basis vectors the last hp_arnoldi left in that workspace (-1: none)
+  struct SolverWs* inner_ws_ptr = nullptr;   // the inner solves of hp_arnoldi's inverse operators
 
   int real_kind() const { return prec == HP_FP64 ? 0 : 1; }
   size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
@@ -741,6 +743,12 @@ struct SolverWs {
   }
 };
 
+// Inverse operators of hp_arnoldi (HP_LEFT_INVERSE, HP_NONE_INVERSE) and the
+// restarted GMRES of their inner solves.
+constexpr int kLeftInverse = 3, kNoneInverse = 4;
+constexpr int kInnerRestart = 64, kInnerCycles = 50;
+constexpr double kInnerRtol = 1e-10;
+
 // A resumable restarted-GMRES solve of nrhs right-hand sides on one stream.
 // The Krylov state stays on the device; the host only enqueues work and reads
 // two pinned flag arrays the kernels publish (converged, cycle ended), so that
@@ -758,6 +766,12 @@ struct Session {
   enum Phase { kIdle, kCycleStart, kArnoldi, kFinished } phase = kIdle;
   int cycles_run = 0, j = 0;
   bool throttle = true;
+  // one Arnoldi process from f itself (every side): no preconditioner on the start,
+  // no cycle end, the basis stays in the workspace
+  bool arnoldi_only = false;
+  // left side: f is the preconditioned right-hand side itself (the system Q P x = f)
+  bool rhs_prec = false;
+  bool inner_failed = false;   // an inner solve of an inverse operator stopped above its tolerance
   hp_status status = HP_OK;
 
   hipError_t start(const cpx<double>* f_, cpx<double>* x_, hipStream_t s) {
@@ -782,7 +796,7 @@ struct Session {
     j = 0;
     hipError_t e;
     if ((e = hp::launch_fill_zero(W->flags.p, W->flags.bytes, st)) != hipSuccess) return e;
-    if (o.side == HP_LEFT) {   // the stopping test uses ||Q f||; ||f|| for the reported true residual
+    if (o.side == HP_LEFT && !arnoldi_only && !rhs_prec) {   // the stopping test uses ||Q f||; ||f|| for the reported true residual
       cpx<double>* qf = (cpx<double>*)W->tvec.p;
       if ((e = run_apply(P, f, 0, np, qf, 0, np, false, nrhs, nullptr, st)) != hipSuccess) return e;
       if ((e = hp::launch_fnorm(K, qf, np, o.rtol, st)) != hipSuccess) return e;
@@ -797,8 +811,19 @@ struct Session {
   // norm and the convergence test
   hipError_t enqueue_cycle_start() {
     hipError_t e;
+    if (o.side == HP_LEFT && rhs_prec) {   // r = f - Q P x
+      const size_t np = P->npts;
+      cpx<double>* px = (cpx<double>*)W->tvec.p;
+      if ((e = run_stencil(P, 0, x, np, px, np, nullptr, nrhs, K.done, st)) != hipSuccess) return e;
+      if ((e = run_apply(P, px, 0, np, K.V, 0, vrs, false, nrhs, K.done, st)) != hipSuccess) return e;
+      if ((e = hp::launch_rsub(f, np, K.V, vrs, np, nrhs, K.done, st)) != hipSuccess) return e;
+      if ((e = hp::launch_cycle_start(K, o.rtol, st)) != hipSuccess) return e;
+      if ((e = hipEventRecord(W->cyc_ev, st)) != hipSuccess) return e;
+      phase = kCycleStart;
+      return hipSuccess;
+    }
     if ((e = run_stencil(P, 3, x, P->npts, K.V, vrs, f, nrhs, K.done, st)) != hipSuccess) return e;
-    if (o.side == HP_LEFT &&
+    if (o.side == HP_LEFT && !arnoldi_only &&
         (e = run_apply(P, K.V, 0, vrs, K.V, 0, vrs, false, nrhs, K.done, st)) != hipSuccess)
       return e;
     if ((e = hp::launch_cycle_start(K, o.rtol, st)) != hipSuccess) return e;
@@ -813,7 +838,9 @@ struct Session {
     cpx<double>* vj = K.V + (size_t)j * np;
     cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
     hipError_t e;
-    if (o.side == HP_NONE) {          // w = P_N u_j (plain GMRES, FP64)
+    if (o.side == kLeftInverse || o.side == kNoneInverse) {   // w = (Q P_N)^{-1} u_j or P_N^{-1} u_j
+      if ((e = inner_solve(vj, vj1)) != hipSuccess) return e;
+    } else if (o.side == HP_NONE) {          // w = P_N u_j (plain GMRES, FP64)
       if ((e = run_stencil(P, 0, vj, vrs, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess) return e;
     } else if (o.side == HP_LEFT) {   // w = Q P_N u_j (P_N in FP64)
       cpx<double>* pv = (cpx<double>*)W->tvec.p;
@@ -829,6 +856,28 @@ struct Session {
     if ((e = hp::launch_arnoldi_update(K, j, st)) != hipSuccess) return e;
     if ((e = hipEventRecord(W->step_ev[j % (SolverWs::kLag + 1)], st)) != hipSuccess) return e;
     ++j;
+    return hipSuccess;
+  }
+
+  // out = A^{-1} in for the inverse operators of hp_arnoldi, by a blocking restarted
+  // GMRES on the same stream with the plan's inner workspace: Q P_N x = in (left
+  // side, right-hand side taken as given), or P_N x = in preconditioned on the right
+  hipError_t inner_solve(const cpx<double>* in, cpx<double>* out) {
+    hipError_t e;
+    if ((e = hp::launch_fill_zero(out, P->npts * sizeof(cpx<double>), st)) != hipSuccess) return e;
+    // the outer process has stopped (an invariant subspace): its remaining steps are void
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (all(K.host_stop)) return hipSuccess;
+    Session I;
+    I.P = P;
+    I.W = P->inner_ws_ptr;
+    I.nrhs = 1;
+    I.o = hp_solve_opts{kInnerRestart, kInnerCycles, kInnerRtol, o.side == kLeftInverse ? HP_LEFT : HP_RIGHT};
+    I.rhs_prec = o.side == kLeftInverse;
+    I.throttle = throttle;
+    if ((e = I.start(in, out, st)) != hipSuccess) return e;
+    if ((e = I.advance(1 << 30, true)) != hipSuccess) return e;
+    if (!I.all(I.K.host_done)) inner_failed = true;
     return hipSuccess;
   }
 
@@ -876,7 +925,7 @@ struct Session {
         if (!ready(W->cyc_ev, block, e)) return e;
         if (all(K.host_done) || cycles_run >= o.max_cycles) {
           phase = kFinished;
-          if (o.side == HP_LEFT) {   // the true residual of the returned x
+          if (o.side == HP_LEFT && !rhs_prec) {   // the true residual of the returned x
             cpx<double>* r = (cpx<double>*)W->tvec.p;
             if ((e = run_stencil(P, 3, x, P->npts, r, P->npts, f, nrhs, nullptr, st)) != hipSuccess) return e;
             if ((e = hp::launch_plain_norm(K, r, P->npts, 1, st)) != hipSuccess) return e;
@@ -890,6 +939,10 @@ struct Session {
       }
       // kArnoldi
       if (j >= o.restart) {
+        if (arnoldi_only) {
+          phase = kFinished;
+          return hipSuccess;
+        }
         if ((e = enqueue_cycle_end()) != hipSuccess) return e;
         continue;
       }
@@ -898,6 +951,10 @@ struct Session {
         // right-hand side has ended it
         if (!ready(W->step_ev[(j - SolverWs::kLag) % (SolverWs::kLag + 1)], block, e)) return e;
         if (all(K.host_stop)) {
+          if (arnoldi_only) {
+            phase = kFinished;
+            return hipSuccess;
+          }
           if ((e = enqueue_cycle_end()) != hipSuccess) return e;
           continue;
         }
@@ -919,7 +976,7 @@ struct Session {
       const bool ok = W->pinned[r] != 0;
       info[r].iters = hs[r].iters;
       info[r].cycles = hs[r].cycles;
-      info[r].rel_true_residual = o.side == HP_LEFT ? hs[r].relres_plain : hs[r].relres;
+      info[r].rel_true_residual = o.side == HP_LEFT && !rhs_prec ? hs[r].relres_plain : hs[r].relres;
       info[r].rel_prec_residual = hs[r].relres;
       info[r].status = ok ? HP_OK : HP_E_NOT_CONVERGED;
       if (!ok) ret = HP_E_NOT_CONVERGED;
@@ -934,11 +991,13 @@ struct hp_solver_s {
 };
 
 void hp_plan_s::release_solver_ws() {
-  if (solver_ws_ptr) {
-    solver_ws_ptr->release();
-    delete solver_ws_ptr;
+  for (SolverWs** w : {&solver_ws_ptr, &inner_ws_ptr}) {
+    if (*w) {
+      (*w)->release();
+      delete *w;
+    }
+    *w = nullptr;
   }
-  solver_ws_ptr = nullptr;
 }
 
 static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x, int nrhs,
@@ -948,6 +1007,7 @@ static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x,
     if (!P->solver_ws_ptr) return HP_E_NOMEM;
   }
   HP_TRY(P->solver_ws_ptr->ensure(P->npts, P->fsize(), o.restart, nrhs));
+  P->arnoldi_k = -1;
   Session S;
   S.P = P;
   S.W = P->solver_ws_ptr;
@@ -961,6 +1021,74 @@ static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x,
 }
 
 extern "C" {
+
+hp_status hp_arnoldi(hp_plan p, const void* v0, int m, int side, void* H, int* steps, void* stream) {
+  if (!p || !v0 || !H || !steps || m < 1 || m > hp::kMaxRestart || side < HP_RIGHT || side > kNoneInverse)
+    return HP_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  if (!p->solver_ws_ptr) {
+    p->solver_ws_ptr = new (std::nothrow) SolverWs();
+    if (!p->solver_ws_ptr) return HP_E_NOMEM;
+  }
+  HP_TRY(p->solver_ws_ptr->ensure(p->npts, p->fsize(), m, 1));
+  if (side >= kLeftInverse) {
+    if (!p->inner_ws_ptr) {
+      p->inner_ws_ptr = new (std::nothrow) SolverWs();
+      if (!p->inner_ws_ptr) return HP_E_NOMEM;
+    }
+    HP_TRY(p->inner_ws_ptr->ensure(p->npts, p->fsize(), kInnerRestart, 1));
+  }
+  p->arnoldi_k = -1;
+  DevBuf x0;   // the starting guess of the cycle (zero): its residual is v0
+  HP_TRY(x0.alloc(p->npts * 16));
+  HP_TRY(hp::launch_fill_zero(x0.p, x0.bytes, st));
+  // m steps under a tolerance no residual meets: only an invariant subspace ends it early
+  const hp_solve_opts o{m, 1, 1e-300, side};
+  Session S;
+  S.P = p;
+  S.W = p->solver_ws_ptr;
+  S.nrhs = 1;
+  S.o = o;
+  S.arnoldi_only = true;
+  S.throttle = p->npts >= ((size_t)1 << 18);
+  hp_status ret = HP_OK;
+  hipError_t e = S.start((const cpx<double>*)v0, (cpx<double>*)x0.p, st);
+  if (e == hipSuccess) e = S.advance(1 << 30, true);
+  hp::KState ks;
+  if (e == hipSuccess) e = hipMemcpyAsync(&ks, S.W->state.p, sizeof(ks), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) ret = from_hip(e);
+  x0.release();
+  if (ret != HP_OK) return ret;
+  const int k = std::min(ks.iters, m);
+  cpx<double>* h = (cpx<double>*)H;
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j < m; ++j)
+      h[(size_t)i * m + j] = (j < k && i <= j + 1) ? ks.Hraw[(size_t)j * (hp::kMaxRestart + 1) + i] : cpx<double>{0, 0};
+  *steps = k;
+  p->arnoldi_k = k;
+  return S.inner_failed ? HP_E_NOT_CONVERGED : HP_OK;
+}
+
+hp_status hp_arnoldi_vector(hp_plan p, const void* y, int k, void* out, void* stream) {
+  if (!p || !y || !out || k < 1 || k > p->arnoldi_k || !p->solver_ws_ptr) return HP_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  SolverWs* W = p->solver_ws_ptr;
+  hp::KState* ks = (hp::KState*)W->state.p;
+  hp::KrylovArgs K{};
+  K.V = (cpx<double>*)W->V.p;
+  K.npts = p->npts;
+  K.vrs = (size_t)(W->restart + 1) * p->npts;
+  K.state = ks;
+  K.done = (int*)W->flags.p + W->nrhs;
+  K.nrhs = 1;
+  HP_TRY(hipMemcpyAsync(ks->y, y, (size_t)k * sizeof(cpx<double>), hipMemcpyHostToDevice, st));
+  HP_TRY(hipMemcpyAsync(&ks->k, &k, sizeof(int), hipMemcpyHostToDevice, st));
+  HP_TRY(hp::launch_fill_zero(K.done, sizeof(int), st));
+  HP_TRY(hp::launch_lincomb(K, (cpx<double>*)out, p->npts, false, st));
+  HP_TRY(hipStreamSynchronize(st));   // y and k are read from host memory
+  return HP_OK;
+}
 
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts, hp_solve_info* info,
                    void* stream) {

@@ -1595,6 +1595,18 @@ __global__ __launch_bounds__(256) void k_lincomb(const cpx<double>* __restrict__
   }
 }
 
+// v = b - v (the residual of a system whose right-hand side is given preconditioned)
+__global__ __launch_bounds__(256) void k_rsub(const cpx<double>* __restrict__ b, size_t b_rs,
+                                              cpx<double>* __restrict__ v, size_t v_rs, size_t n,
+                                              const int* __restrict__ skip) {
+  const int rhs = blockIdx.y;
+  if (skip != nullptr && skip[rhs]) return;
+  const cpx<double>* br = b + (size_t)rhs * b_rs;
+  cpx<double>* vr = v + (size_t)rhs * v_rs;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    vr[i] = csub(br[i], vr[i]);
+}
+
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -1808,6 +1820,13 @@ hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st) {
 hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, bool accumulate, hipStream_t st) {
   hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(a.npts), a.nrhs), dim3(256), 0, st, a.V, a.npts, a.vrs,
                      a.state, out, out_rs, accumulate ? 1 : 0, a.done);
+  return hipGetLastError();
+}
+
+hipError_t launch_rsub(const cpx<double>* b, size_t b_rs, cpx<double>* v, size_t v_rs, size_t n, int nrhs,
+                       const int* skip, hipStream_t st) {
+  if (n == 0 || nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rsub, dim3(stream_blocks(n), nrhs), dim3(256), 0, st, b, b_rs, v, v_rs, n, skip);
   return hipGetLastError();
 }
 
