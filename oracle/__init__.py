@@ -37,14 +37,15 @@ class _Problem(C.Structure):
                 ("omega", C.c_double), ("c", C.c_void_p), ("a", C.c_void_p), ("zeta", C.c_void_p),
                 ("c0", C.c_double), ("m_real", C.c_int), ("m_layer", C.c_int), ("symbol", C.c_int),
                 ("a_floor", C.c_double), ("nodes_real", C.c_void_p), ("nodes_zeta", C.c_void_p),
-                ("a_nodes", C.c_void_p), ("interp_order", C.c_int)]
+                ("a_nodes", C.c_void_p), ("interp_order", C.c_int), ("m_damp", C.c_int)]
 
 
 class _Setup(C.Structure):
     _fields_ = [("M", C.c_int), ("Mt", C.c_int), ("K", C.c_int), ("mo", C.c_int),
                 ("cmin", C.c_double), ("cmax", C.c_double), ("zmax", C.c_double),
                 ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
-                ("gre", C.c_double * 64), ("gim", C.c_double * 64), ("order", C.c_int)]
+                ("gre", C.c_double * 64), ("gim", C.c_double * 64), ("order", C.c_int),
+                ("Ma", C.c_int), ("anode", C.c_double * 64), ("amin", C.c_double), ("amax", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -87,7 +88,7 @@ class Problem:
 
     def __init__(self, shape, omega, c, a=None, zeta=None, length=1.0, c0=1.0, m_real=8,
                  m_layer=3, symbol="continuous", a_floor=0.0, nodes_real=None,
-                 nodes_zeta=None, a_nodes=None, interp_order=1):
+                 nodes_zeta=None, a_nodes=None, interp_order=1, m_damp=0):
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
         self.c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.shape)
@@ -110,6 +111,7 @@ class Problem:
         p.a_floor = float(a_floor)
         p.nodes_real, p.nodes_zeta, p.a_nodes = _addr(self.nodes_real), _addr(self.nodes_zeta), _addr(self.a_nodes)
         p.interp_order = int(interp_order)
+        p.m_damp = int(m_damp)
         self._p = p
         self.omega = float(omega)
         self.length = float(length)
@@ -128,7 +130,7 @@ class Problem:
         return {"M": s.M, "Mt": s.Mt, "K": K, "mo": s.mo, "cmin": s.cmin, "cmax": s.cmax,
                 "zmax": s.zmax, "cnode": np.array(s.cnode[:s.M]), "znode": np.array(s.znode[:s.Mt + 1]),
                 "ahat": np.array(s.ahat[:K]), "gamma": np.array(s.gre[:K]) + 1j * np.array(s.gim[:K]),
-                "_raw": s}
+                "Ma": s.Ma, "anode": np.array(s.anode[:s.Ma]), "_raw": s}
 
     def weights(self, cval, zval):
         """All K node weights at a point with wave speed cval and layer value zval."""
@@ -136,6 +138,13 @@ class Problem:
         w = (C.c_double * 128)()
         lib().or_point_weights(C.byref(st["_raw"]), C.c_double(self.c0), C.c_double(cval),
                                C.c_double(zval), w)
+        return np.array(w[:st["K"]])
+
+    def weights_ca(self, cval, aval):
+        """The M x Ma node weights of the bivariate (c, a) scheme at a point."""
+        st = self.setup()
+        w = (C.c_double * 128)()
+        lib().or_point_weights_ca(C.byref(st["_raw"]), C.c_double(cval), C.c_double(aval), w)
         return np.array(w[:st["K"]])
 
     def _fields(self, x):

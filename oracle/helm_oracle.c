@@ -64,6 +64,9 @@ typedef struct {
     const double* a_nodes;     /* optional damping at the real nodes            */
     int interp_order;          /* real-axis interpolation: 1 (or 0) piecewise linear, 2 or 3
                                   piecewise Lagrange of that degree                */
+    int m_damp;                /* >= 2: bivariate interpolation in (c, a) with m_damp
+                                  equidistant damping nodes on [a_min, a_max]; 0/1: a is
+                                  treated as a function of c (one damping per real node) */
 } or_problem;
 
 /* Derived quantities of the preconditioner (filled by or_setup). */
@@ -78,6 +81,9 @@ typedef struct {
     double ahat[64];       /* symbol damping per node (K)     */
     double gre[64], gim[64]; /* gamma_n per node (K)          */
     int order;             /* real-axis interpolation degree (1, 2 or 3) */
+    int Ma;                /* damping nodes of the bivariate scheme (0: univariate) */
+    double anode[64];      /* a_1..a_Ma; real node (m, r) is node m + M r */
+    double amin, amax;
 } or_setup_t;
 
 static long npoints(const or_problem* p) {
@@ -368,6 +374,23 @@ void or_point_weights(const or_setup_t* s, double c0, double cval, double zval, 
     for (int j = 1; j <= s->Mt; ++j) w[s->M + j - 1] = phimo * hat(tz, nz, nz - 1 - j, im);
 }
 
+/* Weights of the M x Ma real nodes at a point (no layer) in the bivariate
+ * scheme: the tensor product of the hat functions of the speed nodes (in c) and
+ * of the damping nodes (in a), the two-variable form of the interpolation of
+ * Section 4.1 that the concluding remarks call for when a does not depend on c. */
+void or_point_weights_ca(const or_setup_t* s, double cval, double aval, double* w) {
+    for (int r = 0; r < s->Ma; ++r) {
+        double ha = hat(s->anode, s->Ma, r, aval);
+        for (int m = 0; m < s->M; ++m) w[m + s->M * r] = hat(s->cnode, s->M, m, cval) * ha;
+    }
+}
+
+/* Weights of all K nodes at point i of the problem (either scheme). */
+static void point_weights_at(const or_problem* p, const or_setup_t* s, long i, double* w) {
+    if (s->Ma > 0) or_point_weights_ca(s, p->c[i], p->a ? p->a[i] : 0.0, w);
+    else or_point_weights(s, p->c0, p->c[i], p->zeta ? p->zeta[i] : 0.0, w);
+}
+
 /* Set up nodes, per-node damping and per-node complex speed. */
 int or_setup(const or_problem* p, or_setup_t* s) {
     memset(s, 0, sizeof(*s));
@@ -405,6 +428,34 @@ int or_setup(const or_problem* p, or_setup_t* s) {
     }
     s->K = s->M + s->Mt;
     if (s->K > 64) return OR_E_INVALID;
+
+    /* Bivariate (c, a): damping nodes equidistant on [a_min, a_max] (a single
+     * node when a is uniform), real node (m, r) = (c_m, a_r); no absorbing layer
+     * (its nodes would need a third axis) and piecewise linear in both variables. */
+    if (p->m_damp >= 2) {
+        if (has_layer || s->order != 1 || p->m_damp > 64) return OR_E_INVALID;
+        s->amin = INFINITY; s->amax = -INFINITY;
+        for (long i = 0; i < np; ++i) {
+            double av = p->a ? p->a[i] : 0.0;
+            if (av < s->amin) s->amin = av;
+            if (av > s->amax) s->amax = av;
+        }
+        int Ma = s->amax > s->amin ? p->m_damp : 1;
+        for (int r = 0; r < Ma; ++r)
+            s->anode[r] = Ma == 1 ? s->amin : s->amin + (s->amax - s->amin) * (double)r / (double)(Ma - 1);
+        if (Ma > 1) s->anode[Ma - 1] = s->amax;
+        s->Ma = Ma;
+        s->K = s->M * Ma;
+        if (s->K > 64) return OR_E_INVALID;
+        for (int r = 0; r < Ma; ++r)
+            for (int m = 0; m < s->M; ++m) {
+                int n = m + s->M * r;
+                s->gre[n] = s->cnode[m];
+                s->gim[n] = 0.0;
+                s->ahat[n] = s->anode[r] < p->a_floor ? p->a_floor : s->anode[r];
+            }
+        return OR_OK;
+    }
 
     /* Symbol damping per real node: the symbol depends on x only through c,
      * so a must be a function of c (Section 4).  Uniform a is used as is;
@@ -485,8 +536,7 @@ int or_apply(const or_problem* p, int nrhs, const cx* v, cx* u) {
     if (!vh || !z || !lam || !wgt) { free(vh); free(z); free(lam); free(wgt); return OR_E_NOMEM; }
     int idx[3];
     for (long i = 0; i < np; ++i) { unravel(p, i, idx); lam[i] = lambda_of(p, idx); }
-    for (long i = 0; i < np; ++i)
-        or_point_weights(&s, p->c0, p->c[i], p->zeta ? p->zeta[i] : 0.0, wgt + i * s.K);
+    for (long i = 0; i < np; ++i) point_weights_at(p, &s, i, wgt + i * s.K);
     for (int n = 0; n < s.K; ++n) {      /* zero denominators are rejected */
         cx g = s.gre[n] + I * s.gim[n];
         for (long i = 0; i < np; ++i) {
