@@ -349,6 +349,45 @@ def spectrum(args, dev):
                       "estimates": out}))
 
 
+def bivariate_compare(args, dev):
+    """Bivariate (c, a) interpolation against the univariate scheme on a 1024^2 medium whose
+    damping is an independent random field (no layer, FP64, rtol 1e-8): for two damping
+    ranges, the univariate scheme with 16 speed nodes (one damping per node, the weighted
+    mean of a over its points) against speed x damping grids of 16 nodes; iterations,
+    solves/s and the apply time."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    n = 1024
+    shape = (n, n)
+    omega = 2 * np.pi * 100
+    c = inputs.gaussian_random_field(shape, 20.0, inputs.SEED_BASE + 40, lo=0.8, hi=1.2)
+    f = torch.from_numpy(inputs.gaussian_source(shape, 2.0, (0.05, -0.1))[None].astype(np.complex128)).to(dev)
+    rng = np.random.default_rng(0)
+    v = torch.from_numpy(rng.standard_normal(shape) + 1j * rng.standard_normal(shape))[None].to(dev)
+    rows = []
+    for lo, hi in ((0.05, 0.6), (0.01, 0.3)):
+        a = inputs.gaussian_random_field(shape, 30.0, inputs.SEED_BASE + 41, lo=lo * omega, hi=hi * omega)
+        for m, ma in ((16, 0), (8, 2), (4, 4), (16, 4)):
+            p = binding.Plan(shape, omega, c, a, m_real=m, m_damp=ma, a_floor=0.05 * omega)
+            p.solve(f)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = p.solve(f, rtol=1e-8)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            ms, _ = p.profile_apply(v, reps=10)
+            row = {"a_range_over_omega": [lo, hi], "m_real": m, "m_damp": ma, "K": p.info()["K"],
+                   "iters": info[0].iters, "rel_true_residual": info[0].rel_true_residual,
+                   "solves_per_s": 1.0 / dt, "apply_us": sum(ms) * 1e3}
+            print(f"[bench] bivariate a in [{lo}, {hi}] omega, M={m} Ma={ma} K={row['K']}: {row['iters']} iters, "
+                  f"{row['solves_per_s']:.1f} solves/s, apply {row['apply_us']:.0f} us", file=sys.stderr, flush=True)
+            rows.append(row)
+            p.close()
+            del x
+    print(json.dumps({"mode": "bivariate", "grid": list(shape), "omega_over_pi": omega / np.pi, "a_floor_over_omega": 0.05,
+                      "rows": rows}))
+
+
 def apply_only(args, w, plan, dev):
     import numpy as np
     import torch
@@ -398,13 +437,14 @@ def main():
                     help="estimate min |lambda(P_N)| by inverse runs instead of the bound omega a")
     ap.add_argument("--spec-nodes", type=int, nargs="+", default=[1, 2, 4, 8])
     ap.add_argument("--spec-tables", nargs="*", default=[], help="subset of table2..table6")
-    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp", "spectrum"],
+    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp", "spectrum", "bivariate"],
                     default="solve",
                     help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
                          "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch; "
                          "example1: the paper's Example 1 (Table 1 complexity, GMRES comparison); "
                          "interp: interpolation degree against node count; "
-                         "spectrum: condition-number estimates of Tables 2-6 from GPU Arnoldi runs")
+                         "spectrum: condition numbers of Tables 2-6 from GPU Arnoldi runs; "
+                         "bivariate: (c, a) interpolation against the univariate scheme")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -429,6 +469,9 @@ def main():
         return
     if args.mode == "spectrum":
         spectrum(args, dev)
+        return
+    if args.mode == "bivariate":
+        bivariate_compare(args, dev)
         return
     w = inputs.workload(args.workload)
     if args.precision:

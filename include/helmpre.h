@@ -84,7 +84,15 @@ typedef struct {
  *   interp_order  real-axis interpolation: 0 or 1 piecewise linear (Section
  *              4.1), 2 or 3 piecewise Lagrange of that degree through
  *              consecutive nodes (the other polynomial bases of Sections 1
- *              and 4.3; capped at M - 1); the layer leg stays linear           */
+ *              and 4.3; capped at M - 1); the layer leg stays linear
+ *   m_damp     0 or 1: the damping enters the symbol through one value per real
+ *              node (a as a function of c, Section 4); >= 2: bivariate
+ *              interpolation in (c, a), the extension the concluding remarks
+ *              name for a damping independent of c: m_damp equidistant damping
+ *              nodes on [a_min, a_max], node (c_m, a_r) for every pair (K =
+ *              M m_damp <= 64), tensor-product hat weights.  Needs no layer
+ *              and interp_order <= 1 (else HP_E_INVALID); a uniform a falls
+ *              back to the univariate scheme                                   */
 typedef struct {
   int m_real;
   int m_layer;
@@ -96,6 +104,7 @@ typedef struct {
   int precision;
   int max_nrhs;
   int interp_order;
+  int m_damp;
 } hp_plan_opts;
 
 /* Restarted GMRES(restart) on P_N x = f, starting from the x passed in.
@@ -140,6 +149,9 @@ typedef struct {
   size_t workspace_bytes;    /* device bytes held by the plan for apply/matvec */
   int precision;
   int interp_order;          /* real-axis interpolation degree in effect */
+  int m_damp;                /* damping nodes of the bivariate scheme (0: univariate);
+                                real node (c_m, a_r) is node m + M r */
+  double anode[64];          /* damping nodes a_r             */
 } hp_plan_info;
 
 /* Build a plan: upload and validate the media, place the nodes, and compute in

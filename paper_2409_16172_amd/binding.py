@@ -40,12 +40,13 @@ class HpLayer(C.Structure):
 class HpPlanOpts(C.Structure):
     _fields_ = [("m_real", C.c_int), ("m_layer", C.c_int), ("nodes_real", C.c_void_p),
                 ("nodes_zeta", C.c_void_p), ("a_nodes", C.c_void_p), ("a_floor", C.c_double),
-                ("symbol", C.c_int), ("precision", C.c_int), ("max_nrhs", C.c_int), ("interp_order", C.c_int)]
+                ("symbol", C.c_int), ("precision", C.c_int), ("max_nrhs", C.c_int), ("interp_order", C.c_int),
+                ("m_damp", C.c_int)]
 
 
-SIDES = {"right": 0, "left": 1, "none": 2}
+SIDES = {"right": 0, "left": 1, "none": 2}   # HP_RIGHT, HP_LEFT, HP_NONE
 # operators of the spectral diagnostics: the sides, plus (Q P_N)^{-1} and P_N^{-1}
-ARNOLDI_OPS = dict(SIDES, left_inverse=3, none_inverse=4)   # HP_RIGHT, HP_LEFT, HP_NONE
+ARNOLDI_OPS = dict(SIDES, left_inverse=3, none_inverse=4)
 
 
 class HpSolveOpts(C.Structure):
@@ -62,7 +63,8 @@ class HpPlanInfo(C.Structure):
                 ("mo", C.c_int), ("cmin", C.c_double), ("cmax", C.c_double), ("zeta_max", C.c_double),
                 ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
                 ("gamma_re", C.c_double * 64), ("gamma_im", C.c_double * 64),
-                ("workspace_bytes", C.c_size_t), ("precision", C.c_int), ("interp_order", C.c_int)]
+                ("workspace_bytes", C.c_size_t), ("precision", C.c_int), ("interp_order", C.c_int),
+                ("m_damp", C.c_int), ("anode", C.c_double * 64)]
 
 
 _lib = None
@@ -175,7 +177,7 @@ class Plan:
 
     def __init__(self, shape, omega, c, a=None, zeta=None, *, length=1.0, c0=1.0, m_real=8,
                  m_layer=3, symbol="continuous", precision="fp64", a_floor=0.0, max_nrhs=1,
-                 nodes_real=None, nodes_zeta=None, a_nodes=None, stream=None, interp_order=1):
+                 nodes_real=None, nodes_zeta=None, a_nodes=None, stream=None, interp_order=1, m_damp=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("helmpre needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -205,6 +207,7 @@ class Plan:
         o.precision = PRECISIONS[precision]
         o.max_nrhs = int(max_nrhs)
         o.interp_order = int(interp_order)
+        o.m_damp = int(m_damp)
         self._opts = o
         lay = HpLayer()
         lay.zeta = None if keep[2] is None else keep[2].ctypes.data
@@ -231,7 +234,8 @@ class Plan:
                 "zeta_max": pi.zeta_max, "cnode": np.array(pi.cnode[:pi.M]),
                 "znode": np.array(pi.znode[:pi.Mt + 1]), "ahat": np.array(pi.ahat[:K]),
                 "gamma": np.array(pi.gamma_re[:K]) + 1j * np.array(pi.gamma_im[:K]),
-                "workspace_bytes": int(pi.workspace_bytes), "interp_order": int(pi.interp_order)}
+                "workspace_bytes": int(pi.workspace_bytes), "interp_order": int(pi.interp_order),
+                "m_damp": int(pi.m_damp), "anode": np.array(pi.anode[:pi.m_damp])}
 
     def _fields(self, x, dtype, name):
         import torch

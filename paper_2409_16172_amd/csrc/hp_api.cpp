@@ -57,6 +57,9 @@ struct hp_plan_s {
   DevBuf nodes, pos, grpmask, rowmask, slabneed, storemask, coef64, coef32, lam_ax, lam_in, tw64[3], tw32[3];
   int order = 1;   // real-axis interpolation degree in effect
   DevBuf lagtab;   // Lagrange table of CombineArgs::lag (order >= 2)
+  int Ma = 0;      // damping nodes of the bivariate (c, a) scheme (0: univariate)
+  double anode[64] = {0};
+  DevBuf posa;     // per point: position among the damping nodes (Ma >= 2)
   // node usage counts for the byte model of the passes
   double rows_used = 0;    // sum over pass-C rows of the nodes the row uses
   double slabs_used = 0;   // sum over nodes of the axis-0 indices that use the node
@@ -71,7 +74,7 @@ struct hp_plan_s {
   const void* tw(int axis) const { return prec == HP_FP64 ? tw64[axis].p : tw32[axis].p; }
   void release_all() {
     for (DevBuf* b : {&nodes, &pos, &grpmask, &rowmask, &slabneed, &storemask, &coef64, &coef32, &lam_ax, &lam_in, &t,
-                      &fields, &lagtab})
+                      &fields, &lagtab, &posa})
       b->release();
     for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
     release_solver_ws();
@@ -252,6 +255,7 @@ size_t hp_plan_workspace_bytes(const hp_grid* g, const hp_plan_opts* o, int K) {
   const size_t nr = (size_t)std::max(1, o->max_nrhs);
   size_t b = nr * npts * fs * (size_t)(K + 1);      // t and the K node fields
   b += npts * (8 + 32 + (o->precision == HP_FP64 ? 0 : 16));   // pos, coef64, coef32
+  if (o->m_damp >= 2) b += npts * 8;                           // posa
   return b;
 }
 
@@ -365,12 +369,30 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   // degree 2 or 3 on consecutive nodes (at most M - 1)
   if (opts->interp_order < 0 || opts->interp_order > 3) return failc(HP_E_INVALID);
   P->order = std::max(1, std::min(opts->interp_order, P->M - 1));
+  // bivariate (c, a): equidistant damping nodes on [a_min, a_max], real node (c_m, a_r)
+  // = node m + M r; no layer (its nodes would need a third axis), piecewise linear
+  if (opts->m_damp < 0 || opts->m_damp > hp::kMaxNodes) return failc(HP_E_INVALID);
+  if (opts->m_damp >= 2) {
+    if (has_layer || opts->interp_order >= 2 || opts->a_nodes) return failc(HP_E_INVALID);
+    double amin = a ? a[0] : 0.0, amax = amin;
+    if (a)
+      for (size_t i = 1; i < np; ++i) { amin = std::min(amin, a[i]); amax = std::max(amax, a[i]); }
+    if (amax > amin) {
+      P->Ma = opts->m_damp;
+      if (P->M * P->Ma > hp::kMaxNodes) return failc(HP_E_INVALID);
+      for (int r = 0; r < P->Ma; ++r) P->anode[r] = amin + (amax - amin) * ((double)r / (P->Ma - 1));
+      P->anode[P->Ma - 1] = amax;
+      P->K = P->M * P->Ma;
+    }
+  }
   hp::NodeTable T{};
   T.M = P->M;
   T.Mt = P->Mt;
   T.mo = P->mo;
   T.has_layer = has_layer ? 1 : 0;
   T.order = P->order;
+  T.Ma = P->Ma;
+  for (int i = 0; i < P->Ma; ++i) T.anode[i] = P->anode[i];
   for (int i = 0; i < P->M; ++i) T.cnode[i] = P->cnode[i];
   for (int i = 0; i <= P->Mt; ++i) T.znode[i] = P->znode[i];
   {
@@ -399,11 +421,12 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     sih2 += 1.0 / (h * h);
   }
   if ((e = P->pos.alloc(np * 8)) != hipSuccess) return failc(from_hip(e));
+  if (P->Ma >= 2 && (e = P->posa.alloc(np * 8)) != hipSuccess) return failc(from_hip(e));
   if ((e = P->coef64.alloc(np * 32)) != hipSuccess) return failc(from_hip(e));
   if (P->prec == HP_MIXED && (e = P->coef32.alloc(np * 16)) != hipSuccess) return failc(from_hip(e));
   if ((e = hp::launch_plan_points((const double*)dc.p, (const double*)da.p, (const double*)dz.p, np, T, omega, sih2,
-                                  (double*)P->pos.p, (cpx<double>*)P->coef64.p, (cpx<float>*)P->coef32.p, hs)) !=
-      hipSuccess)
+                                  (double*)P->pos.p, (double*)P->posa.p, (cpx<double>*)P->coef64.p,
+                                  (cpx<float>*)P->coef32.p, hs)) != hipSuccess)
     return failc(from_hip(e));
 
   // Node usage.  Each point has at most two non-zero weights, so a row of
@@ -412,7 +435,8 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   const int nl = P->n[P->dim - 1];
   const size_t rows = np / nl;
   if ((e = P->rowmask.alloc(rows * 8)) != hipSuccess) return failc(from_hip(e));
-  if ((e = hp::launch_row_masks((const double*)P->pos.p, nl, rows, T, (uint64_t*)P->rowmask.p, hs)) != hipSuccess)
+  if ((e = hp::launch_row_masks((const double*)P->pos.p, (const double*)P->posa.p, nl, rows, T,
+                                (uint64_t*)P->rowmask.p, hs)) != hipSuccess)
     return failc(from_hip(e));
   std::vector<uint64_t> rm(rows, 0);
   if ((e = hipMemcpyAsync(rm.data(), P->rowmask.p, rows * 8, hipMemcpyDeviceToHost, hs)) != hipSuccess ||
@@ -428,7 +452,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
       if (!(opts->a_nodes[m] >= 0) || !std::isfinite(opts->a_nodes[m])) return failc(HP_E_INVALID);
       P->ahat[m] = opts->a_nodes[m];
     }
-  } else if (a_varies) {
+  } else if (a_varies && P->Ma < 2) {
     std::vector<double> num(P->K, 0.0), den(P->K, 0.0);
     double mean = 0;
     for (size_t i = 0; i < np; ++i) {
@@ -447,6 +471,12 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   }
   for (int m = 0; m < P->M; ++m) P->ahat[m] = std::max(P->ahat[m], opts->a_floor);
   for (int m = 0; m < P->M; ++m) { P->gre[m] = P->cnode[m]; P->gim[m] = 0; }
+  for (int r = 0; r < P->Ma; ++r)   // bivariate: node m + M r carries (c_m, a_r)
+    for (int m = 0; m < P->M; ++m) {
+      P->gre[m + P->M * r] = P->cnode[m];
+      P->gim[m + P->M * r] = 0;
+      P->ahat[m + P->M * r] = std::max(P->anode[r], opts->a_floor);
+    }
   for (int j = 1; j <= P->Mt; ++j) {
     P->ahat[P->M + j - 1] = P->ahat[P->mo];
     P->gre[P->M + j - 1] = c0;
@@ -562,6 +592,9 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info) {
   info->workspace_bytes = p->t.bytes + p->fields.bytes + p->pos.bytes + p->coef64.bytes + p->coef32.bytes;
   info->precision = p->prec;
   info->interp_order = p->order;
+  info->m_damp = p->Ma;
+  for (int i = 0; i < 64; ++i) info->anode[i] = p->anode[i];
+  info->workspace_bytes += p->posa.bytes;
   return HP_OK;
 }
 
@@ -629,6 +662,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   c.grpmask = (const uint64_t*)P->grpmask.p; c.rowmask = (const uint64_t*)P->rowmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
   c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
   c.order = P->order; c.lag = (const double*)P->lagtab.p;
+  c.posa = (const double*)P->posa.p; c.Ma = P->Ma;
   for (int r = 0; r < (acc ? 1 : reps); ++r)
     if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
   return mark(5);

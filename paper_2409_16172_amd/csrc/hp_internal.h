@@ -121,6 +121,8 @@ struct CombineArgs {
   int order;           // real-axis interpolation degree in effect (1 = piecewise linear)
   const double* lag;   // order >= 2: real nodes [0, kMaxNodes), then for node n and stencil
                        // start n - r the inverse Lagrange denominator at kMaxNodes + 4n + r
+  const double* posa;  // Ma >= 2: per point, the position among the damping nodes (bilinear in (c, a))
+  int Ma;              // damping nodes of the bivariate scheme (0: univariate)
 };
 constexpr int kLagTable = kMaxNodes * 5;
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
@@ -191,16 +193,19 @@ hipError_t launch_media_scan(const double* c, const double* a, const double* zet
 struct NodeTable {
   int M, Mt, mo, has_layer;
   int order;   // real-axis interpolation degree in effect (1 = piecewise linear, else Lagrange)
+  int Ma;      // damping nodes of the bivariate (c, a) scheme, real node (m, r) = m + M r (0: off)
   double cnode[kMaxNodes];
   double znode[kMaxNodes + 1];
+  double anode[kMaxNodes];
 };
 // per point: interpolation record (see decode_pos) and stencil coefficients
 // {gamma^2, omega^2 + i omega a - 2 gamma^2 sum_j h_j^-2} in FP64 (and FP32 if coef32)
+// (and, for the bivariate scheme, the damping position posa)
 hipError_t launch_plan_points(const double* c, const double* a, const double* zeta, size_t n, const NodeTable& T,
-                              double omega, double sum_ih2, double* pos, cpx<double>* coef64, cpx<float>* coef32,
-                              hipStream_t st);
+                              double omega, double sum_ih2, double* pos, double* posa, cpx<double>* coef64,
+                              cpx<float>* coef32, hipStream_t st);
 // per row of nl points: bit k set if some point of the row has a non-zero weight on node k
-hipError_t launch_row_masks(const double* pos, int nl, size_t rows, const NodeTable& T, uint64_t* rowmask,
-                            hipStream_t st);
+hipError_t launch_row_masks(const double* pos, const double* posa, int nl, size_t rows, const NodeTable& T,
+                            uint64_t* rowmask, hipStream_t st);
 
 }  // namespace hp

@@ -244,17 +244,34 @@ __device__ __forceinline__ void decode_pos(double p, int M, int Mt, int mo, int&
   }
 }
 
+// Interpolation modes of the combine: piecewise linear along Re gamma (the
+// paper's), piecewise Lagrange of degree >= 2 along the real axis, and bilinear in
+// (c, a) (one damping node axis; no layer).
+enum InterpMode { kInterpLinear = 0, kInterpLagrange = 1, kInterpBilinear = 2 };
+
 // Per-point record for the combine: `ab` packs nodes A, B (piecewise linear:
 // weights 1-t, t) or, for a real-axis point under Lagrange interpolation of degree
 // ord >= 2, the first node A of its ord+1-node stencil and a flag; `tt` holds t,
-// or the point's speed x for the Lagrange weights.  lag: the table of CombineArgs.
-template <typename R, bool LAG>
-__device__ __forceinline__ void interp_record(double pv, int M, int Mt, int mo, int ord, const double* lag, int& ab,
-                                              R& tt) {
+// or the point's speed x for the Lagrange weights.  Bilinear: `ab` packs the four
+// nodes (s, r), (s+1, r), (s, r+1), (s+1, r+1) of node index m + M r, `tt` and `uu`
+// the fractions along c and along a.  lag: the table of CombineArgs.
+template <typename R, int IM>
+__device__ __forceinline__ void interp_record(double pv, double pa, int M, int Mt, int mo, int Ma, int ord,
+                                              const double* lag, int& ab, R& tt, R& uu) {
   int A = -1, B = -1;
   double t = 0.0;
   decode_pos(pv, M, Mt, mo, A, B, t);
-  if (LAG && pv >= 0.0 && M > 1) {
+  if (IM == kInterpBilinear) {
+    int r = (int)pa;
+    if (r > Ma - 2) r = Ma - 2;
+    if (r < 0) r = 0;
+    const double u = pa - (double)r;
+    A += M * r;
+    B += M * r;
+    ab = A | (B << 8) | ((A + M) << 16) | ((B + M) << 24);
+    tt = (R)t;
+    uu = (R)u;
+  } else if (IM == kInterpLagrange && pv >= 0.0 && M > 1) {
     int a = A - (ord - 1) / 2;
     a = a < 0 ? 0 : (a > M - 1 - ord ? M - 1 - ord : a);
     ab = a | (1 << 16);
@@ -265,11 +282,17 @@ __device__ __forceinline__ void interp_record(double pv, int M, int Mt, int mo, 
   }
 }
 
-// Weight of node n at a point with record (ab, tt).
-template <typename R, bool LAG>
-__device__ __forceinline__ R interp_weight(int ab, R tt, int n, int ord, const double* lag) {
+// Weight of node n at a point with record (ab, tt, uu).
+template <typename R, int IM>
+__device__ __forceinline__ R interp_weight(int ab, R tt, R uu, int n, int ord, const double* lag) {
   const int A = ab & 0xff;
-  if (LAG && (ab >> 16)) {
+  if (IM == kInterpBilinear) {
+    const int B = (ab >> 8) & 0xff, Cn = (ab >> 16) & 0xff, D = (ab >> 24) & 0xff;
+    const R lo = (R)1 - uu;
+    return (A == n ? ((R)1 - tt) * lo : (R)0) + (B == n ? tt * lo : (R)0) + (Cn == n ? ((R)1 - tt) * uu : (R)0) +
+           (D == n ? tt * uu : (R)0);
+  }
+  if (IM == kInterpLagrange && (ab >> 16)) {
     if (n < A || n > A + ord) return (R)0;
     R w = (R)lag[kMaxNodes + 4 * n + (n - A)];
     for (int k = A; k <= A + ord; ++k)
@@ -280,13 +303,14 @@ __device__ __forceinline__ R interp_weight(int ab, R tt, int n, int ord, const d
   return (A == n ? (R)1 - tt : (R)0) + (B == n ? tt : (R)0);
 }
 
-template <typename R, typename TO, int N, bool ACC, bool LAG>
+template <typename R, typename TO, int N, bool ACC, int IM>
 __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
     const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
     size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
-    const int* __restrict__ skip, int ord, const double* __restrict__ lag) {
+    const int* __restrict__ skip, int ord, const double* __restrict__ lag, const double* __restrict__ posa, int Ma) {
   using C = CombCfg<R, N>;
+  constexpr bool LAG = IM == kInterpLagrange;
   __shared__ cpx<R> lds[C::LDS];
   __shared__ double slag[LAG ? kLagTable : 1];
   const int rhs = blockIdx.y;
@@ -300,13 +324,18 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
   const bool act = row < rows;
   const size_t rbase = (size_t)row * N;
   int ab[C::E];
-  R tt[C::E];
+  R tt[C::E], uu[C::E];
   cpx<R> acc[C::E];
 #pragma unroll
   for (int s = 0; s < C::E; ++s) {
     ab[s] = 0xffff;
     tt[s] = (R)0;
-    if (act) interp_record<R, LAG>(pos[rbase + j + C::T * s], M, Mt, mo, ord, slag, ab[s], tt[s]);
+    uu[s] = (R)0;
+    if (act) {
+      const size_t pi = rbase + j + C::T * s;
+      interp_record<R, IM>(pos[pi], IM == kInterpBilinear ? posa[pi] : 0.0, M, Mt, mo, Ma, ord, slag, ab[s], tt[s],
+                           uu[s]);
+    }
     acc[s] = {0, 0};
   }
   const uint64_t mask = grpmask[blockIdx.x];
@@ -348,7 +377,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
     fft<R, N, +1, true>(x, lg, j, tw);
 #pragma unroll
     for (int s = 0; s < C::E; ++s) {
-      const R w = interp_weight<R, LAG>(ab[s], tt[s], n, ord, slag);
+      const R w = interp_weight<R, IM>(ab[s], tt[s], uu[s], n, ord, slag);
       acc[s].re += w * x[s].re;
       acc[s].im += w * x[s].im;
     }
@@ -565,7 +594,7 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
 
 // Pass C: inverse transform along rows of every node the row uses, and the
 // hat-weighted combine (weights 1-t on node A, t on node B of each point).
-template <typename R, typename TO, bool ACC, bool LAG>
+template <typename R, typename TO, bool ACC, int IM>
 __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<R>* __restrict__ fields, size_t fs,
                                                            size_t frs, const double* __restrict__ pos,
                                                            const uint64_t* __restrict__ rowmask,
@@ -573,7 +602,9 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
                                                            int Mt, int mo, GenPlan gp,
                                                            const cpx<R>* __restrict__ tw,
                                                            const int* __restrict__ skip, int ord,
-                                                           const double* __restrict__ lag) {
+                                                           const double* __restrict__ lag,
+                                                           const double* __restrict__ posa, int Ma) {
+  constexpr bool LAG = IM == kInterpLagrange;
   extern __shared__ char dyn_lds[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
   __shared__ double slag[LAG ? kLagTable : 1];
@@ -586,14 +617,17 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
   }
   const size_t row = blockIdx.x, rbase = row * n;
   int ab[gen_e<R>()];
-  R tt[gen_e<R>()];
+  R tt[gen_e<R>()], uu[gen_e<R>()];
   cpx<R> acc[gen_e<R>()];
 #pragma unroll
   for (int i = 0; i < gen_e<R>(); ++i) {
     const int p = tid + i * nthr;
     ab[i] = 0xffff;
     tt[i] = (R)0;
-    if (p < n) interp_record<R, LAG>(pos[rbase + p], M, Mt, mo, ord, slag, ab[i], tt[i]);
+    uu[i] = (R)0;
+    if (p < n)
+      interp_record<R, IM>(pos[rbase + p], IM == kInterpBilinear ? posa[rbase + p] : 0.0, M, Mt, mo, Ma, ord, slag,
+                           ab[i], tt[i], uu[i]);
     acc[i] = {0, 0};
   }
   const uint64_t rm = rowmask[row];
@@ -607,7 +641,7 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
     for (int i = 0; i < gen_e<R>(); ++i) {
       const int p = tid + i * nthr;
       if (p < n) {
-        const R w = interp_weight<R, LAG>(ab[i], tt[i], nd, ord, slag);
+        const R w = interp_weight<R, IM>(ab[i], tt[i], uu[i], nd, ord, slag);
         const cpx<R> x = buf[p];
         acc[i].re += w * x.re;
         acc[i].im += w * x.im;
@@ -749,18 +783,25 @@ static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st)
   return hipGetLastError();
 }
 
-template <typename R, typename TO, bool ACC, bool LAG>
+template <typename R, typename TO, bool ACC, int IM>
 static hipError_t combine_gen_l(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
   const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
-  allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC, LAG>, lds);
-  hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC, LAG>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
+  allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC, IM>, lds);
+  hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC, IM>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
                      (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
-                     a.Mt, a.mo, gp, (const cpx<R>*)a.tw, a.skip, a.order, a.lag);
+                     a.Mt, a.mo, gp, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa, a.Ma);
   return hipGetLastError();
+}
+static int interp_mode(const CombineArgs& a) {
+  return a.order >= 2 ? kInterpLagrange : (a.Ma >= 2 ? kInterpBilinear : kInterpLinear);
 }
 template <typename R, typename TO, bool ACC>
 static hipError_t combine_gen(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
-  return a.order >= 2 ? combine_gen_l<R, TO, ACC, true>(gp, a, st) : combine_gen_l<R, TO, ACC, false>(gp, a, st);
+  switch (interp_mode(a)) {
+    case kInterpLagrange: return combine_gen_l<R, TO, ACC, kInterpLagrange>(gp, a, st);
+    case kInterpBilinear: return combine_gen_l<R, TO, ACC, kInterpBilinear>(gp, a, st);
+    default: return combine_gen_l<R, TO, ACC, kInterpLinear>(gp, a, st);
+  }
 }
 
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
@@ -838,14 +879,25 @@ struct CombineL {
     static hipError_t run(const CombineArgs& a, hipStream_t st) {
       using C = CombCfg<R, N>;
       dim3 grid((a.rows + C::G - 1) / C::G, a.nrhs);
-      if (a.order >= 2)
-        hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, true>), grid, dim3(C::THREADS), 0, st,
-                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
-                           a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag);
-      else
-        hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, false>), grid, dim3(C::THREADS), 0, st,
-                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
-                           a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag);
+      switch (interp_mode(a)) {
+        case kInterpLagrange:
+          hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLagrange>), grid, dim3(C::THREADS), 0, st,
+                             (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                             a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag,
+                             a.posa, a.Ma);
+          break;
+        case kInterpBilinear:
+          hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpBilinear>), grid, dim3(C::THREADS), 0, st,
+                             (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                             a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag,
+                             a.posa, a.Ma);
+          break;
+        default:
+          hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLinear>), grid, dim3(C::THREADS), 0, st,
+                             (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                             a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag,
+                             a.posa, a.Ma);
+      }
       return hipGetLastError();
     }
   };
@@ -1674,14 +1726,24 @@ __device__ double encode_pos(const NodeTable& T, double c, double z) {
   return lo + t;
 }
 
+// Position of damping a among the damping nodes of the bivariate scheme: r + u with
+// weights 1-u on node r and u on node r+1 (r in [0, Ma-2]).
+__device__ double encode_damping(const NodeTable& T, double a) {
+  const double aa = fmin(fmax(a, T.anode[0]), T.anode[T.Ma - 1]);
+  int lo = 0, hi = T.Ma - 1;
+  while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (T.anode[mid] <= aa) lo = mid; else hi = mid; }
+  return lo + (aa - T.anode[lo]) / (T.anode[lo + 1] - T.anode[lo]);
+}
+
 __global__ __launch_bounds__(256) void k_plan_points(const double* __restrict__ c, const double* __restrict__ a,
                                                      const double* __restrict__ z, size_t n, NodeTable T,
                                                      double omega, double sih2, double* __restrict__ pos,
-                                                     cpx<double>* __restrict__ coef64,
+                                                     double* __restrict__ posa, cpx<double>* __restrict__ coef64,
                                                      cpx<float>* __restrict__ coef32) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const double cv = c[i], zv = z ? z[i] : 0.0, av = a ? a[i] : 0.0;
     pos[i] = encode_pos(T, cv, T.has_layer ? zv : 0.0);
+    if (T.Ma >= 2) posa[i] = encode_damping(T, av);
     const double gr = cv * cv * (1.0 - zv * zv), gi = -2.0 * cv * cv * zv;   // (c (1 - i zeta))^2
     const cpx<double> g2 = {gr, gi}, be = {omega * omega - 2.0 * gr * sih2, omega * av - 2.0 * gi * sih2};
     coef64[2 * i] = g2;
@@ -1693,8 +1755,8 @@ __global__ __launch_bounds__(256) void k_plan_points(const double* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void k_row_masks(const double* __restrict__ pos, int nl, NodeTable T,
-                                                   uint64_t* __restrict__ rowmask) {
+__global__ __launch_bounds__(256) void k_row_masks(const double* __restrict__ pos, const double* __restrict__ posa,
+                                                   int nl, NodeTable T, uint64_t* __restrict__ rowmask) {
   __shared__ uint64_t sm[256];
   const size_t row = blockIdx.x;
   uint64_t m = 0;
@@ -1703,6 +1765,19 @@ __global__ __launch_bounds__(256) void k_row_masks(const double* __restrict__ po
     double t;
     const double pv = pos[row * nl + i];
     decode_pos(pv, T.M, T.Mt, T.mo, A, B, t);
+    if (T.Ma >= 2) {   // the four nodes of the bilinear cell, where their weight is non-zero
+      double pa = posa[row * nl + i];
+      int r = (int)pa;
+      r = r > T.Ma - 2 ? T.Ma - 2 : r;
+      const double u = pa - (double)r;
+      const double wc[2] = {A == B ? 1.0 : 1.0 - t, A == B ? 0.0 : t};
+      const double wa[2] = {1.0 - u, u};
+      const int nc[2] = {A, B};
+      for (int q = 0; q < 2; ++q)
+        for (int p = 0; p < 2; ++p)
+          if (wc[p] != 0.0 && wa[q] != 0.0) m |= 1ull << (nc[p] + T.M * (r + q));
+      continue;
+    }
     if (T.order >= 2 && pv >= 0.0 && T.M > 1) {   // the whole Lagrange stencil
       int a = A - (T.order - 1) / 2;
       a = a < 0 ? 0 : (a > T.M - 1 - T.order ? T.M - 1 - T.order : a);
@@ -1728,17 +1803,19 @@ hipError_t launch_media_scan(const double* c, const double* a, const double* zet
 }
 
 hipError_t launch_plan_points(const double* c, const double* a, const double* zeta, size_t n, const NodeTable& T,
-                              double omega, double sum_ih2, double* pos, cpx<double>* coef64, cpx<float>* coef32,
-                              hipStream_t st) {
+                              double omega, double sum_ih2, double* pos, double* posa, cpx<double>* coef64,
+                              cpx<float>* coef32, hipStream_t st) {
+  if (T.Ma >= 2 && posa == nullptr) return hipErrorInvalidValue;
   const size_t b = (n + 255) / 256;
   hipLaunchKernelGGL(k_plan_points, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, st, c, a, zeta, n, T, omega,
-                     sum_ih2, pos, coef64, coef32);
+                     sum_ih2, pos, posa, coef64, coef32);
   return hipGetLastError();
 }
 
-hipError_t launch_row_masks(const double* pos, int nl, size_t rows, const NodeTable& T, uint64_t* rowmask,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_row_masks, dim3((unsigned)rows), dim3(256), 0, st, pos, nl, T, rowmask);
+hipError_t launch_row_masks(const double* pos, const double* posa, int nl, size_t rows, const NodeTable& T,
+                            uint64_t* rowmask, hipStream_t st) {
+  if (T.Ma >= 2 && posa == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_row_masks, dim3((unsigned)rows), dim3(256), 0, st, pos, posa, nl, T, rowmask);
   return hipGetLastError();
 }
 
