@@ -98,9 +98,9 @@ def serving_run(dev, n_requests=24, rate=40.0):
     return st
 
 
-def large_grid_compare(dev, reps=2):
+def large_grid_compare(dev, reps=2, tune=True):
     """2048^2, 200 wavelengths, 24 + 3 nodes: mixed precision against the FP64 GPU
-    path, both to the FP64 true residual 1e-8."""
+    path, both to the FP64 true residual 1e-8 (plans autotuned unless tune is False)."""
     import torch
     from paper_2409_16172_amd import binding, inputs
     w = inputs.workload("2d_2048_grf")
@@ -108,6 +108,8 @@ def large_grid_compare(dev, reps=2):
     out = {}
     for prec in ("mixed", "fp64"):
         p = binding.plan_from_workload(w, precision=prec)
+        if tune:
+            p.autotune()
         p.solve(f)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -388,6 +390,37 @@ def bivariate_compare(args, dev):
                       "rows": rows}))
 
 
+def autotune_compare(args, dev):
+    """The transform-pass autotuner on the benchmark grids: 1024^2 FP64 and 2048^2 mixed
+    (power-of-two: node groups of the symbol pass), Example 1's 2400^2, 3600^2 and
+    4800^2 FP64 (mixed radix: threads per line, lines per workgroup, radix schedule);
+    per-pass apply time before and after, and the choices."""
+    import torch
+    from paper_2409_16172_amd import binding, inputs
+    cases = [("2d_1024_grf", {}), ("2d_2048_grf", {})] + [("2d_inclusion", {"n": n}) for n in (2400, 3600, 4800)]
+    rows = []
+    rng = np.random.default_rng(0)
+    for name, kw in cases:
+        w = inputs.workload(name, **kw)
+        p = binding.plan_from_workload(w)
+        dt = torch.complex128 if w.precision == "fp64" else torch.complex64
+        v = torch.from_numpy(rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape))[None].to(dev).to(dt)
+        ms0, _ = p.profile_apply(v, reps=10)
+        t0 = time.perf_counter()
+        before, after = p.autotune()
+        tune_s = time.perf_counter() - t0
+        ms1, _ = p.profile_apply(v, reps=10)
+        row = {"workload": w.name, "precision": w.precision, "K": p.info()["K"], "tune_seconds": tune_s,
+               "apply_us_before": sum(ms0) * 1e3, "apply_us_after": sum(ms1) * 1e3,
+               "pass_us_before": [round(t * 1e3, 1) for t in ms0], "pass_us_after": [round(t * 1e3, 1) for t in ms1],
+               "choices": p.info()["tune"]}
+        print(f"[bench] autotune {w.name} ({w.precision}): apply {row['apply_us_before']:.0f} -> "
+              f"{row['apply_us_after']:.0f} us in {tune_s:.1f} s, choices {row['choices']}", file=sys.stderr, flush=True)
+        rows.append(row)
+        p.close()
+    print(json.dumps({"mode": "autotune", "rows": rows}))
+
+
 def apply_only(args, w, plan, dev):
     import numpy as np
     import torch
@@ -418,6 +451,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="2d_1024_grf")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in pass choices")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
@@ -437,14 +471,16 @@ def main():
                     help="estimate min |lambda(P_N)| by inverse runs instead of the bound omega a")
     ap.add_argument("--spec-nodes", type=int, nargs="+", default=[1, 2, 4, 8])
     ap.add_argument("--spec-tables", nargs="*", default=[], help="subset of table2..table6")
-    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp", "spectrum", "bivariate"],
+    ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp", "spectrum", "bivariate",
+                                       "autotune"],
                     default="solve",
                     help="apply: only event-timed preconditioner applies plus a copy kernel of known size "
                          "(used to calibrate hardware byte counters); batch3d: the 3-D multi-source batch; "
                          "example1: the paper's Example 1 (Table 1 complexity, GMRES comparison); "
                          "interp: interpolation degree against node count; "
                          "spectrum: condition numbers of Tables 2-6 from GPU Arnoldi runs; "
-                         "bivariate: (c, a) interpolation against the univariate scheme")
+                         "bivariate: (c, a) interpolation against the univariate scheme; "
+                         "autotune: the transform-pass autotuner on the benchmark grids")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -473,10 +509,15 @@ def main():
     if args.mode == "bivariate":
         bivariate_compare(args, dev)
         return
+    if args.mode == "autotune":
+        autotune_compare(args, dev)
+        return
     w = inputs.workload(args.workload)
     if args.precision:
         w.precision = args.precision
     plan = binding.plan_from_workload(w)
+    if not args.no_autotune:   # once per grid, as a user would (plan set-up, untimed)
+        plan.autotune()
     f = torch.from_numpy(w.f).to(dev)
     if args.mode == "apply":
         apply_only(args, w, plan, dev)
@@ -521,6 +562,8 @@ def main():
     mixed = None
     if not args.no_mixed:
         pm = binding.plan_from_workload(w, precision="mixed")
+        if not args.no_autotune:
+            pm.autotune()
         pm.solve(f, rtol=rtol, restart=restart)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -534,7 +577,7 @@ def main():
         pm.close()
 
     serving = None if args.no_serve else serving_run(dev, args.serve_requests, args.serve_rate)
-    large = None if args.no_large else large_grid_compare(dev)
+    large = None if args.no_large else large_grid_compare(dev, tune=not args.no_autotune)
     cpu = None if args.no_cpu else cpu_baseline(w, info.iters, info.cycles)
     lat_ms = sorted(t * 1e3 for t in lat)
     out = {

@@ -152,6 +152,9 @@ typedef struct {
   int m_damp;                /* damping nodes of the bivariate scheme (0: univariate);
                                 real node (c_m, a_r) is node m + M r */
   double anode[64];          /* damping nodes a_r             */
+  int tune[5][4];            /* run-time choices of passes A, A', B, M, C: threads per
+                                line, lines per workgroup, radix schedule, node groups
+                                (0 = built-in); see hp_plan_autotune */
 } hp_plan_info;
 
 /* Build a plan: upload and validate the media, place the nodes, and compute in
@@ -281,6 +284,18 @@ hp_status hp_solver_destroy(hp_solver s);
  * some point of a row uses (the others are neither written nor read). */
 hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps, double* ms, double* bytes,
                            void* stream);
+
+/* Autotuner of the transform passes: for each pass in turn, times the plan's apply
+ * (one right-hand side) under every valid run-time choice — threads per line, lines
+ * per workgroup and radix schedule of the mixed-radix passes (N = 2^a 3^b 5^c),
+ * node groups per column tile of the power-of-two symbol pass — and keeps the
+ * fastest (by at least 2 %); the plan then uses it for every apply, matvec-free
+ * solve step and session.  Only the radix schedule changes results (rounding).
+ * If the environment variable HP_TUNE_CACHE names a file the choices are appended
+ * to it, and hp_plan_create reads it for plans of the same grid, precision and K.
+ * before_ms / after_ms (may be NULL): the summed per-pass apply time before and
+ * after.  Allocates two temporary device fields; blocks (a few hundred applies). */
+hp_status hp_plan_autotune(hp_plan p, double* before_ms, double* after_ms, void* stream);
 
 hp_status hp_plan_destroy(hp_plan p);
 

@@ -26,7 +26,7 @@ EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_byt
             "hp_apply_precond", "hp_matvec", "hp_solve", "hp_profile_apply", "hp_plan_destroy",
             "hp_status_str", "hp_last_error", "hp_solver_create", "hp_solver_start", "hp_solver_advance",
             "hp_solver_wait", "hp_solver_destroy", "hp_arnoldi", "hp_ritz_values",
-            "hp_arnoldi_vector", "hp_extreme_eigenvalue"]
+            "hp_arnoldi_vector", "hp_extreme_eigenvalue", "hp_plan_autotune"]
 
 
 class HpGrid(C.Structure):
@@ -64,7 +64,7 @@ class HpPlanInfo(C.Structure):
                 ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
                 ("gamma_re", C.c_double * 64), ("gamma_im", C.c_double * 64),
                 ("workspace_bytes", C.c_size_t), ("precision", C.c_int), ("interp_order", C.c_int),
-                ("m_damp", C.c_int), ("anode", C.c_double * 64)]
+                ("m_damp", C.c_int), ("anode", C.c_double * 64), ("tune", (C.c_int * 4) * 5)]
 
 
 _lib = None
@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH):
     lib.hp_arnoldi.restype = i
     lib.hp_ritz_values.argtypes = [vp, i, i, i, vp, vp, C.POINTER(d)]
     lib.hp_ritz_values.restype = i
+    lib.hp_plan_autotune.argtypes = [vp, C.POINTER(d), C.POINTER(d), vp]
+    lib.hp_plan_autotune.restype = i
     lib.hp_arnoldi_vector.argtypes = [vp, vp, i, vp, vp]
     lib.hp_arnoldi_vector.restype = i
     lib.hp_extreme_eigenvalue.argtypes = [vp, vp, i, i, i, i, d, vp, C.POINTER(d), C.POINTER(i), vp]
@@ -235,7 +237,8 @@ class Plan:
                 "znode": np.array(pi.znode[:pi.Mt + 1]), "ahat": np.array(pi.ahat[:K]),
                 "gamma": np.array(pi.gamma_re[:K]) + 1j * np.array(pi.gamma_im[:K]),
                 "workspace_bytes": int(pi.workspace_bytes), "interp_order": int(pi.interp_order),
-                "m_damp": int(pi.m_damp), "anode": np.array(pi.anode[:pi.m_damp])}
+                "m_damp": int(pi.m_damp), "anode": np.array(pi.anode[:pi.m_damp]),
+                "tune": [tuple(int(x) for x in pi.tune[k]) for k in range(5)]}
 
     def _fields(self, x, dtype, name):
         import torch
@@ -299,6 +302,13 @@ class Plan:
         _check(load_library().hp_arnoldi(self._h, C.c_void_p(v0.data_ptr()), int(m), ARNOLDI_OPS[side],
                                          C.c_void_p(H.ctypes.data), C.byref(steps), _stream(stream)), "hp_arnoldi")
         return H, steps.value
+
+    def autotune(self, stream=None):
+        """Pick the fastest run-time choices of the transform passes (see hp_plan_autotune);
+        returns (apply ms before, apply ms after)."""
+        b, a = C.c_double(0.0), C.c_double(0.0)
+        _check(load_library().hp_plan_autotune(self._h, C.byref(b), C.byref(a), _stream(stream)), "hp_plan_autotune")
+        return b.value, a.value
 
     def arnoldi_vector(self, y, out=None, stream=None):
         """V_k y from the basis of the last arnoldi() on this plan (y: k complex numbers)."""

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -40,6 +41,12 @@ bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1))
 
 }  // namespace
 
+struct hp_plan_s;
+namespace {
+void load_tune(hp_plan_s& P);
+void save_tune(const hp_plan_s& P);
+}  // namespace
+
 struct hp_plan_s {
   int dim = 2;
   int n[3] = {1, 1, 1};
@@ -57,6 +64,7 @@ struct hp_plan_s {
   DevBuf nodes, pos, grpmask, rowmask, slabneed, storemask, coef64, coef32, lam_ax, lam_in, tw64[3], tw32[3];
   int order = 1;   // real-axis interpolation degree in effect
   DevBuf lagtab;   // Lagrange table of CombineArgs::lag (order >= 2)
+  hp::PassTune tune[5];   // run-time choices of passes A, A', B, M, C (hp_plan_autotune)
   int Ma = 0;      // damping nodes of the bivariate (c, a) scheme (0: univariate)
   double anode[64] = {0};
   DevBuf posa;     // per point: position among the damping nodes (Ma >= 2)
@@ -566,6 +574,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   if ((e = hp::launch_fill_zero(P->fields.p, P->fields.bytes, hs)) != hipSuccess) return failc(from_hip(e));
   if ((e = hipStreamSynchronize(hs)) != hipSuccess) return failc(from_hip(e));
   cleanup();
+  load_tune(*P);
   *out = P;
   return HP_OK;
 }
@@ -593,6 +602,12 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info) {
   info->precision = p->prec;
   info->interp_order = p->order;
   info->m_damp = p->Ma;
+  for (int sl = 0; sl < 5; ++sl) {
+    info->tune[sl][0] = p->tune[sl].nthr;
+    info->tune[sl][1] = p->tune[sl].tc;
+    info->tune[sl][2] = p->tune[sl].order;
+    info->tune[sl][3] = p->tune[sl].ng;
+  }
   for (int i = 0; i < 64; ++i) info->anode[i] = p->anode[i];
   info->workspace_bytes += p->posa.bytes;
   return HP_OK;
@@ -624,7 +639,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   };
   if ((e = mark(0)) != hipSuccess) return e;
   for (int r = 0; r < reps; ++r) {
-    e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, st);
+    e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, P->tune[0],
+                            st);
     if (e != hipSuccess) return e;
   }
   if ((e = mark(1)) != hipSuccess) return e;
@@ -633,6 +649,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.real_kind = rk; m.n = P->n[1]; m.dir = -1; m.mode = 0;
     m.in = P->t.p; m.out = P->t.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = 1; m.nrhs = nrhs;
     m.in_rs = np; m.out_rs = np; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
+    m.tune = P->tune[1];
     if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
   }
   if ((e = mark(2)) != hipSuccess) return e;
@@ -644,6 +661,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
   b.store_mask = (const uint16_t*)P->storemask.p;
   b.store_need = (const uint8_t*)P->slabneed.p;
+  b.tune = P->tune[2];
   for (int r = 0; r < reps; ++r)
     if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
   if ((e = mark(3)) != hipSuccess) return e;
@@ -653,6 +671,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.in = P->fields.p; m.out = P->fields.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = P->K; m.nrhs = nrhs;
     m.in_rs = np * P->K; m.out_rs = np * P->K; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.slab_need = (const uint8_t*)P->slabneed.p;
+    m.tune = P->tune[3];
     if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
   }
   if ((e = mark(4)) != hipSuccess) return e;
@@ -663,9 +682,78 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
   c.order = P->order; c.lag = (const double*)P->lagtab.p;
   c.posa = (const double*)P->posa.p; c.Ma = P->Ma;
+  c.tune = P->tune[4];
   for (int r = 0; r < (acc ? 1 : reps); ++r)
     if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
   return mark(5);
+}
+
+// Per-launch time (ms) of each pass slot (A, A', B, M, C; 0 for slots a 2-D grid does
+// not have): one plain apply first (fills the intermediate buffers and warms the
+// caches), then every out-of-place pass reps times back to back between a pair of
+// events, so that an event pair brackets a run of launches of one kernel and the
+// per-launch figure is that kernel's duration (the in-place 3-D middle-axis passes run
+// once).
+hipError_t time_passes(hp_plan_s* p, const void* v, void* u, int nrhs, int reps, double* ms, hipStream_t st) {
+  const int kind = p->prec == HP_FP64 ? 0 : 1;
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) {
+    hipError_t e = hipEventCreate(&ev[i]);
+    if (e != hipSuccess) {
+      for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+      return e;
+    }
+  }
+  double acc[5] = {0, 0, 0, 0, 0};
+  hipError_t err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st);
+  if (err == hipSuccess) err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st, ev, reps);
+  if (err == hipSuccess) err = hipEventSynchronize(ev[5]);
+  const int slots3[5][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}};
+  const int slots2[5][2] = {{0, 1}, {-1, -1}, {1, 3}, {-1, -1}, {3, 5}};
+  const int count[5] = {reps, 1, reps, 1, reps};
+  for (int i = 0; i < 5 && err == hipSuccess; ++i) {
+    const int a = p->dim == 3 ? slots3[i][0] : slots2[i][0], b = p->dim == 3 ? slots3[i][1] : slots2[i][1];
+    if (a < 0) continue;
+    float t = 0;
+    err = hipEventElapsedTime(&t, ev[a], ev[b]);
+    acc[i] = (double)t / count[i];
+  }
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 5; ++i) ms[i] = acc[i];
+  return err;
+}
+
+// Tuning cache: the file named by HP_TUNE_CACHE, one line per pass choice,
+//   hp-tune <dim> <n0> <n1> <n2> <precision> <K> <slot> <nthr> <tc> <order> <ng>
+// appended by hp_plan_autotune and read (later lines win) when a plan is created.
+void load_tune(hp_plan_s& P) {
+  const char* path = std::getenv("HP_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char tag[16];
+  int d, n0, n1, n2, prec, K, slot, nthr, tc, order, ng;
+  while (std::fscanf(f, "%15s %d %d %d %d %d %d %d %d %d %d %d", tag, &d, &n0, &n1, &n2, &prec, &K, &slot, &nthr, &tc,
+                     &order, &ng) == 12) {
+    if (std::strcmp(tag, "hp-tune") != 0 || d != P.dim || n0 != P.n[0] || n1 != P.n[1] || n2 != P.n[2] ||
+        prec != P.prec || K != P.K || slot < 0 || slot > 4)
+      continue;
+    P.tune[slot] = hp::PassTune{std::max(0, nthr), std::max(0, tc), std::max(0, order), std::max(0, ng)};
+  }
+  std::fclose(f);
+}
+
+void save_tune(const hp_plan_s& P) {
+  const char* path = std::getenv("HP_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  for (int sl = 0; sl < 5; ++sl) {
+    const hp::PassTune& t = P.tune[sl];
+    std::fprintf(f, "hp-tune %d %d %d %d %d %d %d %d %d %d %d\n", P.dim, P.n[0], P.n[1], P.n[2], P.prec, P.K, sl, t.nthr,
+                 t.tc, t.order, t.ng);
+  }
+  std::fclose(f);
 }
 
 // Algorithmic bytes of each pass for one launch over nrhs fields.
@@ -1196,32 +1284,68 @@ hp_status hp_solver_destroy(hp_solver s) {
 hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps, double* ms, double* bytes,
                            void* stream) {
   if (!p || !v || !u || !ms || !bytes || nrhs < 1 || nrhs > p->max_nrhs || reps < 1) return HP_E_INVALID;
-  hipStream_t st = (hipStream_t)stream;
-  const int kind = p->prec == HP_FP64 ? 0 : 1;
-  hipEvent_t ev[6];
-  for (int i = 0; i < 6; ++i) HP_TRY(hipEventCreate(&ev[i]));
-  // one plain apply first (fills the intermediate buffers and warms the caches), then
-  // every out-of-place pass reps times back to back between a pair of events, so that
-  // an event pair brackets a run of launches of one kernel and the per-launch figure
-  // is that kernel's duration (the in-place 3-D middle-axis passes run once).
-  double acc[5] = {0, 0, 0, 0, 0};
-  hipError_t err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st);
-  if (err == hipSuccess) err = run_apply(p, v, kind, p->npts, u, kind, p->npts, false, nrhs, nullptr, st, ev, reps);
-  if (err == hipSuccess) err = hipEventSynchronize(ev[5]);
-  const int slots3[5][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}};
-  const int slots2[5][2] = {{0, 1}, {-1, -1}, {1, 3}, {-1, -1}, {3, 5}};
-  const int count[5] = {reps, 1, reps, 1, reps};
-  for (int i = 0; i < 5 && err == hipSuccess; ++i) {
-    const int a = p->dim == 3 ? slots3[i][0] : slots2[i][0], b = p->dim == 3 ? slots3[i][1] : slots2[i][1];
-    if (a < 0) continue;
-    float t = 0;
-    err = hipEventElapsedTime(&t, ev[a], ev[b]);
-    acc[i] = (double)t / count[i];
-  }
-  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
-  HP_TRY(err);
+  double acc[5];
+  HP_TRY(time_passes(p, v, u, nrhs, reps, acc, (hipStream_t)stream));
   for (int i = 0; i < 5; ++i) ms[i] = acc[i];
   pass_bytes(p, nrhs, (int)p->fsize(), (int)p->fsize(), bytes);
+  return HP_OK;
+}
+
+hp_status hp_plan_autotune(hp_plan p, double* before_ms, double* after_ms, void* stream) {
+  if (!p) return HP_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  DevBuf v, u;
+  HP_TRY(v.alloc(p->npts * p->fsize()));
+  HP_TRY(u.alloc(p->npts * p->fsize()));
+  HP_TRY(hp::launch_fill_zero(v.p, v.bytes, st));
+  const int rk = p->real_kind();
+  const int nl = p->n[p->dim - 1];
+  const size_t S0 = p->npts / p->n[0];
+  // per slot: candidate kind, line length, lines across, mode
+  struct Slot { int kind, n, S, mode; bool used; };
+  const Slot slots[5] = {{hp::kTuneRows, nl, 1, 0, true},
+                         {hp::kTuneCols, p->n[1], p->n[2], 0, p->dim == 3},
+                         {hp::kTuneCols, p->n[0], (int)S0, 1, true},
+                         {hp::kTuneCols, p->n[1], p->n[2], 0, p->dim == 3},
+                         {hp::kTuneCombine, nl, 1, 0, true}};
+  // the fastest of three timings of every pass (the in-place 3-D passes run once per apply)
+  auto measure = [&](double* t) -> hipError_t {
+    for (int i = 0; i < 5; ++i) t[i] = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+      double m[5];
+      hipError_t e = time_passes(p, v.p, u.p, 1, 4, m, st);
+      if (e != hipSuccess) return e;
+      for (int i = 0; i < 5; ++i) t[i] = std::min(t[i], m[i]);
+    }
+    return hipSuccess;
+  };
+  double base[5];
+  HP_TRY(measure(base));
+  double best_t[5];
+  for (int i = 0; i < 5; ++i) best_t[i] = base[i];
+  // one pass at a time, the others at their current choice; a candidate must win by 2 %
+  for (int sl = 0; sl < 5; ++sl) {
+    if (!slots[sl].used) continue;
+    hp::PassTune cand[64];
+    const int nc = hp::tune_candidates(rk, slots[sl].kind, slots[sl].n, slots[sl].S, slots[sl].mode, p->K, cand, 64);
+    hp::PassTune best = p->tune[sl];
+    for (int c = 0; c < nc; ++c) {
+      p->tune[sl] = cand[c];
+      double t[5];
+      HP_TRY(measure(t));
+      if (t[sl] < 0.98 * best_t[sl]) {
+        best_t[sl] = t[sl];
+        best = cand[c];
+      }
+    }
+    p->tune[sl] = best;
+  }
+  double fin[5];
+  HP_TRY(measure(fin));
+  HP_TRY(hipStreamSynchronize(st));
+  if (before_ms) *before_ms = base[0] + base[1] + base[2] + base[3] + base[4];
+  if (after_ms) *after_ms = fin[0] + fin[1] + fin[2] + fin[3] + fin[4];
+  save_tune(*p);
   return HP_OK;
 }
 

@@ -69,10 +69,28 @@ struct GenPlan {
 };
 // Fills *gp for length n, E elements per thread and at most maxthr threads per
 // line; false if n is not a product of 2, 3 and 5 within kGenMaxN or does not fit.
-bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp);
+// order: radix schedule (0: 4,2,3,5; 1: 5,3,4,2; 2: 3,5,4,2; 3: 2,4,3,5 — each radix
+// taken as often as it divides what is left); nthr_req > 0 asks for that many threads
+// per line (false if it does not fit E and maxthr).
+bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order = 0, int nthr_req = 0);
+constexpr int kGenOrders = 4;
 // Every mixed-radix kernel can take lines of length n.
 bool gen_length_ok(int n);
 inline bool is_pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Run-time choices of a transform pass (0 = the built-in choice): threads per line,
+// lines per workgroup (column passes) and radix schedule of the mixed-radix passes,
+// node groups per column tile of the power-of-two symbol pass.  None of them changes
+// the arithmetic except the radix schedule (rounding only).
+struct PassTune {
+  int nthr = 0, tc = 0, order = 0, ng = 0;
+};
+// slot kinds of the candidates below: 0 pass A (rows forward), 1 column pass (B, A', M),
+// 2 pass C (rows inverse + combine)
+constexpr int kTuneRows = 0, kTuneCols = 1, kTuneCombine = 2;
+// Valid choices for one pass over lines of length n (S lines across for column passes;
+// mode 1 = the symbol pass, K node fields); writes at most max and returns the count.
+int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, PassTune* out, int max);
 
 // ---- launchers (all enqueue on `st`, return the launch status) ----
 
@@ -80,7 +98,7 @@ inline bool is_pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
 // in_kind: 0 = complex128 input, 1 = complex64 input.  real_kind: 0 = FP64, 1 = FP32.
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
                            size_t in_rs, size_t out_rs, int nrhs, const void* tw, const int* skip,
-                           hipStream_t st);
+                           const PassTune& tune, hipStream_t st);
 
 // Strided-axis transform over column tiles: element (o, p, c) at o*n*S + p*S + c.
 // mode 0: plain transform (dir -1/+1) of nfields fields;
@@ -101,6 +119,7 @@ struct ColsArgs {
   const uint16_t* store_mask;   // mode 1: [K][T] bit s = axis-0 index j + T*s uses node n
   const uint8_t* slab_need;     // mode 0 over node fields: [K][outer] != 0 if the slab uses node n
   const uint8_t* store_need;    // mode 1, mixed-radix lengths: [K][n] != 0 if axis-0 index p uses node n
+  PassTune tune;
 };
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st);
 
@@ -123,6 +142,7 @@ struct CombineArgs {
                        // start n - r the inverse Lagrange denominator at kMaxNodes + 4n + r
   const double* posa;  // Ma >= 2: per point, the position among the damping nodes (bilinear in (c, a))
   int Ma;              // damping nodes of the bivariate scheme (0: univariate)
+  PassTune tune;
 };
 constexpr int kLagTable = kMaxNodes * 5;
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);

@@ -697,8 +697,9 @@ struct RowsFwdL {
 };
 
 // ---- mixed-radix launch helpers
-bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp) {
-  if (n < 2 || n > kGenMaxN) return false;
+bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order, int nthr_req) {
+  static const int kOrder[kGenOrders][4] = {{4, 2, 3, 5}, {5, 3, 4, 2}, {3, 5, 4, 2}, {2, 4, 3, 5}};
+  if (n < 2 || n > kGenMaxN || order < 0 || order >= kGenOrders) return false;
   GenPlan g{};
   g.n = n;
   g.tc = 1;
@@ -706,20 +707,31 @@ bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp) {
   auto take = [&](int r) {
     while (m % r == 0 && g.nst < kGenMaxStages) { g.radix[g.nst++] = r; m /= r; }
   };
-  take(4);
-  take(2);
-  take(3);
-  take(5);
+  for (int i = 0; i < 4; ++i) take(kOrder[order][i]);
   if (m != 1) return false;
-  for (int t = 64; t <= maxthr; t += 64) {
+  auto fits = [&](int t) {
     bool ok = (size_t)t * E >= (size_t)n;
     for (int s = 0; s < g.nst && ok; ++s) {
       const int r = g.radix[s];
       ok = (n / r + t - 1) / t <= E / r;
     }
-    if (ok) { g.nthr = t; *gp = g; return true; }
+    return ok;
+  };
+  if (nthr_req > 0) {
+    if (nthr_req % 64 != 0 || nthr_req > maxthr || !fits(nthr_req)) return false;
+    g.nthr = nthr_req;
+    *gp = g;
+    return true;
   }
+  for (int t = 64; t <= maxthr; t += 64)
+    if (fits(t)) { g.nthr = t; *gp = g; return true; }
   return false;
+}
+
+// A pass's plan with its run-time choices, or the built-in one when they do not fit.
+static bool tuned_gen_plan(int n, int E, int maxthr, const PassTune& t, GenPlan* gp) {
+  if ((t.nthr > 0 || t.order > 0) && make_gen_plan(n, E, maxthr, gp, t.order, t.nthr)) return true;
+  return make_gen_plan(n, E, maxthr, gp);
 }
 
 bool gen_length_ok(int n) {
@@ -731,14 +743,54 @@ bool gen_length_ok(int n) {
 // Column passes: as many adjacent columns per workgroup as the thread limit and
 // the LDS (here up to 144 KiB, one workgroup per CU at most) allow, at most 8.
 template <typename R>
-static bool make_col_plan(int n, int S, GenPlan* gp) {
-  if (!make_gen_plan(n, gen_e<R>(), gen_maxthr<R>(), gp)) return false;
+static bool col_tc_fits(int n, int S, int nthr, int tc) {
+  return tc >= 1 && tc <= 8 && tc * nthr <= gen_maxthr<R>() && (size_t)tc * n * sizeof(cpx<R>) <= (size_t)144 * 1024 &&
+         tc <= S;
+}
+
+template <typename R>
+static bool make_col_plan(int n, int S, GenPlan* gp, const PassTune& t = PassTune{}) {
+  if (!tuned_gen_plan(n, gen_e<R>(), gen_maxthr<R>(), t, gp)) return false;
+  if (t.tc > 0 && col_tc_fits<R>(n, S, gp->nthr, t.tc)) {
+    gp->tc = t.tc;
+    return true;
+  }
   int tc = 1;
-  while (tc < 8 && (tc * 2) * gp->nthr <= gen_maxthr<R>() &&
-         (size_t)(tc * 2) * n * sizeof(cpx<R>) <= (size_t)144 * 1024 && tc * 2 <= S)
-    tc *= 2;
+  while (tc < 8 && col_tc_fits<R>(n, S, gp->nthr, tc * 2)) tc *= 2;
   gp->tc = tc;
   return true;
+}
+
+int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, PassTune* out, int max) {
+  int cnt = 0;
+  auto push = [&](const PassTune& t) {
+    if (cnt < max) out[cnt++] = t;
+  };
+  if (is_pow2_len(n)) {   // compile-time tiles; only the symbol pass's node groups vary
+    if (kind == kTuneCols && mode == 1)
+      for (int ng = 1; ng <= K && ng <= kMaxNodes; ng *= 2) push(PassTune{0, 0, 0, ng});
+    return cnt;
+  }
+  const int E = kind == kTuneRows ? kGenRowE : (real_kind == 0 ? gen_e<double>() : gen_e<float>());
+  const int maxthr = kind == kTuneRows ? 512 : (real_kind == 0 ? gen_maxthr<double>() : gen_maxthr<float>());
+  for (int order = 0; order < kGenOrders; ++order) {
+    GenPlan g;
+    if (!make_gen_plan(n, E, maxthr, &g, order)) continue;
+    // the smallest thread count that fits, and up to three larger ones
+    for (int t = g.nthr, k = 0; t <= maxthr && k < 4; t += 64, ++k) {
+      GenPlan h;
+      if (!make_gen_plan(n, E, maxthr, &h, order, t)) continue;
+      if (kind != kTuneCols) {
+        push(PassTune{t, 0, order, 0});
+        continue;
+      }
+      for (int tc = 1; tc <= 8; tc *= 2) {
+        const bool ok = real_kind == 0 ? col_tc_fits<double>(n, S, t, tc) : col_tc_fits<float>(n, S, t, tc);
+        if (ok) push(PassTune{t, tc, order, 0});
+      }
+    }
+  }
+  return cnt;
 }
 
 template <typename K>
@@ -806,10 +858,10 @@ static hipError_t combine_gen(const GenPlan& gp, const CombineArgs& a, hipStream
 
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
                            size_t in_rs, size_t out_rs, int nrhs, const void* tw, const int* skip,
-                           hipStream_t st) {
+                           const PassTune& tune, hipStream_t st) {
   if (!is_pow2_len(n)) {
     GenPlan gp;
-    if (!make_gen_plan(n, kGenRowE, 512, &gp)) return hipErrorInvalidValue;
+    if (!tuned_gen_plan(n, kGenRowE, 512, tune, &gp)) return hipErrorInvalidValue;
     if (real_kind == 0) {
       if (in_kind != 0) return hipErrorInvalidValue;
       return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
@@ -838,8 +890,11 @@ struct ColsL {
       } else {
         const int TC = a.mode == 1 ? C1::TC : C0::TC;
         const int tiles = (a.S + TC - 1) / TC;
-        // symbol pass: node groups so that at least ~512 workgroups run (small grids)
-        const int ng = a.mode == 1 ? std::max(1, std::min(a.K, (512 + tiles - 1) / tiles)) : 1;
+        // symbol pass: node groups so that at least ~512 workgroups run (small grids),
+        // or the tuned count
+        const int ng = a.mode != 1 ? 1
+                       : a.tune.ng > 0 ? std::min(a.K, a.tune.ng)
+                                       : std::max(1, std::min(a.K, (512 + tiles - 1) / tiles));
         dim3 grid(tiles, a.mode == 1 ? ng : a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
         const cpx<R>* in = (const cpx<R>*)a.in;
         cpx<R>* out = (cpx<R>*)a.out;
@@ -865,8 +920,9 @@ struct ColsL {
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st) {
   if (!is_pow2_len(a.n)) {
     GenPlan gp;
-    if (a.real_kind == 0) return make_col_plan<double>(a.n, a.S, &gp) ? cols_gen<double>(gp, a, st) : hipErrorInvalidValue;
-    return make_col_plan<float>(a.n, a.S, &gp) ? cols_gen<float>(gp, a, st) : hipErrorInvalidValue;
+    if (a.real_kind == 0)
+      return make_col_plan<double>(a.n, a.S, &gp, a.tune) ? cols_gen<double>(gp, a, st) : hipErrorInvalidValue;
+    return make_col_plan<float>(a.n, a.S, &gp, a.tune) ? cols_gen<float>(gp, a, st) : hipErrorInvalidValue;
   }
   if (a.real_kind == 0) return dispatch_n<ColsL<double>::F>(a.n, a, st);
   return dispatch_n<ColsL<float>::F>(a.n, a, st);
@@ -906,8 +962,8 @@ struct CombineL {
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
   if (!is_pow2_len(a.n)) {
     GenPlan gp;
-    if (a.real_kind == 0 ? !make_gen_plan(a.n, gen_e<double>(), gen_maxthr<double>(), &gp)
-                         : !make_gen_plan(a.n, gen_e<float>(), gen_maxthr<float>(), &gp))
+    if (a.real_kind == 0 ? !tuned_gen_plan(a.n, gen_e<double>(), gen_maxthr<double>(), a.tune, &gp)
+                         : !tuned_gen_plan(a.n, gen_e<float>(), gen_maxthr<float>(), a.tune, &gp))
       return hipErrorInvalidValue;
     if (a.real_kind == 0) {
       if (a.out_kind != 0) return hipErrorInvalidValue;

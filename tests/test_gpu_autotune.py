@@ -1,0 +1,98 @@
+"""The transform-pass autotuner (hp_plan_autotune): the choices it makes keep the apply's
+results (bitwise, unless a radix schedule changed, then to rounding) and its parity with
+the oracle; the tuning cache carries them to a new plan of the same grid."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2409_16172_amd import inputs
+from tests.util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2409_16172_amd import binding
+    binding.load_library()
+    return binding
+
+
+def _problem(shape, seed):
+    n = min(shape)
+    c = inputs.gaussian_random_field(shape, max(2.0, n / 10), seed, lo=0.8, hi=1.3)
+    width = max(2, n // 8)
+    c = inputs.blend_to_background(c, width, 1.0, taper=max(2, min(8, n // 8)))
+    zeta = inputs.frame_layer(shape, width, 0.133)
+    omega = 2 * np.pi * n / 10
+    return c, np.full(shape, 0.05 * omega), zeta, omega
+
+
+@pytest.mark.parametrize("shape,precision", [((240, 360), "fp64"), ((180, 120), "mixed"), ((256, 256), "fp64"),
+                                             ((24, 20, 30), "fp64")])
+def test_autotune_keeps_results(orc, hp, dev, shape, precision, tmp_path, monkeypatch):
+    print(f"[case] autotune shape={shape} {precision}", flush=True)
+    monkeypatch.setenv("HP_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    c, a, zeta, omega = _problem(shape, 3 + sum(shape))
+    kw = dict(m_real=6, m_layer=3, a_floor=0.05 * omega, precision=precision)
+    plan = hp.Plan(shape, omega, c, a, zeta, **kw)
+    assert plan.info()["tune"] == [(0, 0, 0, 0)] * 5
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    rng = np.random.default_rng(5)
+    v_np = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    v = torch.from_numpy(v_np).to(dev).to(dt)
+    u0 = plan.apply(v).clone()
+    before, after = plan.autotune()
+    tune = plan.info()["tune"]
+    print(f"    apply {before * 1e3:.1f} -> {after * 1e3:.1f} us, choices {tune}", flush=True)
+    assert after <= before * 1.1
+    u1 = plan.apply(v)
+    if all(t[2] == 0 for t in tune):
+        assert torch.equal(u0, u1)
+    else:
+        assert rel(u1.cpu().numpy(), u0.cpu().numpy()) < (1e-13 if precision == "fp64" else 1e-6)
+    ref = orc.Problem(shape, omega, c, a, zeta, m_real=6, m_layer=3, a_floor=0.05 * omega).apply(v_np)
+    assert rel(u1.cpu().numpy(), ref) < (1e-12 if precision == "fp64" else 1e-5)
+    # a new plan of the same grid, precision and K reads the choices from the cache
+    again = hp.Plan(shape, omega, c, a, zeta, **kw)
+    assert again.info()["tune"] == tune
+    assert torch.equal(again.apply(v), u1)
+    assert os.path.getsize(tmp_path / "tune.txt") > 0
+
+
+def test_autotuned_plan_solves(orc, hp, dev, tmp_path, monkeypatch):
+    print("[case] autotune solve 240x180", flush=True)
+    monkeypatch.setenv("HP_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    shape = (240, 180)
+    c, a, zeta, omega = _problem(shape, 9)
+    plan = hp.Plan(shape, omega, c, a, zeta, m_real=6, m_layer=3, a_floor=0.05 * omega)
+    plan.autotune()
+    f = inputs.gaussian_source(shape, 2.0, (0.05, 0.1))[None].astype(np.complex128)
+    x, info = plan.solve(torch.from_numpy(f).to(dev), rtol=1e-8)
+    ref = orc.Problem(shape, omega, c, a, zeta, m_real=6, m_layer=3, a_floor=0.05 * omega)
+    r = np.linalg.norm(f[0] - ref.matvec(x.cpu().numpy()[0])) / np.linalg.norm(f[0])
+    assert info[0].status == 0 and r <= 1.5e-8
+
+
+def test_corrupt_cache_lines_fall_back(hp, dev, tmp_path, monkeypatch):
+    # choices that do not fit the kernels (from another build, or edited by hand) are
+    # ignored by the launchers, which then use the built-in ones
+    path = tmp_path / "tune.txt"
+    shape = (240, 360)
+    c, a, zeta, omega = _problem(shape, 4)
+    plan0 = hp.Plan(shape, omega, c, a, zeta, m_real=6, m_layer=3, a_floor=0.05 * omega)
+    K = plan0.info()["K"]
+    lines = [f"hp-tune 2 240 360 1 0 {K} {s} 4160 64 9 -3\n" for s in range(5)]
+    path.write_text("".join(lines) + "garbage line\n")
+    monkeypatch.setenv("HP_TUNE_CACHE", str(path))
+    plan = hp.Plan(shape, omega, c, a, zeta, m_real=6, m_layer=3, a_floor=0.05 * omega)
+    v = torch.from_numpy(np.random.default_rng(2).standard_normal(shape) + 0j).to(dev)
+    assert torch.equal(plan.apply(v), plan0.apply(v))
