@@ -288,9 +288,10 @@ hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps
 /* Autotuner of the transform passes: for each pass in turn, times the plan's apply
  * (one right-hand side) under every valid run-time choice — threads per line, lines
  * per workgroup and radix schedule of the mixed-radix passes (N = 2^a 3^b 5^c),
- * node groups per column tile of the power-of-two symbol pass — and keeps the
- * fastest (by at least 2 %); the plan then uses it for every apply, matvec-free
- * solve step and session.  Only the radix schedule changes results (rounding).
+ * node groups per column tile of the power-of-two symbol pass, node splits of the
+ * power-of-two combine (lines of at most 1024 points) — and keeps the fastest (by
+ * at least 2 %); the plan then uses it for every apply, solve step and session.
+ * Only the radix schedule and the node splits change results (rounding).
  * If the environment variable HP_TUNE_CACHE names a file the choices are appended
  * to it, and hp_plan_create reads it for plans of the same grid, precision and K.
  * before_ms / after_ms (may be NULL): the summed per-pass apply time before and

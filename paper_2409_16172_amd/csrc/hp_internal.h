@@ -80,8 +80,9 @@ inline bool is_pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // Run-time choices of a transform pass (0 = the built-in choice): threads per line,
 // lines per workgroup (column passes) and radix schedule of the mixed-radix passes,
-// node groups per column tile of the power-of-two symbol pass.  None of them changes
-// the arithmetic except the radix schedule (rounding only).
+// node groups per column tile of the power-of-two symbol pass, node splits (1 or 4)
+// of the power-of-two pass C.  Only the radix schedule and the node splits change
+// results (rounding: the order of the node sum).
 struct PassTune {
   int nthr = 0, tc = 0, order = 0, ng = 0;
 };

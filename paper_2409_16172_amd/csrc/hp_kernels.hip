@@ -303,23 +303,37 @@ __device__ __forceinline__ R interp_weight(int ab, R tt, R uu, int n, int ord, c
   return (A == n ? (R)1 - tt : (R)0) + (B == n ? tt : (R)0);
 }
 
-template <typename R, typename TO, int N, bool ACC, int IM>
-__global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
+// NS > 1 (lines of at most one wavefront, few rows): NS wavefronts share the
+// workgroup's rows, wavefront s taking every NS-th node the rows use, and their
+// partial sums meet in LDS at the end; the node loop is NS times shorter and the
+// chip holds NS times more wavefronts.
+template <typename R, int N>
+constexpr bool combine_splits_fit() {
+  return CombCfg<R, N>::T <= 64 && N >= 128;
+}
+constexpr int kCombineSplits = 4;
+
+template <typename R, typename TO, int N, bool ACC, int IM, int NS = 1>
+__global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
     const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
     size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip, int ord, const double* __restrict__ lag, const double* __restrict__ posa, int Ma) {
   using C = CombCfg<R, N>;
+  static_assert(NS == 1 || combine_splits_fit<R, N>(), "node splits need transforms within one wavefront");
   constexpr bool LAG = IM == kInterpLagrange;
-  __shared__ cpx<R> lds[C::LDS];
+  constexpr int XCH = NS * C::LDS, RED = (NS - 1) * C::G * N;
+  __shared__ cpx<R> lds[XCH > RED ? XCH : RED];
   __shared__ double slag[LAG ? kLagTable : 1];
   const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
   if constexpr (LAG) {
-    for (int i = threadIdx.x; i < kLagTable; i += C::THREADS) slag[i] = lag[i];
+    for (int i = threadIdx.x; i < kLagTable; i += C::THREADS * NS) slag[i] = lag[i];
     __syncthreads();
   }
-  const int g = threadIdx.x / C::T, j = threadIdx.x % C::T;
+  const int sp = NS > 1 ? (int)threadIdx.x / C::THREADS : 0;
+  const int tl = NS > 1 ? (int)threadIdx.x % C::THREADS : (int)threadIdx.x;
+  const int g = tl / C::T, j = tl % C::T;
   const int row = blockIdx.x * C::G + g;
   const bool act = row < rows;
   const size_t rbase = (size_t)row * N;
@@ -341,7 +355,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
   const uint64_t mask = grpmask[blockIdx.x];
   const uint64_t rmask = act ? rowmask[row] : 0ull;
   const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
-  cpx<R>* lg = lds + g * lds_elems<R>(N);
+  cpx<R>* lg = lds + (sp * C::G + g) * lds_elems<R>(N);
   // Nodes no point of this group uses are skipped; rows that do not use a node
   // read zeros (pass B did not write them).  The next used node's row is loaded
   // while the current one is transformed.
@@ -349,8 +363,14 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
     while (n < K && ((mask >> n) & 1ull) == 0) ++n;
     return n;
   };
+  // the node after the next NS - 1 used ones (this split's next node)
+  auto split_next = [&](int n) {
+    for (int q = 0; q < NS && n < K; ++q) n = next_node(n + 1);
+    return n;
+  };
   cpx<R> nx[C::E];
   int n = next_node(0);
+  for (int q = 0; q < sp && n < K; ++q) n = next_node(n + 1);
   if (!HP_PREFETCH_C && n < K) {
     // loaded at the top of the loop instead
   } else if (n < K) {
@@ -360,7 +380,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
   }
   for (; n < K;) {
     cpx<R> x[C::E];
-    const int n2 = next_node(n + 1);
+    const int n2 = NS > 1 ? split_next(n) : next_node(n + 1);
     if (!HP_PREFETCH_C) {
       const bool ld = ((rmask >> n) & 1ull) != 0;
 #pragma unroll
@@ -382,6 +402,23 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS)) void k_rows_combine(
       acc[s].im += w * x[s].im;
     }
     n = n2;
+  }
+  if constexpr (NS > 1) {   // partial sums of the splits, added by split 0 in a fixed order
+    __syncthreads();        // every split is done with its exchange area
+    if (sp > 0) {
+#pragma unroll
+      for (int s = 0; s < C::E; ++s) lds[((sp - 1) * C::G + g) * N + j + C::T * s] = acc[s];
+    }
+    __syncthreads();
+    if (sp > 0) return;
+    for (int q = 1; q < NS; ++q) {
+#pragma unroll
+      for (int s = 0; s < C::E; ++s) {
+        const cpx<R> o = lds[((q - 1) * C::G + g) * N + j + C::T * s];
+        acc[s].re += o.re;
+        acc[s].im += o.im;
+      }
+    }
   }
   if (act) {
     cpx<TO>* dst = out + (size_t)rhs * out_rs + rbase;
@@ -761,14 +798,21 @@ static bool make_col_plan(int n, int S, GenPlan* gp, const PassTune& t = PassTun
   return true;
 }
 
+bool combine_splits_ok(int real_kind, int n);   // pass C of this length can split its nodes
+
 int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, PassTune* out, int max) {
   int cnt = 0;
   auto push = [&](const PassTune& t) {
     if (cnt < max) out[cnt++] = t;
   };
-  if (is_pow2_len(n)) {   // compile-time tiles; only the symbol pass's node groups vary
+  if (is_pow2_len(n)) {   // compile-time tiles; the node groups of the symbol pass and the
+                          // node splits of pass C vary
     if (kind == kTuneCols && mode == 1)
       for (int ng = 1; ng <= K && ng <= kMaxNodes; ng *= 2) push(PassTune{0, 0, 0, ng});
+    if (kind == kTuneCombine && combine_splits_ok(real_kind, n)) {
+      push(PassTune{0, 0, 0, 1});
+      push(PassTune{0, 0, 0, kCombineSplits});
+    }
     return cnt;
   }
   const int E = kind == kTuneRows ? kGenRowE : (real_kind == 0 ? gen_e<double>() : gen_e<float>());
@@ -928,6 +972,31 @@ hipError_t launch_cols(const ColsArgs& a, hipStream_t st) {
   return dispatch_n<ColsL<float>::F>(a.n, a, st);
 }
 
+template <typename R, typename TO, int N, bool ACC, int NS>
+static void combine_launch(const CombineArgs& a, dim3 grid, hipStream_t st) {
+  using C = CombCfg<R, N>;
+  const dim3 block(C::THREADS * NS);
+  switch (interp_mode(a)) {
+    case kInterpLagrange:
+      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLagrange, NS>), grid, block, 0, st,
+                         (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                         a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa,
+                         a.Ma);
+      break;
+    case kInterpBilinear:
+      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpBilinear, NS>), grid, block, 0, st,
+                         (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                         a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa,
+                         a.Ma);
+      break;
+    default:
+      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLinear, NS>), grid, block, 0, st,
+                         (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
+                         a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa,
+                         a.Ma);
+  }
+}
+
 template <typename R, typename TO, bool ACC>
 struct CombineL {
   template <int N>
@@ -935,29 +1004,32 @@ struct CombineL {
     static hipError_t run(const CombineArgs& a, hipStream_t st) {
       using C = CombCfg<R, N>;
       dim3 grid((a.rows + C::G - 1) / C::G, a.nrhs);
-      switch (interp_mode(a)) {
-        case kInterpLagrange:
-          hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLagrange>), grid, dim3(C::THREADS), 0, st,
-                             (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
-                             a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag,
-                             a.posa, a.Ma);
-          break;
-        case kInterpBilinear:
-          hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpBilinear>), grid, dim3(C::THREADS), 0, st,
-                             (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
-                             a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag,
-                             a.posa, a.Ma);
-          break;
-        default:
-          hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLinear>), grid, dim3(C::THREADS), 0, st,
-                             (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
-                             a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag,
-                             a.posa, a.Ma);
+      if constexpr (combine_splits_fit<R, N>()) {
+        // node splits when the row groups alone would leave most of the chip idle, or
+        // as tuned (the tuner's node-group field: 1 or kCombineSplits).  The choice
+        // depends on the grid only, so that a batch sums in the order a single field does.
+        const int groups = (int)grid.x;
+        const int ns = a.tune.ng > 0 ? a.tune.ng : (groups < 512 ? kCombineSplits : 1);
+        if (ns == kCombineSplits) {
+          combine_launch<R, TO, N, ACC, kCombineSplits>(a, grid, st);
+          return hipGetLastError();
+        }
       }
+      combine_launch<R, TO, N, ACC, 1>(a, grid, st);
       return hipGetLastError();
     }
   };
 };
+
+bool combine_splits_ok(int real_kind, int n) {
+  switch (n) {
+    case 128: return real_kind == 0 ? combine_splits_fit<double, 128>() : combine_splits_fit<float, 128>();
+    case 256: return real_kind == 0 ? combine_splits_fit<double, 256>() : combine_splits_fit<float, 256>();
+    case 512: return real_kind == 0 ? combine_splits_fit<double, 512>() : combine_splits_fit<float, 512>();
+    case 1024: return real_kind == 0 ? combine_splits_fit<double, 1024>() : combine_splits_fit<float, 1024>();
+    default: return false;
+  }
+}
 
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
   if (!is_pow2_len(a.n)) {

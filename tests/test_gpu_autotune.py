@@ -1,6 +1,7 @@
 """The transform-pass autotuner (hp_plan_autotune): the choices it makes keep the apply's
-results (bitwise, unless a radix schedule changed, then to rounding) and its parity with
-the oracle; the tuning cache carries them to a new plan of the same grid."""
+results (bitwise, unless a radix schedule or the node splits of pass C changed, then to
+rounding) and its parity with the oracle; the tuning cache carries them to a new plan of
+the same grid."""
 import os
 
 import numpy as np
@@ -55,7 +56,9 @@ def test_autotune_keeps_results(orc, hp, dev, shape, precision, tmp_path, monkey
     print(f"    apply {before * 1e3:.1f} -> {after * 1e3:.1f} us, choices {tune}", flush=True)
     assert after <= before * 1.1
     u1 = plan.apply(v)
-    if all(t[2] == 0 for t in tune):
+    # the radix schedule (mixed radix) and the node splits of pass C (power of two)
+    # reorder sums; every other choice leaves the results bitwise
+    if all(t[2] == 0 for t in tune) and tune[4][3] == 0:
         assert torch.equal(u0, u1)
     else:
         assert rel(u1.cpu().numpy(), u0.cpu().numpy()) < (1e-13 if precision == "fp64" else 1e-6)
