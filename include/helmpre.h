@@ -196,7 +196,11 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
  * info: host array of nrhs entries.  Blocks until every right-hand side has
  * converged or max_cycles is reached.  Krylov storage is allocated on first
  * use and kept by the plan.  Returns HP_E_NOT_CONVERGED if any right-hand side
- * stopped above rtol (x and info are filled in any case). */
+ * stopped above rtol (x and info are filled in any case).
+ * With the environment variable HP_STEP_GRAPHS=1, grids of fewer than 2^18 points
+ * (times nrhs) run each Arnoldi step as a HIP graph captured once per step index
+ * and solver configuration (also in hp_solver sessions); results are bitwise those
+ * of the direct launches. */
 hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_opts* opts,
                    hp_solve_info* info, void* stream);
 

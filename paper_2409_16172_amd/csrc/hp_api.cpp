@@ -45,6 +45,14 @@ struct hp_plan_s;
 namespace {
 void load_tune(hp_plan_s& P);
 void save_tune(const hp_plan_s& P);
+
+// Arnoldi steps of small grids run as captured HIP graphs when HP_STEP_GRAPHS=1 (off
+// by default: on this runtime a graph launch of a step costs more than its seven
+// direct launches, 256^2 FP64 solve 5.5 -> 6.1 ms).
+bool step_graphs_enabled() {
+  const char* v = std::getenv("HP_STEP_GRAPHS");
+  return v && v[0] == '1';
+}
 }  // namespace
 
 struct hp_plan_s {
@@ -65,6 +73,7 @@ struct hp_plan_s {
   int order = 1;   // real-axis interpolation degree in effect
   DevBuf lagtab;   // Lagrange table of CombineArgs::lag (order >= 2)
   hp::PassTune tune[5];   // run-time choices of passes A, A', B, M, C (hp_plan_autotune)
+  int tune_gen = 0;        // bumped when they change (captured step graphs become stale)
   int Ma = 0;      // damping nodes of the bivariate (c, a) scheme (0: univariate)
   double anode[64] = {0};
   DevBuf posa;     // per point: position among the damping nodes (Ma >= 2)
@@ -823,6 +832,19 @@ struct SolverWs {
   hipEvent_t step_ev[kLag + 1] = {};
   hipEvent_t cyc_ev = nullptr;
   int restart = 0, nrhs = 0;
+  // Arnoldi steps captured as HIP graphs (small grids), one per step index j, for the
+  // session configuration `graph_key` (plan, side, right-hand sides, restart, tuning
+  // generation); captured on a private stream, launched on the session's stream
+  hipGraphExec_t step_graph[hp::kMaxRestart] = {};
+  hipStream_t cap_st = nullptr;
+  uint64_t graph_key = 0;
+  void drop_graphs() {
+    for (hipGraphExec_t& g : step_graph) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+    graph_key = 0;
+  }
 
   static size_t bytes(size_t np, size_t fsize, int restart, int nrhs) {
     const size_t n = (size_t)nrhs;
@@ -833,6 +855,7 @@ struct SolverWs {
     if (restart >= r && nrhs >= n) return hipSuccess;
     r = std::max(r, restart);
     n = std::max(n, nrhs);
+    drop_graphs();   // the captured steps point into the buffers about to be replaced
     hipError_t e;
     if ((e = V.alloc((size_t)n * (r + 1) * np * 16)) != hipSuccess) return e;
     if ((e = z.alloc((size_t)n * np * fsize)) != hipSuccess) return e;
@@ -852,6 +875,9 @@ struct SolverWs {
     return hipSuccess;
   }
   void release() {
+    drop_graphs();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    cap_st = nullptr;
     for (DevBuf* b : {&V, &z, &tvec, &state, &part, &flags}) b->release();
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
@@ -894,6 +920,9 @@ struct Session {
   // left side: f is the preconditioned right-hand side itself (the system Q P x = f)
   bool rhs_prec = false;
   bool inner_failed = false;   // an inner solve of an inverse operator stopped above its tolerance
+  // Arnoldi steps as HIP graphs: for grids where a step is too short to hide the
+  // launches (the same threshold as `throttle`), when HP_STEP_GRAPHS=1
+  bool use_graphs = false;
   hp_status status = HP_OK;
 
   hipError_t start(const cpx<double>* f_, cpx<double>* x_, hipStream_t s) {
@@ -954,28 +983,80 @@ struct Session {
     return hipSuccess;
   }
 
-  hipError_t enqueue_step() {
+  // The kernels of Arnoldi step j on stream s (a fixed sequence for given j).
+  hipError_t step_kernels(hipStream_t s) {
     const size_t np = P->npts;
     const int mixed = P->prec == HP_MIXED;
     cpx<double>* vj = K.V + (size_t)j * np;
     cpx<double>* vj1 = K.V + (size_t)(j + 1) * np;
     hipError_t e;
-    if (o.side == kLeftInverse || o.side == kNoneInverse) {   // w = (Q P_N)^{-1} u_j or P_N^{-1} u_j
-      if ((e = inner_solve(vj, vj1)) != hipSuccess) return e;
-    } else if (o.side == HP_NONE) {          // w = P_N u_j (plain GMRES, FP64)
-      if ((e = run_stencil(P, 0, vj, vrs, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess) return e;
+    if (o.side == HP_NONE) {          // w = P_N u_j (plain GMRES, FP64)
+      if ((e = run_stencil(P, 0, vj, vrs, vj1, vrs, nullptr, nrhs, K.skip_step, s)) != hipSuccess) return e;
     } else if (o.side == HP_LEFT) {   // w = Q P_N u_j (P_N in FP64)
       cpx<double>* pv = (cpx<double>*)W->tvec.p;
-      if ((e = run_stencil(P, 0, vj, vrs, pv, np, nullptr, nrhs, K.skip_step, st)) != hipSuccess) return e;
-      if ((e = run_apply(P, pv, 0, np, vj1, 0, vrs, false, nrhs, K.skip_step, st)) != hipSuccess) return e;
+      if ((e = run_stencil(P, 0, vj, vrs, pv, np, nullptr, nrhs, K.skip_step, s)) != hipSuccess) return e;
+      if ((e = run_apply(P, pv, 0, np, vj1, 0, vrs, false, nrhs, K.skip_step, s)) != hipSuccess) return e;
     } else {                          // w = P_N Q u_j
-      if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, st)) != hipSuccess)
+      if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, s)) != hipSuccess)
         return e;
-      if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, st)) != hipSuccess)
+      if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, s)) != hipSuccess)
         return e;
     }
-    if ((e = hp::launch_arnoldi_dots(K, j, st)) != hipSuccess) return e;
-    if ((e = hp::launch_arnoldi_update(K, j, st)) != hipSuccess) return e;
+    if ((e = hp::launch_arnoldi_dots(K, j, s)) != hipSuccess) return e;
+    return hp::launch_arnoldi_update(K, j, s);
+  }
+
+  // Step j as a graph: captured once per workspace configuration on the private
+  // stream (nothing runs during capture), then launched on the session's stream.
+  hipError_t launch_step_graph() {
+    hipError_t e;
+    const uint64_t key = graph_key_of();
+    if (W->graph_key != key) {
+      W->drop_graphs();
+      W->graph_key = key;
+    }
+    hipGraphExec_t& ge = W->step_graph[j];
+    if (!ge) {
+      if (!W->cap_st && (e = hipStreamCreateWithFlags(&W->cap_st, hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipStreamBeginCapture(W->cap_st, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+      hipError_t ek = step_kernels(W->cap_st);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(W->cap_st, &g);
+      if (ek != hipSuccess) e = ek;
+      if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        ge = nullptr;
+        return e;
+      }
+    }
+    return hipGraphLaunch(ge, st);
+  }
+
+  uint64_t graph_key_of() const {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    mix((uint64_t)(uintptr_t)P);
+    mix((uint64_t)o.side);
+    mix((uint64_t)nrhs);
+    mix((uint64_t)W->restart);
+    mix((uint64_t)o.restart);
+    mix((uint64_t)P->tune_gen);
+    return h == 0 ? 1 : h;
+  }
+
+  hipError_t enqueue_step() {
+    hipError_t e;
+    if (o.side == kLeftInverse || o.side == kNoneInverse) {   // w = (Q P_N)^{-1} u_j or P_N^{-1} u_j
+      const size_t np = P->npts;
+      if ((e = inner_solve(K.V + (size_t)j * np, K.V + (size_t)(j + 1) * np)) != hipSuccess) return e;
+      if ((e = hp::launch_arnoldi_dots(K, j, st)) != hipSuccess) return e;
+      if ((e = hp::launch_arnoldi_update(K, j, st)) != hipSuccess) return e;
+    } else if (use_graphs) {
+      if ((e = launch_step_graph()) != hipSuccess) return e;
+    } else if ((e = step_kernels(st)) != hipSuccess) {
+      return e;
+    }
     if ((e = hipEventRecord(W->step_ev[j % (SolverWs::kLag + 1)], st)) != hipSuccess) return e;
     ++j;
     return hipSuccess;
@@ -1135,8 +1216,10 @@ static hp_status solve_batch(hp_plan_s* P, const cpx<double>* f, cpx<double>* x,
   S.W = P->solver_ws_ptr;
   S.nrhs = nrhs;
   S.o = o;
-  // small problems: a step is too short to hide a host round trip, enqueue freely
+  // small problems: a step is too short to hide a host round trip, enqueue freely,
+  // and launch each step as one graph
   S.throttle = P->npts * (size_t)nrhs >= ((size_t)1 << 18);
+  S.use_graphs = !S.throttle && step_graphs_enabled();
   HP_TRY(S.start(f, x, st));
   HP_TRY(S.advance(1 << 30, true));
   return S.collect(info);
@@ -1250,6 +1333,7 @@ hp_status hp_solver_create(hp_solver* out, hp_plan p, int nrhs, const hp_solve_o
   s->sess.nrhs = nrhs;
   s->sess.o = *opts;
   s->sess.throttle = true;
+  s->sess.use_graphs = p->npts * (size_t)nrhs < ((size_t)1 << 18) && step_graphs_enabled();
   *out = s;
   return HP_OK;
 }
@@ -1345,6 +1429,7 @@ hp_status hp_plan_autotune(hp_plan p, double* before_ms, double* after_ms, void*
   HP_TRY(hipStreamSynchronize(st));
   if (before_ms) *before_ms = base[0] + base[1] + base[2] + base[3] + base[4];
   if (after_ms) *after_ms = fin[0] + fin[1] + fin[2] + fin[3] + fin[4];
+  ++p->tune_gen;
   save_tune(*p);
   return HP_OK;
 }
