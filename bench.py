@@ -83,18 +83,20 @@ def cpu_baseline(w, gpu_iters, gpu_cycles, steps=6):
                       f"to {gpu_iters} steps and {gpu_cycles} cycles = {t_solve:.1f} s"}
 
 
-def serving_run(dev, n_requests=24, rate=40.0):
+SERVING_GRIDS = ((256, 256), (512, 512), (1024, 1024), (2048, 2048), (128, 128, 128))
+
+
+def serving_run(dev, n_requests=30, rate=25.0):
     """Continuous-batching stream: Poisson arrivals of mixed-precision solves on
-    256^2 / 512^2 / 1024^2 random media, 20-150 wavelengths (at most N/4), rtol 1e-8;
-    latency from arrival to solution, including plan set-up."""
+    256^2 / 512^2 / 1024^2 / 2048^2 / 128^3 random media, 20-150 wavelengths (at most
+    N/4), rtol 1e-8; latency from arrival to solution, including plan set-up."""
     from paper_2409_16172_amd import serve
-    reqs = serve.stream_requests(n_requests, rate_per_s=rate, grids=((256, 256), (512, 512), (1024, 1024)),
-                                 precision="mixed")
+    reqs = serve.stream_requests(n_requests, rate_per_s=rate, grids=SERVING_GRIDS, precision="mixed")
     srv = serve.Server(hbm_budget_bytes=200 << 30, max_active=8, steps_per_turn=2)
     done = srv.run(reqs, dev=dev)
     st = serve.latency_stats(done)
-    st.update({"arrival_rate_per_s": rate, "grids": [256, 512, 1024], "precision": "mixed",
-               "peak_workspace_GiB": srv.peak_in_use / 2 ** 30})
+    st.update({"arrival_rate_per_s": rate, "grids": ["x".join(map(str, g)) for g in SERVING_GRIDS],
+               "precision": "mixed", "peak_workspace_GiB": srv.peak_in_use / 2 ** 30})
     return st
 
 
@@ -456,8 +458,8 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 mixed vs FP64 comparison")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-rate", type=float, default=40.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=30)
+    ap.add_argument("--serve-rate", type=float, default=25.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--n3d", type=int, default=256)
     ap.add_argument("--nrhs3d", type=int, default=16)
     ap.add_argument("--ex1-sizes", type=int, nargs="+", default=[180, 360, 720, 1440, 2880])
