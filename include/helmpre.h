@@ -9,8 +9,9 @@
  *   - Grids: d = 2 or 3 dimensions, n[j] points per axis, each a power of two in
  *     [8, 2048] (FP64 plans) or [8, 4096] (mixed plans), or an even product of
  *     2, 3 and 5 in [8, 4800] (such as the N = 180 * 2^k and 2400 of Section 5.1;
- *     these lines are transformed in LDS by mixed-radix stages); side len[j];
- *     spacing h_j = len[j]/n[j]; periodic boundary conditions (Section 5).
+ *     these lines are transformed in LDS by mixed-radix stages), fewer than 2^32
+ *     points in all; side len[j]; spacing h_j = len[j]/n[j]; periodic boundary
+ *     conditions (Section 5).
  *   - Fields: row-major with the last axis contiguous, complex interleaved
  *     (re, im); several right-hand sides are stored one after another
  *     ("batch outermost": [nrhs][n0][n1]([n2])).

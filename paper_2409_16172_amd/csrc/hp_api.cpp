@@ -240,6 +240,10 @@ hp_status check_grid(const hp_grid* g, int prec) {
     if (!ok) return HP_E_SHAPE;
     if (!(g->len[d] > 0) || !std::isfinite(g->len[d])) return HP_E_INVALID;
   }
+  // point indices are 32-bit in the kernels
+  size_t np = 1;
+  for (int d = 0; d < g->dim; ++d) np *= (size_t)g->n[d];
+  if (np >= ((size_t)1 << 32)) return HP_E_SHAPE;
   return HP_OK;
 }
 

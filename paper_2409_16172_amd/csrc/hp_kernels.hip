@@ -1121,17 +1121,21 @@ __global__ __launch_bounds__(256) void k_stencil(const cpx<TI>* __restrict__ u, 
   // periodic neighbours (any length)
   auto nxt = [](int k, int n) { return k + 1 == n ? 0 : k + 1; };
   auto prv = [](int k, int n) { return k == 0 ? n - 1 : k - 1; };
+  // index arithmetic in 32 bits (every grid has fewer than 2^32 points): 64-bit
+  // division is a long software sequence on the GPU
+  const uint32_t i32 = (uint32_t)i;
   if constexpr (DIM == 2) {
-    const int i1 = (int)(i % n1), i0 = (int)(i / n1);
+    const int i1 = (int)(i32 % (uint32_t)n1), i0 = (int)(i32 / (uint32_t)n1);
     const size_t r0 = (size_t)i0 * n1;
     const size_t up = (size_t)nxt(i0, n0) * n1, dn = (size_t)prv(i0, n0) * n1;
     const cpx<R> a = cvt<R>(ur[r0 + nxt(i1, n1)]), b = cvt<R>(ur[r0 + prv(i1, n1)]);
     const cpx<R> c = cvt<R>(ur[up + i1]), d = cvt<R>(ur[dn + i1]);
     lap = {(a.re + b.re) * ih1 + (c.re + d.re) * ih0, (a.im + b.im) * ih1 + (c.im + d.im) * ih0};
   } else {
-    const int i2 = (int)(i % n2);
-    const int i1 = (int)((i / n2) % n1);
-    const int i0 = (int)(i / ((size_t)n1 * n2));
+    const uint32_t q2 = i32 / (uint32_t)n2;
+    const int i2 = (int)(i32 - q2 * (uint32_t)n2);
+    const int i1 = (int)(q2 % (uint32_t)n1);
+    const int i0 = (int)(q2 / (uint32_t)n1);
     const size_t s1 = n2, s0 = (size_t)n1 * n2;
     const size_t b0 = (size_t)i0 * s0, b1 = (size_t)i1 * s1;
     const cpx<R> a = cvt<R>(ur[b0 + b1 + nxt(i2, n2)]), b = cvt<R>(ur[b0 + b1 + prv(i2, n2)]);
