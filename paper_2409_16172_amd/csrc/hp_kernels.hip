@@ -31,6 +31,13 @@ __device__ __forceinline__ cpx<R> cvt(cpx<S> a) {
 #ifndef HP_PREFETCH_C
 #define HP_PREFETCH_C 0
 #endif
+// mixed-radix column and combine passes read their twiddles from a copy in LDS
+// (8-12 % faster at 2400^2-4800^2; pass A keeps them in global memory: the copy would
+// halve its occupancy and costs 2-40 %)
+#ifndef HP_GEN_LDS_TW
+#define HP_GEN_LDS_TW 1
+#endif
+
 template <typename R, int N, int WG = 256>
 struct RowCfg {
   static constexpr int E = elems_per_thread<R>(N);
@@ -578,6 +585,11 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
   const size_t obase = (size_t)blockIdx.y * n * S + (act ? c : 0);
   const cpx<R>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
   for (int p = tl; p < n; p += nthr) buf[(size_t)p * tc] = act ? src[(size_t)p * S] : cpx<R>{0, 0};
+  if (HP_GEN_LDS_TW) {   // the line's twiddles after the tc lines
+    cpx<R>* stw = reinterpret_cast<cpx<R>*>(dyn_lds) + (size_t)n * tc;
+    for (int p = threadIdx.x; p < n; p += nthr * tc) stw[p] = tw[p];
+    tw = stw;
+  }
   __syncthreads();
   if constexpr (MODE == 0) {
     fft_gen<R, DIR, E>(buf, tc, gp, tw, tl);
@@ -669,6 +681,11 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
   }
   const uint64_t rm = rowmask[row];
   const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
+  if (HP_GEN_LDS_TW) {   // the row's twiddles after the line
+    cpx<R>* stw = buf + n;
+    for (int p = tid; p < n; p += nthr) stw[p] = tw[p];
+    tw = stw;
+  }
   for (int nd = 0; nd < K; ++nd) {
     if (((rm >> nd) & 1ull) == 0) continue;
     for (int p = tid; p < n; p += nthr) buf[p] = fr[(size_t)nd * fs + p];
@@ -781,8 +798,8 @@ bool gen_length_ok(int n) {
 // the LDS (here up to 144 KiB, one workgroup per CU at most) allow, at most 8.
 template <typename R>
 static bool col_tc_fits(int n, int S, int nthr, int tc) {
-  return tc >= 1 && tc <= 8 && tc * nthr <= gen_maxthr<R>() && (size_t)tc * n * sizeof(cpx<R>) <= (size_t)144 * 1024 &&
-         tc <= S;
+  return tc >= 1 && tc <= 8 && tc * nthr <= gen_maxthr<R>() &&
+         (size_t)(tc + (HP_GEN_LDS_TW ? 1 : 0)) * n * sizeof(cpx<R>) <= (size_t)144 * 1024 && tc <= S;
 }
 
 template <typename R>
@@ -855,7 +872,7 @@ static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int
 
 template <typename R>
 static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)gp.n * gp.tc * sizeof(cpx<R>);
+  const size_t lds = (size_t)gp.n * (gp.tc + (HP_GEN_LDS_TW ? 1 : 0)) * sizeof(cpx<R>);
   dim3 grid((a.S + gp.tc - 1) / gp.tc, a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
   const cpx<R>* in = (const cpx<R>*)a.in;
   cpx<R>* out = (cpx<R>*)a.out;
@@ -881,7 +898,7 @@ static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st)
 
 template <typename R, typename TO, bool ACC, int IM>
 static hipError_t combine_gen_l(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
+  const size_t lds = (size_t)gp.n * (HP_GEN_LDS_TW ? 2 : 1) * sizeof(cpx<R>);
   allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC, IM>, lds);
   hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC, IM>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
                      (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
