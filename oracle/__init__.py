@@ -37,7 +37,8 @@ class _Problem(C.Structure):
                 ("omega", C.c_double), ("c", C.c_void_p), ("a", C.c_void_p), ("zeta", C.c_void_p),
                 ("c0", C.c_double), ("m_real", C.c_int), ("m_layer", C.c_int), ("symbol", C.c_int),
                 ("a_floor", C.c_double), ("nodes_real", C.c_void_p), ("nodes_zeta", C.c_void_p),
-                ("a_nodes", C.c_void_p), ("interp_order", C.c_int), ("m_damp", C.c_int)]
+                ("a_nodes", C.c_void_p), ("interp_order", C.c_int), ("m_damp", C.c_int),
+                ("layer_tensor", C.c_int)]
 
 
 class _Setup(C.Structure):
@@ -45,7 +46,8 @@ class _Setup(C.Structure):
                 ("cmin", C.c_double), ("cmax", C.c_double), ("zmax", C.c_double),
                 ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
                 ("gre", C.c_double * 64), ("gim", C.c_double * 64), ("order", C.c_int),
-                ("Ma", C.c_int), ("anode", C.c_double * 64), ("amin", C.c_double), ("amax", C.c_double)]
+                ("Ma", C.c_int), ("anode", C.c_double * 64), ("amin", C.c_double), ("amax", C.c_double),
+                ("tensor", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -88,7 +90,7 @@ class Problem:
 
     def __init__(self, shape, omega, c, a=None, zeta=None, length=1.0, c0=1.0, m_real=8,
                  m_layer=3, symbol="continuous", a_floor=0.0, nodes_real=None,
-                 nodes_zeta=None, a_nodes=None, interp_order=1, m_damp=0):
+                 nodes_zeta=None, a_nodes=None, interp_order=1, m_damp=0, layer_tensor=False):
         self.shape = tuple(int(s) for s in shape)
         self.dim = len(self.shape)
         self.c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.shape)
@@ -112,6 +114,7 @@ class Problem:
         p.nodes_real, p.nodes_zeta, p.a_nodes = _addr(self.nodes_real), _addr(self.nodes_zeta), _addr(self.a_nodes)
         p.interp_order = int(interp_order)
         p.m_damp = int(m_damp)
+        p.layer_tensor = int(bool(layer_tensor))
         self._p = p
         self.omega = float(omega)
         self.length = float(length)
@@ -130,7 +133,7 @@ class Problem:
         return {"M": s.M, "Mt": s.Mt, "K": K, "mo": s.mo, "cmin": s.cmin, "cmax": s.cmax,
                 "zmax": s.zmax, "cnode": np.array(s.cnode[:s.M]), "znode": np.array(s.znode[:s.Mt + 1]),
                 "ahat": np.array(s.ahat[:K]), "gamma": np.array(s.gre[:K]) + 1j * np.array(s.gim[:K]),
-                "Ma": s.Ma, "anode": np.array(s.anode[:s.Ma]), "_raw": s}
+                "Ma": s.Ma, "anode": np.array(s.anode[:s.Ma]), "tensor": s.tensor, "_raw": s}
 
     def weights(self, cval, zval):
         """All K node weights at a point with wave speed cval and layer value zval."""

@@ -67,6 +67,9 @@ typedef struct {
     int m_damp;                /* >= 2: bivariate interpolation in (c, a) with m_damp
                                   equidistant damping nodes on [a_min, a_max]; 0/1: a is
                                   treated as a function of c (one damping per real node) */
+    int layer_tensor;          /* 1: with a layer, interpolate on the tensor grid of
+                                  (Re gamma, Im gamma) nodes instead of the two legs of
+                                  Eqn. 405, so that c need not equal c_o in the layer  */
 } or_problem;
 
 /* Derived quantities of the preconditioner (filled by or_setup). */
@@ -81,9 +84,11 @@ typedef struct {
     double ahat[64];       /* symbol damping per node (K)     */
     double gre[64], gim[64]; /* gamma_n per node (K)          */
     int order;             /* real-axis interpolation degree (1, 2 or 3) */
-    int Ma;                /* damping nodes of the bivariate scheme (0: univariate) */
-    double anode[64];      /* a_1..a_Ma; real node (m, r) is node m + M r */
+    int Ma;                /* second-axis nodes of a tensor scheme (0: none) */
+    double anode[64];      /* a_1..a_Ma (bivariate in (c, a)) or the Im gamma nodes
+                              (layer tensor); node (m, r) is node m + M r */
     double amin, amax;
+    int tensor;            /* 1: the second axis is Im gamma (layer tensor) */
 } or_setup_t;
 
 static long npoints(const or_problem* p) {
@@ -385,9 +390,11 @@ void or_point_weights_ca(const or_setup_t* s, double cval, double aval, double* 
     }
 }
 
-/* Weights of all K nodes at point i of the problem (either scheme). */
+/* Weights of all K nodes at point i of the problem (any scheme).  The layer tensor
+ * uses the same tensor-product hats with Im gamma = -c zeta on the second axis. */
 static void point_weights_at(const or_problem* p, const or_setup_t* s, long i, double* w) {
-    if (s->Ma > 0) or_point_weights_ca(s, p->c[i], p->a ? p->a[i] : 0.0, w);
+    if (s->tensor) or_point_weights_ca(s, p->c[i], -p->c[i] * (p->zeta ? p->zeta[i] : 0.0), w);
+    else if (s->Ma > 0) or_point_weights_ca(s, p->c[i], p->a ? p->a[i] : 0.0, w);
     else or_point_weights(s, p->c0, p->c[i], p->zeta ? p->zeta[i] : 0.0, w);
 }
 
@@ -417,6 +424,53 @@ int or_setup(const or_problem* p, or_setup_t* s) {
      * the single node c_o and no layer nodes. */
     int q1 = p->m_real == 1;
     int has_layer = s->zmax > 0.0 && !q1;
+    /* Layer tensor: Re gamma = c on M equidistant nodes over [c_min, c_max] (c_o need
+     * not be one), Im gamma = -c zeta on m_layer + 1 equidistant nodes over
+     * [-max(c zeta), 0], node (m, r) with gamma = c_m + i g_r; the damping per speed
+     * node as in the univariate scheme.  Piecewise linear, not with (c, a). */
+    if (p->layer_tensor && has_layer) {
+        if (p->m_damp >= 2 || s->order != 1 || p->m_layer < 1) return OR_E_INVALID;
+        int rc = real_nodes(p, s, 0);
+        if (rc) return rc;
+        double gmax = 0.0;
+        for (long i = 0; i < np; ++i) {
+            double g = p->c[i] * (p->zeta ? p->zeta[i] : 0.0);
+            if (g > gmax) gmax = g;
+        }
+        int Mi = p->m_layer + 1;
+        for (int r = 0; r < Mi; ++r) s->anode[r] = -gmax + gmax * (double)r / (double)(Mi - 1);
+        s->anode[Mi - 1] = 0.0;
+        s->Ma = Mi;
+        s->Mt = 0;
+        s->tensor = 1;
+        s->K = s->M * Mi;
+        if (s->K > 64) return OR_E_INVALID;
+        double a0 = p->a ? p->a[0] : 0.0, ahat[64];
+        int uniform = 1;
+        if (p->a) for (long i = 1; i < np; ++i) if (p->a[i] != a0) { uniform = 0; break; }
+        for (int m = 0; m < s->M; ++m) ahat[m] = p->a_nodes ? p->a_nodes[m] : a0;
+        if (!p->a_nodes && !uniform) {   /* hat(c)-weighted mean of a over the points */
+            double num[64] = {0}, den[64] = {0}, mean = 0;
+            for (long i = 0; i < np; ++i) {
+                for (int m = 0; m < s->M; ++m) {
+                    double h = hat(s->cnode, s->M, m, p->c[i]);
+                    num[m] += h * p->a[i];
+                    den[m] += h;
+                }
+                mean += p->a[i];
+            }
+            mean /= (double)np;
+            for (int m = 0; m < s->M; ++m) ahat[m] = den[m] > 0 ? num[m] / den[m] : mean;
+        }
+        for (int r = 0; r < Mi; ++r)
+            for (int m = 0; m < s->M; ++m) {
+                int n = m + s->M * r;
+                s->gre[n] = s->cnode[m];
+                s->gim[n] = s->anode[r];
+                s->ahat[n] = ahat[m] < p->a_floor ? p->a_floor : ahat[m];
+            }
+        return OR_OK;
+    }
     int rc = real_nodes(p, s, has_layer);
     if (rc) return rc;
     if (has_layer) {
