@@ -93,7 +93,14 @@ typedef struct {
  *              nodes on [a_min, a_max], node (c_m, a_r) for every pair (K =
  *              M m_damp <= 64), tensor-product hat weights.  Needs no layer
  *              and interp_order <= 1 (else HP_E_INVALID); a uniform a falls
- *              back to the univariate scheme                                   */
+ *              back to the univariate scheme
+ *   layer_tensor  with a layer: replace the two legs of Eqn. 405 by a tensor grid
+ *              of M speed nodes (equidistant on [c_min, c_max]) by m_layer + 1
+ *              nodes of Im gamma = -c zeta (equidistant on [-max c zeta, 0]),
+ *              node gamma = c_m + i g_r (K = M (m_layer + 1) <= 64), tensor-product
+ *              hat weights in (Re gamma, Im gamma): c need not equal c0 inside
+ *              the layer (no HP_E_LAYER).  Needs interp_order <= 1 and no m_damp
+ *              (else HP_E_INVALID); ignored without a layer                     */
 typedef struct {
   int m_real;
   int m_layer;
@@ -106,6 +113,7 @@ typedef struct {
   int max_nrhs;
   int interp_order;
   int m_damp;
+  int layer_tensor;
 } hp_plan_opts;
 
 /* Restarted GMRES(restart) on P_N x = f, starting from the x passed in.
@@ -152,10 +160,12 @@ typedef struct {
   int interp_order;          /* real-axis interpolation degree in effect */
   int m_damp;                /* damping nodes of the bivariate scheme (0: univariate);
                                 real node (c_m, a_r) is node m + M r */
-  double anode[64];          /* damping nodes a_r             */
+  double anode[64];          /* damping nodes a_r (bivariate), or the Im gamma nodes
+                                g_r (layer tensor; node gamma = c_m + i g_r) */
   int tune[5][4];            /* run-time choices of passes A, A', B, M, C: threads per
                                 line, lines per workgroup, radix schedule, node groups
                                 (0 = built-in); see hp_plan_autotune */
+  int layer_tensor;          /* 1: the layer tensor is in use */
 } hp_plan_info;
 
 /* Build a plan: upload and validate the media, place the nodes, and compute in

@@ -41,7 +41,7 @@ class HpPlanOpts(C.Structure):
     _fields_ = [("m_real", C.c_int), ("m_layer", C.c_int), ("nodes_real", C.c_void_p),
                 ("nodes_zeta", C.c_void_p), ("a_nodes", C.c_void_p), ("a_floor", C.c_double),
                 ("symbol", C.c_int), ("precision", C.c_int), ("max_nrhs", C.c_int), ("interp_order", C.c_int),
-                ("m_damp", C.c_int)]
+                ("m_damp", C.c_int), ("layer_tensor", C.c_int)]
 
 
 SIDES = {"right": 0, "left": 1, "none": 2}   # HP_RIGHT, HP_LEFT, HP_NONE
@@ -64,7 +64,8 @@ class HpPlanInfo(C.Structure):
                 ("cnode", C.c_double * 64), ("znode", C.c_double * 65), ("ahat", C.c_double * 64),
                 ("gamma_re", C.c_double * 64), ("gamma_im", C.c_double * 64),
                 ("workspace_bytes", C.c_size_t), ("precision", C.c_int), ("interp_order", C.c_int),
-                ("m_damp", C.c_int), ("anode", C.c_double * 64), ("tune", (C.c_int * 4) * 5)]
+                ("m_damp", C.c_int), ("anode", C.c_double * 64), ("tune", (C.c_int * 4) * 5),
+                ("layer_tensor", C.c_int)]
 
 
 _lib = None
@@ -179,7 +180,8 @@ class Plan:
 
     def __init__(self, shape, omega, c, a=None, zeta=None, *, length=1.0, c0=1.0, m_real=8,
                  m_layer=3, symbol="continuous", precision="fp64", a_floor=0.0, max_nrhs=1,
-                 nodes_real=None, nodes_zeta=None, a_nodes=None, stream=None, interp_order=1, m_damp=0):
+                 nodes_real=None, nodes_zeta=None, a_nodes=None, stream=None, interp_order=1, m_damp=0,
+                 layer_tensor=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("helmpre needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -210,6 +212,7 @@ class Plan:
         o.max_nrhs = int(max_nrhs)
         o.interp_order = int(interp_order)
         o.m_damp = int(m_damp)
+        o.layer_tensor = int(bool(layer_tensor))
         self._opts = o
         lay = HpLayer()
         lay.zeta = None if keep[2] is None else keep[2].ctypes.data
@@ -237,7 +240,8 @@ class Plan:
                 "znode": np.array(pi.znode[:pi.Mt + 1]), "ahat": np.array(pi.ahat[:K]),
                 "gamma": np.array(pi.gamma_re[:K]) + 1j * np.array(pi.gamma_im[:K]),
                 "workspace_bytes": int(pi.workspace_bytes), "interp_order": int(pi.interp_order),
-                "m_damp": int(pi.m_damp), "anode": np.array(pi.anode[:pi.m_damp]),
+                "m_damp": int(pi.m_damp), "layer_tensor": int(pi.layer_tensor),
+                "anode": np.array(pi.anode[:(pi.K // pi.M if pi.layer_tensor else pi.m_damp)]),
                 "tune": [tuple(int(x) for x in pi.tune[k]) for k in range(5)]}
 
     def _fields(self, x, dtype, name):

@@ -74,7 +74,8 @@ struct hp_plan_s {
   DevBuf lagtab;   // Lagrange table of CombineArgs::lag (order >= 2)
   hp::PassTune tune[5];   // run-time choices of passes A, A', B, M, C (hp_plan_autotune)
   int tune_gen = 0;        // bumped when they change (captured step graphs become stale)
-  int Ma = 0;      // damping nodes of the bivariate (c, a) scheme (0: univariate)
+  int Ma = 0;      // second-axis nodes of a tensor scheme: damping (c, a) or Im gamma (layer tensor)
+  int tensor = 0;  // 1: layer tensor (second axis Im gamma)
   double anode[64] = {0};
   DevBuf posa;     // per point: position among the damping nodes (Ma >= 2)
   // node usage counts for the byte model of the passes
@@ -276,7 +277,7 @@ size_t hp_plan_workspace_bytes(const hp_grid* g, const hp_plan_opts* o, int K) {
   const size_t nr = (size_t)std::max(1, o->max_nrhs);
   size_t b = nr * npts * fs * (size_t)(K + 1);      // t and the K node fields
   b += npts * (8 + 32 + (o->precision == HP_FP64 ? 0 : 16));   // pos, coef64, coef32
-  if (o->m_damp >= 2) b += npts * 8;                           // posa
+  if (o->m_damp >= 2 || o->layer_tensor) b += npts * 8;       // posa
   return b;
 }
 
@@ -367,10 +368,24 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   if (bad) return failc(HP_E_MEDIA);
   const bool q1 = opts->m_real == 1 && !opts->nodes_real;
   const bool has_layer = P->zmax > 0 && !q1;
-  st = place_real_nodes(*P, *opts, c0, has_layer);
+  // layer tensor: speed nodes on [c_min, c_max] by Im gamma nodes on [-max(c zeta), 0]
+  // (c need not equal c0 in the layer); the layer legs are replaced
+  const bool tensor = has_layer && opts->layer_tensor;
+  if (tensor && (opts->m_damp >= 2 || opts->interp_order >= 2 || opts->m_layer < 1 ||
+                 opts->m_layer + 1 > hp::kMaxNodes))
+    return failc(HP_E_INVALID);
+  st = place_real_nodes(*P, *opts, c0, has_layer && !tensor);
   if (st) return failc(st);
   P->Mt = 0;
-  if (has_layer) {
+  if (tensor) {
+    double gmax = 0.0;
+    for (size_t i = 0; i < np; ++i) gmax = std::max(gmax, c[i] * zeta[i]);
+    P->tensor = 1;
+    P->Ma = opts->m_layer + 1;
+    for (int r = 0; r < P->Ma; ++r) P->anode[r] = -gmax + gmax * ((double)r / (P->Ma - 1));
+    P->anode[P->Ma - 1] = 0.0;
+    if (P->M * P->Ma > hp::kMaxNodes) return failc(HP_E_INVALID);
+  } else if (has_layer) {
     const int Mt = opts->m_layer;
     if (Mt < 1 || P->M + Mt > hp::kMaxNodes) return failc(HP_E_INVALID);
     P->znode[0] = 0;
@@ -385,7 +400,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     P->Mt = Mt;
     if (layer_bad) return failc(HP_E_LAYER);
   }
-  P->K = P->M + P->Mt;
+  P->K = P->tensor ? P->M * P->Ma : P->M + P->Mt;
   // real-axis interpolation: piecewise linear (Section 4.1), or piecewise Lagrange of
   // degree 2 or 3 on consecutive nodes (at most M - 1)
   if (opts->interp_order < 0 || opts->interp_order > 3) return failc(HP_E_INVALID);
@@ -394,7 +409,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   // = node m + M r; no layer (its nodes would need a third axis), piecewise linear
   if (opts->m_damp < 0 || opts->m_damp > hp::kMaxNodes) return failc(HP_E_INVALID);
   if (opts->m_damp >= 2) {
-    if (has_layer || opts->interp_order >= 2 || opts->a_nodes) return failc(HP_E_INVALID);
+    if (has_layer || opts->interp_order >= 2 || opts->a_nodes || opts->layer_tensor) return failc(HP_E_INVALID);
     double amin = a ? a[0] : 0.0, amax = amin;
     if (a)
       for (size_t i = 1; i < np; ++i) { amin = std::min(amin, a[i]); amax = std::max(amax, a[i]); }
@@ -410,7 +425,8 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   T.M = P->M;
   T.Mt = P->Mt;
   T.mo = P->mo;
-  T.has_layer = has_layer ? 1 : 0;
+  T.has_layer = has_layer && !tensor ? 1 : 0;
+  T.second = tensor ? 1 : 0;
   T.order = P->order;
   T.Ma = P->Ma;
   for (int i = 0; i < P->Ma; ++i) T.anode[i] = P->anode[i];
@@ -473,7 +489,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
       if (!(opts->a_nodes[m] >= 0) || !std::isfinite(opts->a_nodes[m])) return failc(HP_E_INVALID);
       P->ahat[m] = opts->a_nodes[m];
     }
-  } else if (a_varies && P->Ma < 2) {
+  } else if (a_varies && (P->Ma < 2 || P->tensor)) {
     std::vector<double> num(P->K, 0.0), den(P->K, 0.0);
     double mean = 0;
     for (size_t i = 0; i < np; ++i) {
@@ -492,12 +508,21 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
   }
   for (int m = 0; m < P->M; ++m) P->ahat[m] = std::max(P->ahat[m], opts->a_floor);
   for (int m = 0; m < P->M; ++m) { P->gre[m] = P->cnode[m]; P->gim[m] = 0; }
-  for (int r = 0; r < P->Ma; ++r)   // bivariate: node m + M r carries (c_m, a_r)
-    for (int m = 0; m < P->M; ++m) {
-      P->gre[m + P->M * r] = P->cnode[m];
-      P->gim[m + P->M * r] = 0;
-      P->ahat[m + P->M * r] = std::max(P->anode[r], opts->a_floor);
-    }
+  if (P->tensor) {   // layer tensor: node m + M r carries gamma = c_m + i g_r and the damping of c_m
+    for (int r = P->Ma - 1; r >= 0; --r)
+      for (int m = 0; m < P->M; ++m) {
+        P->gre[m + P->M * r] = P->cnode[m];
+        P->gim[m + P->M * r] = P->anode[r];
+        P->ahat[m + P->M * r] = P->ahat[m];
+      }
+  } else {
+    for (int r = 0; r < P->Ma; ++r)   // bivariate: node m + M r carries (c_m, a_r)
+      for (int m = 0; m < P->M; ++m) {
+        P->gre[m + P->M * r] = P->cnode[m];
+        P->gim[m + P->M * r] = 0;
+        P->ahat[m + P->M * r] = std::max(P->anode[r], opts->a_floor);
+      }
+  }
   for (int j = 1; j <= P->Mt; ++j) {
     P->ahat[P->M + j - 1] = P->ahat[P->mo];
     P->gre[P->M + j - 1] = c0;
@@ -614,7 +639,8 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info) {
   info->workspace_bytes = p->t.bytes + p->fields.bytes + p->pos.bytes + p->coef64.bytes + p->coef32.bytes;
   info->precision = p->prec;
   info->interp_order = p->order;
-  info->m_damp = p->Ma;
+  info->m_damp = p->tensor ? 0 : p->Ma;
+  info->layer_tensor = p->tensor;
   for (int sl = 0; sl < 5; ++sl) {
     info->tune[sl][0] = p->tune[sl].nthr;
     info->tune[sl][1] = p->tune[sl].tc;

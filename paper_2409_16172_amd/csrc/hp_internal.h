@@ -214,7 +214,8 @@ hipError_t launch_media_scan(const double* c, const double* a, const double* zet
 struct NodeTable {
   int M, Mt, mo, has_layer;
   int order;   // real-axis interpolation degree in effect (1 = piecewise linear, else Lagrange)
-  int Ma;      // damping nodes of the bivariate (c, a) scheme, real node (m, r) = m + M r (0: off)
+  int Ma;      // second-axis nodes of a tensor scheme, node (m, r) = m + M r (0: off)
+  int second;  // the second axis: 0 damping a (bivariate), 1 Im gamma = -c zeta (layer tensor)
   double cnode[kMaxNodes];
   double znode[kMaxNodes + 1];
   double anode[kMaxNodes];

@@ -1875,8 +1875,9 @@ __device__ double encode_pos(const NodeTable& T, double c, double z) {
   return lo + t;
 }
 
-// Position of damping a among the damping nodes of the bivariate scheme: r + u with
-// weights 1-u on node r and u on node r+1 (r in [0, Ma-2]).
+// Position of a value among the second-axis nodes of a tensor scheme (damping a, or
+// Im gamma for the layer tensor): r + u with weights 1-u on node r and u on node r+1
+// (r in [0, Ma-2]).
 __device__ double encode_damping(const NodeTable& T, double a) {
   const double aa = fmin(fmax(a, T.anode[0]), T.anode[T.Ma - 1]);
   int lo = 0, hi = T.Ma - 1;
@@ -1892,7 +1893,7 @@ __global__ __launch_bounds__(256) void k_plan_points(const double* __restrict__ 
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const double cv = c[i], zv = z ? z[i] : 0.0, av = a ? a[i] : 0.0;
     pos[i] = encode_pos(T, cv, T.has_layer ? zv : 0.0);
-    if (T.Ma >= 2) posa[i] = encode_damping(T, av);
+    if (T.Ma >= 2) posa[i] = encode_damping(T, T.second ? -cv * zv : av);
     const double gr = cv * cv * (1.0 - zv * zv), gi = -2.0 * cv * cv * zv;   // (c (1 - i zeta))^2
     const cpx<double> g2 = {gr, gi}, be = {omega * omega - 2.0 * gr * sih2, omega * av - 2.0 * gi * sih2};
     coef64[2 * i] = g2;
