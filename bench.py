@@ -141,9 +141,13 @@ def batch3d(args, dev):
     plan = binding.plan_from_workload(w)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if not args.no_autotune:
+        plan.autotune()
+    t_tune = time.perf_counter() - t0
     f = torch.from_numpy(w.f).to(dev)
-    print(f"[bench] 3-D batch {w.shape} x {w.f.shape[0]} K={plan.info()['K']} plan {t_plan * 1e3:.0f} ms",
-          file=sys.stderr, flush=True)
+    print(f"[bench] 3-D batch {w.shape} x {w.f.shape[0]} K={plan.info()['K']} plan {t_plan * 1e3:.0f} ms, "
+          f"autotune {t_tune:.1f} s, choices {plan.info()['tune']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x, infos = plan.solve(f, rtol=1e-8, restart=30)
@@ -164,7 +168,8 @@ def batch3d(args, dev):
     out = {"mode": "batch3d", "workload": f"{w.name}: {w.shape[0]}^3, 7-point FD, {w.info['n_lambda']:.0f} wavelengths, "
                                          f"random field in [0.8,1.2] + c=1.4 sphere, {w.info['layer_cells']}-cell layer, "
                                          f"{w.m_real}+{w.m_layer} nodes, mixed precision, rtol 1e-8",
-           "nrhs": int(w.f.shape[0]), "plan_ms": t_plan * 1e3, "batch_s": t_batch,
+           "nrhs": int(w.f.shape[0]), "plan_ms": t_plan * 1e3, "autotune_s": t_tune, "tune": plan.info()["tune"],
+           "batch_s": t_batch,
            "batch_solves_per_s": w.f.shape[0] / t_batch, "single_s": singles,
            "single_solves_per_s": len(singles) / sum(singles) if singles else None,
            "iters": [i.iters for i in infos], "max_rel_true_residual": max(i.rel_true_residual for i in infos),
