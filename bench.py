@@ -477,7 +477,8 @@ def main():
     ap.add_argument("--spec-pn-inverse", action="store_true",
                     help="estimate min |lambda(P_N)| by inverse runs instead of the bound omega a")
     ap.add_argument("--spec-nodes", type=int, nargs="+", default=[1, 2, 4, 8])
-    ap.add_argument("--spec-tables", nargs="*", default=[], help="subset of table2..table6")
+    ap.add_argument("--spec-tables", nargs="*", default=["table2"],
+                    help="which of table2..table6 (each takes a few minutes at N = 480)")
     ap.add_argument("--mode", choices=["solve", "apply", "batch3d", "example1", "interp", "spectrum", "bivariate",
                                        "autotune"],
                     default="solve",
