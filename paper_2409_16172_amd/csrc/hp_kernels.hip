@@ -1239,42 +1239,48 @@ __device__ __forceinline__ void block_reduce_write(cpx<double> (&acc)[CNT], int 
 
 __device__ __forceinline__ double cabs2(cpx<double> a) { return a.re * a.re + a.im * a.im; }
 
+// Workgroup barrier that orders LDS only: global stores issued before it (the
+// solver state) are not waited for, since no thread of the block reads them back.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum the kRedBlocks block partials of `cnt` slots of right-hand side `rhs`
-// into sums[] in a fixed order (wave w handles slots w, w + nw, ...; two slots
-// per round, every partial load of a round issued before the first add).
+// into sums[] in a fixed order (wave w handles slots w, w + nw, ...; kSlotsPerWave
+// slots per round, so that each lane has 16 partial loads of a round in flight
+// before the first add).
 static_assert(kRedBlocks % 64 == 0, "partials per slot must fill whole wavefronts");
-__device__ void reduce_slots(const cpx<double>* __restrict__ part, int rhs, int cnt, cpx<double>* sums) {
-  constexpr int kLoads = kRedBlocks / 64;
+constexpr int kSlotLoads = kRedBlocks / 64;
+constexpr int kSlotsPerWave = kSlotLoads >= 16 ? 1 : 16 / kSlotLoads;
+__device__ __forceinline__ void reduce_slots(const cpx<double>* __restrict__ part, int rhs, int cnt, cpx<double>* sums) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks + lane;
-  for (int s0 = wv; s0 < cnt; s0 += 2 * nw) {
-    const int s1 = s0 + nw;
-    const cpx<double>* p0 = pr + (size_t)s0 * kRedBlocks;
-    const cpx<double>* p1 = pr + (size_t)(s1 < cnt ? s1 : s0) * kRedBlocks;
-    cpx<double> x0[kLoads], x1[kLoads];
+  for (int s0 = wv; s0 < cnt; s0 += kSlotsPerWave * nw) {
+    cpx<double> x[kSlotsPerWave][kSlotLoads];
 #pragma unroll
-    for (int b = 0; b < kLoads; ++b) {
-      x0[b] = p0[64 * b];
-      x1[b] = p1[64 * b];
-    }
-    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    for (int q = 0; q < kSlotsPerWave; ++q) {
+      const int sl = s0 + q * nw;
+      const cpx<double>* p = pr + (size_t)(sl < cnt ? sl : s0) * kRedBlocks;
 #pragma unroll
-    for (int b = 0; b < kLoads; ++b) {
-      r0 += x0[b].re;
-      i0 += x0[b].im;
-      r1 += x1[b].re;
-      i1 += x1[b].im;
+      for (int b = 0; b < kSlotLoads; ++b) x[q][b] = p[64 * b];
     }
-    r0 = wave_sum(r0);
-    i0 = wave_sum(i0);
-    r1 = wave_sum(r1);
-    i1 = wave_sum(i1);
-    if (lane == 0) {
-      sums[s0] = {r0, i0};
-      if (s1 < cnt) sums[s1] = {r1, i1};
+#pragma unroll
+    for (int q = 0; q < kSlotsPerWave; ++q) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int b = 0; b < kSlotLoads; ++b) {
+        re += x[q][b].re;
+        im += x[q][b].im;
+      }
+      re = wave_sum(re);
+      im = wave_sum(im);
+      const int sl = s0 + q * nw;
+      if (lane == 0 && sl < cnt) sums[sl] = {re, im};
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Givens state of one right-hand side staged in LDS by the finishing kernels.
@@ -1284,21 +1290,39 @@ struct GivensLds {
 };
 
 // Commit Hessenberg column j given its unrotated entries raw[0..j+1] (in LDS):
-// store it (raw and rotated) in the state, apply the previous Givens rotations,
-// form rotation j and rotate g.  Single thread.  Returns |g_{j+1}|.
-__device__ double commit_column(KState& S, GivensLds& L, int j, const cpx<double>* raw) {
+// apply the previous Givens rotations (rotated column to L.col), form rotation j,
+// rotate g and store the rotation and g in the state.  Single thread; the
+// columns themselves are stored by store_column.  `iters`: the state's step count,
+// read at kernel start (a global load here would stall the chain), incremented
+// and stored.  Returns |g_{j+1}|.
+__device__ double commit_column(KState& S, GivensLds& L, int j, const cpx<double>* raw, int& iters) {
   cpx<double>* col = L.col;
-  for (int i = 0; i <= j + 1; ++i) col[i] = raw[i];
-  for (int i = 0; i < j; ++i) {
-    const cpx<double> a = col[i], b = col[i + 1];
-    const cpx<double> c = L.cs[i], s = L.sn[i];
-    // [conj(c) conj(s); -s c] applied to (a, b)
-    col[i] = {c.re * a.re + c.im * a.im + s.re * b.re + s.im * b.im,
-              c.re * a.im - c.im * a.re + s.re * b.im - s.im * b.re};
-    col[i + 1] = {-(s.re * a.re - s.im * a.im) + (c.re * b.re - c.im * b.im),
-                  -(s.re * a.im + s.im * a.re) + (c.re * b.im + c.im * b.re)};
+  // Rotation i mixes entries i and i+1.  The entry carried to the next rotation
+  // stays in registers, and the operands of four rotations are loaded from LDS
+  // at once (indices clamped in range), so the dependent chain waits for LDS once
+  // per four steps.
+  constexpr int U = 4;
+  cpx<double> a = raw[0];
+  for (int i0 = 0; i0 < j; i0 += U) {
+    cpx<double> bb[U], cc[U], ss[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u < j ? i0 + u : j - 1;
+      bb[u] = raw[i + 1];
+      cc[u] = L.cs[i];
+      ss[u] = L.sn[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i0 + u >= j) break;
+      const cpx<double> b = bb[u], c = cc[u], s = ss[u];
+      // [conj(c) conj(s); -s c] applied to (a, b)
+      col[i0 + u] = {c.re * a.re + c.im * a.im + s.re * b.re + s.im * b.im,
+                     c.re * a.im - c.im * a.re + s.re * b.im - s.im * b.re};
+      a = {-(s.re * a.re - s.im * a.im) + (c.re * b.re - c.im * b.im),
+           -(s.re * a.im + s.im * a.re) + (c.re * b.im + c.im * b.re)};
+    }
   }
-  const cpx<double> a = col[j];
   const double hn = raw[j + 1].re;   // the subdiagonal entry is real and >= 0
   const double aa = sqrt(cabs2(a));
   const double den = sqrt(aa * aa + hn * hn);
@@ -1313,16 +1337,31 @@ __device__ double commit_column(KState& S, GivensLds& L, int j, const cpx<double
   const cpx<double> gj = L.g[j];
   L.g[j] = {c.re * gj.re + c.im * gj.im, c.re * gj.im - c.im * gj.re};   // conj(c) g_j
   L.g[j + 1] = {-s.re * gj.re, -s.re * gj.im};
-  cpx<double>* hr = S.Hraw + (size_t)j * (kMaxRestart + 1);
-  cpx<double>* hc = S.H + (size_t)j * (kMaxRestart + 1);
-  for (int i = 0; i <= j + 1; ++i) { hr[i] = raw[i]; hc[i] = col[i]; }
   S.cs[j] = c;
   S.sn[j] = s;
   S.g[j] = L.g[j];
   S.g[j + 1] = L.g[j + 1];
   S.k = j + 1;
-  S.iters += 1;
+  S.iters = ++iters;
   return sqrt(cabs2(L.g[j + 1]));
+}
+
+// Make one lane's LDS writes visible to the rest of its wavefront.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Store committed column j (raw and rotated entries 0..j+1) in the state; the
+// lanes of one wavefront share the entries.
+__device__ __forceinline__ void store_column(KState& S, const GivensLds& L, int j, const cpx<double>* raw, int lane) {
+  cpx<double>* hr = S.Hraw + (size_t)j * (kMaxRestart + 1);
+  cpx<double>* hc = S.H + (size_t)j * (kMaxRestart + 1);
+  for (int i = lane; i <= j + 1; i += 64) {
+    hr[i] = raw[i];
+    hc[i] = L.col[i];
+  }
 }
 
 __device__ __forceinline__ void publish_stop(int* host_stop, int rhs, int v) {
@@ -1441,32 +1480,75 @@ __global__ __launch_bounds__(256) void k_scale_v0(cpx<double>* V, size_t npts, s
 // and w = A u_j (slot j+1).  Partial-sum slots: [0, j) a = V^H u_j,
 // [j, 2j) b = V^H w, 2j ||u_j||^2, 2j+1 u_j^H w, 2j+2 ||w||^2.
 
+// Element-wise load of a complex value (keeps a conditional struct copy from
+// becoming a private-memory temporary).
+__device__ __forceinline__ cpx<double> ldc(const cpx<double>& p) { return {p.re, p.im}; }
+
+// Hessenberg columns 0..j-2 staged in LDS, packed: column i (entries 0..i+1) at
+// offset i (i + 3) / 2.
+__device__ __forceinline__ int hpacked(int i) { return i * (i + 3) / 2; }
+constexpr int kHPacked = kMaxRestart * (kMaxRestart + 3) / 2;
+constexpr int kFinThreads = 1024;
+constexpr int kHPrefetch = ((kMaxRestart - 1) * (kMaxRestart + 1) + kFinThreads - 1) / kFinThreads;
+
 __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, int j, int restart,
                                  int* skip_step, int* host_stop) {
   __shared__ cpx<double> sums[kPartSlots];
   __shared__ cpx<double> zz[kMaxRestart + 1], hp[kMaxRestart + 1], raw[kMaxRestart + 2];
+  __shared__ cpx<double> hsh[kHPacked];
   __shared__ GivensLds L;
   __shared__ double sh_sigma;
   __shared__ int sh_break;
-  for (int i = threadIdx.x; i < kMaxRestart; i += blockDim.x) { L.cs[i] = S.cs[i]; L.sn[i] = S.sn[i]; }
-  for (int i = threadIdx.x; i <= kMaxRestart; i += blockDim.x) { L.g[i] = S.g[i]; hp[i] = S.hprov[i]; }
+  // Every load of the state this step reads (Givens rotations, g, the provisional
+  // column, the finished Hessenberg columns but the last) is issued together with
+  // the partial sums, so that their latencies overlap; they go to LDS afterwards.
+  // (loads are unconditional, from clamped in-bounds indices, so that they stay
+  // plain register loads; the unused values are dropped)
+  const int t = threadIdx.x;
+  const int tc = t < kMaxRestart ? t : 0, tg = t <= kMaxRestart ? t : 0;
+  const cpx<double> rc = ldc(S.cs[tc]), rs = ldc(S.sn[tc]), rg = ldc(S.g[tg]), rh = ldc(S.hprov[tg]);
+  cpx<double> hv[kHPrefetch];
+  int hdst[kHPrefetch];
+  const int ld = j + 1;            // columns 0..j-2, rows 0..j as a rectangle
+#pragma unroll
+  for (int r = 0; r < kHPrefetch; ++r) {
+    const int e = t + kFinThreads * r;
+    const int i = e / ld, k = e - i * ld;
+    const bool use = i < j - 1 && k <= i + 1;
+    hv[r] = ldc(S.Hraw[use ? (size_t)i * (kMaxRestart + 1) + k : 0]);
+    hdst[r] = use ? hpacked(i) + k : -1;
+  }
+  const double target = S.target;
+  int iters = S.iters;
   reduce_slots(part, rhs, 2 * j + 3, sums);   // ends with a barrier
+  if (t < kMaxRestart) { L.cs[t] = rc; L.sn[t] = rs; }
+  if (t <= kMaxRestart) { L.g[t] = rg; hp[t] = rh; }
+#pragma unroll
+  for (int r = 0; r < kHPrefetch; ++r)
+    if (hdst[r] >= 0) hsh[hdst[r]] = hv[r];
+  lds_barrier();
   const cpx<double>* a = sums;
   const cpx<double>* bv = sums + j;
   const int lane = threadIdx.x & 63;
   if (threadIdx.x < 64) {
     // v_j = (u_j - V a) / sigma; column j-1 = (hprov_{j-1} + a, sigma)
     const double aa = wave_sum(lane < j ? cabs2(a[lane]) : 0.0);
-    if (threadIdx.x != 0) goto first_done;
     const double s2 = sums[2 * j].re - aa;
     const double sigma = s2 > 0.0 ? sqrt(s2) : 0.0;
-    sh_sigma = sigma;
-    sh_break = !(sigma > 0.0);
+    const int brk = !(sigma > 0.0);
+    if (lane == 0) {
+      sh_sigma = sigma;
+      sh_break = brk;
+    }
     if (j >= 1) {
-      for (int k = 0; k < j; ++k) raw[k] = cadd(hp[k], a[k]);
-      raw[j] = {sigma, 0.0};
-      const double est = commit_column(S, L, j - 1, raw);
-      if (sh_break || est <= S.target) {   // the cycle ended with column j-1
+      if (lane < j) raw[lane] = cadd(hp[lane], a[lane]);
+      if (lane == 0) raw[j] = {sigma, 0.0};
+      wave_lds_sync();
+      double est = 0.0;
+      if (lane == 0) est = commit_column(S, L, j - 1, raw, iters);
+      wave_lds_sync();
+      store_column(S, L, j - 1, raw, lane);
+      if (lane == 0 && (brk || est <= target)) {   // the cycle ended with column j-1
         S.stop_at = j - 1;
         skip_step[rhs] = 1;
         publish_stop(host_stop, rhs, 1);
@@ -1474,15 +1556,25 @@ __device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, in
       }
     }
   }
-first_done:
-  __syncthreads();
+  lds_barrier();
   if (sh_break) return;
-  // z = Hraw[0..j][0..j-1] a, the expansion of A V a in v_0..v_j
-  for (int k = threadIdx.x; k <= j; k += blockDim.x) {
+  // z = Hraw[0..j][0..j-1] a, the expansion of A V a in v_0..v_j (column j-1 is
+  // the one committed above, still in raw).  Sixteen lanes per row k, each over
+  // every sixteenth term, then summed across the sixteen in a fixed order.
+  {
+    static_assert(kFinThreads >= 16 * (kMaxRestart + 1) - 16, "one 16-lane group per row of z");
+    const int k = threadIdx.x >> 4, q = threadIdx.x & 15;
     cpx<double> acc = {0.0, 0.0};
-#pragma unroll 8
-    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) acc = cadd(acc, cmul(S.Hraw[(size_t)i * (kMaxRestart + 1) + k], a[i]));
-    zz[k] = acc;
+    if (k <= j) {
+      for (int i = (k > 0 ? k - 1 : 0) + q; i < j; i += 16)
+        acc = cadd(acc, cmul(i < j - 1 ? hsh[hpacked(i) + k] : raw[k], a[i]));
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+      acc.re += __shfl_xor(acc.re, off, 16);
+      acc.im += __shfl_xor(acc.im, off, 16);
+    }
+    if (k <= j && q == 0) zz[k] = acc;
   }
   const double sigma = sh_sigma, isg = 1.0 / sigma;
   if (threadIdx.x < 64) {
@@ -1492,13 +1584,13 @@ first_done:
     const cpx<double> ab = {wave_sum(t.re), wave_sum(t.im)};
     if (lane == 0) raw[j] = cscale(csub(sums[2 * j + 1], ab), isg);
   }
-  __syncthreads();
+  lds_barrier();
   // hprov_j = [V, v_j]^H A v_j = (p - z) / sigma (parallel over k)
   for (int k = threadIdx.x; k <= j; k += blockDim.x) {
     const cpx<double> pk = k < j ? bv[k] : raw[j];
     hp[k] = cscale(csub(pk, zz[k]), isg);
   }
-  __syncthreads();
+  lds_barrier();
   // update coefficients: u_{j+1} = w/sigma - V cv - cu u_j, y = z/sigma + hprov_j
   const cpx<double> cu = cscale(cadd(cscale(zz[j], isg), hp[j]), isg);
   for (int k = threadIdx.x; k <= j; k += blockDim.x) {
@@ -1520,32 +1612,52 @@ first_done:
   zp = wave_sum(zp);
   z2 = wave_sum(z2);
   h2 = wave_sum(h2);
-  if (lane != 0) return;
-  S.cu = cu;
-  S.inv_sigma = isg;
+  // from here on every lane of wave 0 computes the same values
+  if (lane == 0) {
+    S.cu = cu;
+    S.inv_sigma = isg;
+  }
   const double av2 = (sums[2 * j + 2].re - 2.0 * zp + z2) * isg * isg;   // ||A v_j||^2
   const double r2 = av2 - h2;
   const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
-  // residual estimate with the provisional column j
+  // residual estimate with the provisional column j (operands of four rotations
+  // loaded at once, as in commit_column)
   cpx<double> t0 = hp[0];
-  for (int i = 0; i < j; ++i) {
-    const cpx<double> x1 = hp[i + 1], c = L.cs[i], s = L.sn[i];
-    t0 = {-(s.re * t0.re - s.im * t0.im) + (c.re * x1.re - c.im * x1.im),
-          -(s.re * t0.im + s.im * t0.re) + (c.re * x1.im + c.im * x1.re)};
+  for (int i0 = 0; i0 < j; i0 += 4) {
+    cpx<double> xx[4], cc[4], ss[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u < j ? i0 + u : j - 1;
+      xx[u] = hp[i + 1];
+      cc[u] = L.cs[i];
+      ss[u] = L.sn[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u >= j) break;
+      const cpx<double> x1 = xx[u], c = cc[u], s = ss[u];
+      t0 = {-(s.re * t0.re - s.im * t0.im) + (c.re * x1.re - c.im * x1.im),
+            -(s.re * t0.im + s.im * t0.re) + (c.re * x1.im + c.im * x1.re)};
+    }
   }
   const double tt = sqrt(cabs2(t0));
   const double den = sqrt(tt * tt + rho * rho);
   const double est = den > 0.0 ? rho / den * sqrt(cabs2(L.g[j])) : 0.0;
   const bool breakdown = rho <= 1e-14 * sqrt(av2 > 0.0 ? av2 : 0.0);
-  if (est <= S.target || breakdown || j + 1 >= restart) {
+  if (est <= target || breakdown || j + 1 >= restart) {
     // end the cycle with the provisional column j (its second projection would
     // change it by the loss of orthogonality only)
-    for (int k = 0; k <= j; ++k) raw[k] = hp[k];
-    raw[j + 1] = {rho, 0.0};
-    commit_column(S, L, j, raw);
-    S.stop_at = j;
-    skip_step[rhs] = 1;
-    publish_stop(host_stop, rhs, 1);
+    if (lane <= j) raw[lane] = hp[lane];
+    if (lane == 0) raw[j + 1] = {rho, 0.0};
+    wave_lds_sync();
+    if (lane == 0) commit_column(S, L, j, raw, iters);
+    wave_lds_sync();
+    store_column(S, L, j, raw, lane);
+    if (lane == 0) {
+      S.stop_at = j;
+      skip_step[rhs] = 1;
+      publish_stop(host_stop, rhs, 1);
+    }
   }
 }
 
@@ -1652,7 +1764,7 @@ __global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __r
   }
 }
 
-__global__ __launch_bounds__(1024) void k_arnoldi_fin(const cpx<double>* __restrict__ part, int* __restrict__ skip_step,
+__global__ __launch_bounds__(kFinThreads) void k_arnoldi_fin(const cpx<double>* __restrict__ part, int* __restrict__ skip_step,
                                                       KState* state, int j, int restart, int* __restrict__ host_stop) {
   const int rhs = blockIdx.x;
   if (skip_step[rhs]) return;
@@ -2019,7 +2131,9 @@ hipError_t launch_scale_v0(const KrylovArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st) {
-  if (j <= 4 * kDotsSlots)
+  // four waves per block when there are 512 or more blocks per right-hand side
+  // (two blocks per CU), else eight
+  if (kRedBlocks >= 512 && j <= 4 * kDotsSlots)
     hipLaunchKernelGGL(k_arnoldi_dots<4>, dim3(kRedBlocks, a.nrhs), dim3(4 * 64), 0, st, a.V, a.npts, a.vrs,
                        a.part, (const int*)a.skip_step, j);
   else if (j <= 8 * kDotsSlots)
@@ -2027,7 +2141,7 @@ hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st) {
                        a.part, (const int*)a.skip_step, j);
   else
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(1024), 0, st, (const cpx<double>*)a.part, a.skip_step,
+  hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(kFinThreads), 0, st, (const cpx<double>*)a.part, a.skip_step,
                      a.state, j, a.restart, a.host_stop);
   return hipGetLastError();
 }
