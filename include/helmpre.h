@@ -300,6 +300,19 @@ hp_status hp_solver_destroy(hp_solver s);
 hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps, double* ms, double* bytes,
                            void* stream);
 
+/* Pass timer (for benchmarks): hp_plan_time_pass(p, slot) makes every later
+ * launch of pass `slot` (numbered as in hp_profile_apply; -1 switches the timer
+ * off) on this plan, in applies, solves and solver sessions alike, run between a
+ * pair of HIP events recorded on the launch's stream, and clears the record.
+ * Launches captured into a graph and launches beyond 65536 per read are not
+ * timed.  hp_plan_pass_times waits for the recorded launches, stores the
+ * milliseconds of each in launch order in ms[0..min(count, cap)-1], sets *count
+ * to the number recorded and clears the record.  A launch whose right-hand sides
+ * had all stopped returns at once and is recorded too (a few microseconds).  The
+ * events are created on demand and kept until hp_plan_destroy. */
+hp_status hp_plan_time_pass(hp_plan p, int slot);
+hp_status hp_plan_pass_times(hp_plan p, double* ms, int cap, int* count);
+
 /* Autotuner of the transform passes: for each pass in turn, times the plan's apply
  * (one right-hand side) under every valid run-time choice — threads per line, lines
  * per workgroup and radix schedule of the mixed-radix passes (N = 2^a 3^b 5^c),

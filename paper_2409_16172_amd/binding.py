@@ -26,7 +26,8 @@ EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_byt
             "hp_apply_precond", "hp_matvec", "hp_solve", "hp_profile_apply", "hp_plan_destroy",
             "hp_status_str", "hp_last_error", "hp_solver_create", "hp_solver_start", "hp_solver_advance",
             "hp_solver_wait", "hp_solver_destroy", "hp_arnoldi", "hp_ritz_values",
-            "hp_arnoldi_vector", "hp_extreme_eigenvalue", "hp_plan_autotune"]
+            "hp_arnoldi_vector", "hp_extreme_eigenvalue", "hp_plan_autotune", "hp_plan_time_pass",
+            "hp_plan_pass_times"]
 
 
 class HpGrid(C.Structure):
@@ -101,6 +102,10 @@ def load_library(path: str = LIB_PATH):
     lib.hp_solve.restype = i
     lib.hp_profile_apply.argtypes = [vp, vp, vp, i, i, C.POINTER(d), C.POINTER(d), vp]
     lib.hp_profile_apply.restype = i
+    lib.hp_plan_time_pass.argtypes = [vp, i]
+    lib.hp_plan_time_pass.restype = i
+    lib.hp_plan_pass_times.argtypes = [vp, C.POINTER(d), i, C.POINTER(i)]
+    lib.hp_plan_pass_times.restype = i
     lib.hp_arnoldi.argtypes = [vp, vp, i, i, vp, C.POINTER(i), vp]
     lib.hp_arnoldi.restype = i
     lib.hp_ritz_values.argtypes = [vp, i, i, i, vp, vp, C.POINTER(d)]
@@ -361,6 +366,19 @@ class Plan:
         _check(load_library().hp_profile_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()), nr,
                                                int(reps), ms, by, _stream(stream)), "hp_profile_apply")
         return list(ms), list(by)
+
+    def time_pass(self, slot):
+        """Record every later launch of pass `slot` (0..4 as in profile_apply; None: off)
+        between HIP events (hp_plan_time_pass); read them with pass_times()."""
+        _check(load_library().hp_plan_time_pass(self._h, -1 if slot is None else int(slot)), "hp_plan_time_pass")
+
+    def pass_times(self):
+        """Milliseconds of each launch recorded since time_pass() or the last read, in order."""
+        cap = 1 << 16                       # the most launches recorded per read
+        ms = (C.c_double * cap)()
+        n = C.c_int(0)
+        _check(load_library().hp_plan_pass_times(self._h, ms, cap, C.byref(n)), "hp_plan_pass_times")
+        return list(ms[:min(n.value, cap)])
 
     def close(self):
         if getattr(self, "_h", None):

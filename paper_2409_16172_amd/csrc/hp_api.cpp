@@ -86,6 +86,11 @@ struct hp_plan_s {
   struct SolverWs* solver_ws_ptr = nullptr;
   int arnoldi_k = -1;   // basis vectors the last hp_arnoldi left in that workspace (-1: none)
   struct SolverWs* inner_ws_ptr = nullptr;   // the inner solves of hp_arnoldi's inverse operators
+  // pass timer (hp_plan_time_pass): an event pair around every launch of one pass
+  int timer_slot = -1;
+  bool timer_open = false;            // a start event was recorded for the current launch
+  size_t timer_n = 0;                 // launches recorded since the last read
+  std::vector<hipEvent_t> timer_ev;   // 2 per launch, created on demand and reused
 
   int real_kind() const { return prec == HP_FP64 ? 0 : 1; }
   size_t fsize() const { return prec == HP_FP64 ? 16 : 8; }
@@ -96,6 +101,9 @@ struct hp_plan_s {
       b->release();
     for (int i = 0; i < 3; ++i) { tw64[i].release(); tw32[i].release(); }
     release_solver_ws();
+    for (hipEvent_t e : timer_ev) (void)hipEventDestroy(e);
+    timer_ev.clear();
+    timer_n = 0;
   }
   void release_solver_ws();
 };
@@ -664,6 +672,35 @@ namespace {
 // launched reps times back to back between their events; they read and write
 // disjoint buffers, so a repeat recomputes the same result.  The in-place
 // middle-axis passes of 3-D grids are launched once.
+// Pass timer: launches recorded per read at most (later ones are not timed).
+constexpr size_t kMaxTimedLaunches = 1 << 16;
+
+// Start (end = false) or end the event pair of one launch of the timed pass on st.
+// Launches captured into a graph are not timed.
+hipError_t timer_mark(hp_plan_s* P, hipStream_t st, bool end) {
+  if (end) {
+    if (!P->timer_open) return hipSuccess;
+    P->timer_open = false;
+    hipError_t e = hipEventRecord(P->timer_ev[2 * P->timer_n + 1], st);
+    if (e == hipSuccess) ++P->timer_n;
+    return e;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusNone || P->timer_n >= kMaxTimedLaunches) return hipSuccess;
+  while (P->timer_ev.size() < 2 * (P->timer_n + 1)) {
+    // timing-only events: no system-scope fence (cache write-back) when they are
+    // recorded, so they add little to the work they bracket
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess) return e;
+    P->timer_ev.push_back(ev);
+  }
+  if ((e = hipEventRecord(P->timer_ev[2 * P->timer_n], st)) != hipSuccess) return e;
+  P->timer_open = true;
+  return hipSuccess;
+}
+
 hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, void* u, int out_kind,
                      size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st,
                      hipEvent_t* ev = nullptr, int reps = 1) {
@@ -676,10 +713,21 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   auto mark = [&](int i) {
     return (ev && (P->dim == 3 || (i != 2 && i != 4))) ? hipEventRecord(ev[i], st) : hipSuccess;
   };
+  // launch of pass `slot`, between the timer's events when that pass is timed
+  auto timed = [&](int slot, auto&& launch) -> hipError_t {
+    if (P->timer_slot != slot) return launch();
+    hipError_t e2 = timer_mark(P, st, false);
+    if (e2 == hipSuccess) e2 = launch();
+    if (e2 == hipSuccess) e2 = timer_mark(P, st, true);
+    P->timer_open = false;
+    return e2;
+  };
   if ((e = mark(0)) != hipSuccess) return e;
   for (int r = 0; r < reps; ++r) {
-    e = hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip, P->tune[0],
-                            st);
+    e = timed(0, [&] {
+      return hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip,
+                                 P->tune[0], st);
+    });
     if (e != hipSuccess) return e;
   }
   if ((e = mark(1)) != hipSuccess) return e;
@@ -689,7 +737,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.in = P->t.p; m.out = P->t.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = 1; m.nrhs = nrhs;
     m.in_rs = np; m.out_rs = np; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.tune = P->tune[1];
-    if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
+    if ((e = timed(1, [&] { return hp::launch_cols(m, st); })) != hipSuccess) return e;
   }
   if ((e = mark(2)) != hipSuccess) return e;
   hp::ColsArgs b{};
@@ -702,7 +750,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   b.store_need = (const uint8_t*)P->slabneed.p;
   b.tune = P->tune[2];
   for (int r = 0; r < reps; ++r)
-    if ((e = hp::launch_cols(b, st)) != hipSuccess) return e;
+    if ((e = timed(2, [&] { return hp::launch_cols(b, st); })) != hipSuccess) return e;
   if ((e = mark(3)) != hipSuccess) return e;
   if (P->dim == 3) {   // inverse along the middle axis for the K fields, in place
     hp::ColsArgs m{};
@@ -711,7 +759,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.in_rs = np * P->K; m.out_rs = np * P->K; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.slab_need = (const uint8_t*)P->slabneed.p;
     m.tune = P->tune[3];
-    if ((e = hp::launch_cols(m, st)) != hipSuccess) return e;
+    if ((e = timed(3, [&] { return hp::launch_cols(m, st); })) != hipSuccess) return e;
   }
   if ((e = mark(4)) != hipSuccess) return e;
   hp::CombineArgs c{};
@@ -723,7 +771,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   c.posa = (const double*)P->posa.p; c.Ma = P->Ma;
   c.tune = P->tune[4];
   for (int r = 0; r < (acc ? 1 : reps); ++r)
-    if ((e = hp::launch_combine(c, st)) != hipSuccess) return e;
+    if ((e = timed(4, [&] { return hp::launch_combine(c, st); })) != hipSuccess) return e;
   return mark(5);
 }
 
@@ -1461,6 +1509,30 @@ hp_status hp_plan_autotune(hp_plan p, double* before_ms, double* after_ms, void*
   if (after_ms) *after_ms = fin[0] + fin[1] + fin[2] + fin[3] + fin[4];
   ++p->tune_gen;
   save_tune(*p);
+  return HP_OK;
+}
+
+hp_status hp_plan_time_pass(hp_plan p, int slot) {
+  if (!p || slot < -1 || slot > 4) return HP_E_INVALID;
+  p->timer_slot = slot;
+  p->timer_open = false;
+  p->timer_n = 0;
+  return HP_OK;
+}
+
+hp_status hp_plan_pass_times(hp_plan p, double* ms, int cap, int* count) {
+  if (!p || !count || cap < 0 || (cap > 0 && !ms)) return HP_E_INVALID;
+  const size_t n = p->timer_n;
+  p->timer_n = 0;
+  for (size_t i = 0; i < n; ++i) {
+    HP_TRY(hipEventSynchronize(p->timer_ev[2 * i + 1]));
+    if ((int)i < cap) {
+      float t = 0;
+      HP_TRY(hipEventElapsedTime(&t, p->timer_ev[2 * i], p->timer_ev[2 * i + 1]));
+      ms[i] = (double)t;
+    }
+  }
+  *count = (int)n;
   return HP_OK;
 }
 
