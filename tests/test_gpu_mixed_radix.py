@@ -143,3 +143,24 @@ def test_plain_and_left_gmres_match_oracle(orc, hp, dev):
     _, iq = plan.solve(f, rtol=1e-15, restart=10, max_cycles=3, side="none")
     assert ip[0].iters == iq[0].iters == 30
     assert ip[0].rel_true_residual < 1e-2 * iq[0].rel_true_residual
+
+
+def test_long_restart_gmres_matches_oracle(orc, hp, dev):
+    """GMRES(64): Arnoldi steps past 32 take the eight-wave dot-product sweep and stage more
+    than 1024 Hessenberg entries in the finishing kernel; plain (many steps per cycle) and
+    right-preconditioned solves against the oracle's GMRES(64)."""
+    _case("long_restart_gmres", n=36)
+    w = inputs.workload("2d_inclusion", n=36, ppw=6.0)
+    plan = hp.plan_from_workload(w)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    for side, rtol in (("none", 1e-10), ("right", 1e-12)):
+        x, info = plan.solve(f, rtol=rtol, restart=64, max_cycles=100, side=side)
+        xr, res = ref.gmres(w.f[0], restart=64, rtol=rtol, max_cycles=100, side=side)
+        assert info[0].status == 0 and res["status"] == 0, side
+        true = rel(ref.matvec(x.cpu().numpy()[0]), w.f[0])
+        assert true <= rtol * 1.001, (side, true)
+        assert abs(info[0].rel_true_residual - true) <= 1e-6 * true + 1e-15, (side, info[0], true)
+        assert abs(info[0].iters - res["iters"]) <= max(2, res["iters"] // 50), (side, info[0].iters, res["iters"])
+        if side == "none":
+            assert res["iters"] > 64      # a full cycle of 64 steps and a second one
