@@ -302,8 +302,10 @@ hp_status hp_profile_apply(hp_plan p, const void* v, void* u, int nrhs, int reps
 
 /* Pass timer (for benchmarks): hp_plan_time_pass(p, slot) makes every later
  * launch of pass `slot` (numbered as in hp_profile_apply; -1 switches the timer
- * off) on this plan, in applies, solves and solver sessions alike, run between a
- * pair of HIP events recorded on the launch's stream, and clears the record.
+ * off) on this plan, in applies, solves and solver sessions alike, carry a pair of
+ * HIP events that take the kernel's own start and end times on the launch's
+ * stream (hipExtLaunchKernelGGL: no extra packets, so the timed work is not
+ * changed), and clears the record.
  * Launches captured into a graph and launches beyond 65536 per read are not
  * timed.  hp_plan_pass_times waits for the recorded launches, stores the
  * milliseconds of each in launch order in ms[0..min(count, cap)-1], sets *count

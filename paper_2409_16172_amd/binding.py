@@ -368,8 +368,8 @@ class Plan:
         return list(ms), list(by)
 
     def time_pass(self, slot):
-        """Record every later launch of pass `slot` (0..4 as in profile_apply; None: off)
-        between HIP events (hp_plan_time_pass); read them with pass_times()."""
+        """Record the start and end of every later launch of pass `slot` (0..4 as in
+        profile_apply; None: off) in HIP events (hp_plan_time_pass); read them with pass_times()."""
         _check(load_library().hp_plan_time_pass(self._h, -1 if slot is None else int(slot)), "hp_plan_time_pass")
 
     def pass_times(self):

@@ -86,9 +86,8 @@ struct hp_plan_s {
   struct SolverWs* solver_ws_ptr = nullptr;
   int arnoldi_k = -1;   // basis vectors the last hp_arnoldi left in that workspace (-1: none)
   struct SolverWs* inner_ws_ptr = nullptr;   // the inner solves of hp_arnoldi's inverse operators
-  // pass timer (hp_plan_time_pass): an event pair around every launch of one pass
+  // pass timer (hp_plan_time_pass): the start and end times of every launch of one pass
   int timer_slot = -1;
-  bool timer_open = false;            // a start event was recorded for the current launch
   size_t timer_n = 0;                 // launches recorded since the last read
   std::vector<hipEvent_t> timer_ev;   // 2 per launch, created on demand and reused
 
@@ -685,29 +684,21 @@ constexpr unsigned kSolverEventFlags = HP_SOLVER_EVENT_FLAGS;
 // Pass timer: launches recorded per read at most (later ones are not timed).
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
-// Start (end = false) or end the event pair of one launch of the timed pass on st.
-// Launches captured into a graph are not timed.
-hipError_t timer_mark(hp_plan_s* P, hipStream_t st, bool end) {
-  if (end) {
-    if (!P->timer_open) return hipSuccess;
-    P->timer_open = false;
-    hipError_t e = hipEventRecord(P->timer_ev[2 * P->timer_n + 1], st);
-    if (e == hipSuccess) ++P->timer_n;
-    return e;
-  }
+// Timing events for the next launch of the timed pass on st (nullptr when the
+// launch is not timed: a graph capture, or the record is full).
+hipError_t timer_events(hp_plan_s* P, hipStream_t st, const hipEvent_t** tev) {
+  *tev = nullptr;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(st, &cs);
   if (e != hipSuccess) return e;
   if (cs != hipStreamCaptureStatusNone || P->timer_n >= kMaxTimedLaunches) return hipSuccess;
   while (P->timer_ev.size() < 2 * (P->timer_n + 1)) {
-    // timing-only events: no system-scope fence (cache write-back) when they are
-    // recorded, so they add little to the work they bracket
     hipEvent_t ev;
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&ev)) != hipSuccess) return e;
     P->timer_ev.push_back(ev);
   }
-  if ((e = hipEventRecord(P->timer_ev[2 * P->timer_n], st)) != hipSuccess) return e;
-  P->timer_open = true;
+  *tev = &P->timer_ev[2 * P->timer_n];
+  ++P->timer_n;
   return hipSuccess;
 }
 
@@ -723,20 +714,20 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   auto mark = [&](int i) {
     return (ev && (P->dim == 3 || (i != 2 && i != 4))) ? hipEventRecord(ev[i], st) : hipSuccess;
   };
-  // launch of pass `slot`, between the timer's events when that pass is timed
+  // launch of pass `slot`, with the timer's events when that pass is timed
   auto timed = [&](int slot, auto&& launch) -> hipError_t {
-    if (P->timer_slot != slot) return launch();
-    hipError_t e2 = timer_mark(P, st, false);
-    if (e2 == hipSuccess) e2 = launch();
-    if (e2 == hipSuccess) e2 = timer_mark(P, st, true);
-    P->timer_open = false;
-    return e2;
+    const hipEvent_t* tev = nullptr;
+    if (P->timer_slot == slot) {
+      hipError_t e2 = timer_events(P, st, &tev);
+      if (e2 != hipSuccess) return e2;
+    }
+    return launch(tev);
   };
   if ((e = mark(0)) != hipSuccess) return e;
   for (int r = 0; r < reps; ++r) {
-    e = timed(0, [&] {
+    e = timed(0, [&](const hipEvent_t* tev) {
       return hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip,
-                                 P->tune[0], st);
+                                 P->tune[0], st, tev);
     });
     if (e != hipSuccess) return e;
   }
@@ -747,7 +738,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.in = P->t.p; m.out = P->t.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = 1; m.nrhs = nrhs;
     m.in_rs = np; m.out_rs = np; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.tune = P->tune[1];
-    if ((e = timed(1, [&] { return hp::launch_cols(m, st); })) != hipSuccess) return e;
+    if ((e = timed(1, [&](const hipEvent_t* tev) { m.tev = tev; return hp::launch_cols(m, st); })) != hipSuccess)
+      return e;
   }
   if ((e = mark(2)) != hipSuccess) return e;
   hp::ColsArgs b{};
@@ -760,7 +752,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   b.store_need = (const uint8_t*)P->slabneed.p;
   b.tune = P->tune[2];
   for (int r = 0; r < reps; ++r)
-    if ((e = timed(2, [&] { return hp::launch_cols(b, st); })) != hipSuccess) return e;
+    if ((e = timed(2, [&](const hipEvent_t* tev) { b.tev = tev; return hp::launch_cols(b, st); })) != hipSuccess)
+      return e;
   if ((e = mark(3)) != hipSuccess) return e;
   if (P->dim == 3) {   // inverse along the middle axis for the K fields, in place
     hp::ColsArgs m{};
@@ -769,7 +762,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     m.in_rs = np * P->K; m.out_rs = np * P->K; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.slab_need = (const uint8_t*)P->slabneed.p;
     m.tune = P->tune[3];
-    if ((e = timed(3, [&] { return hp::launch_cols(m, st); })) != hipSuccess) return e;
+    if ((e = timed(3, [&](const hipEvent_t* tev) { m.tev = tev; return hp::launch_cols(m, st); })) != hipSuccess)
+      return e;
   }
   if ((e = mark(4)) != hipSuccess) return e;
   hp::CombineArgs c{};
@@ -781,7 +775,8 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   c.posa = (const double*)P->posa.p; c.Ma = P->Ma;
   c.tune = P->tune[4];
   for (int r = 0; r < (acc ? 1 : reps); ++r)
-    if ((e = timed(4, [&] { return hp::launch_combine(c, st); })) != hipSuccess) return e;
+    if ((e = timed(4, [&](const hipEvent_t* tev) { c.tev = tev; return hp::launch_combine(c, st); })) != hipSuccess)
+      return e;
   return mark(5);
 }
 
@@ -1526,7 +1521,6 @@ hp_status hp_plan_autotune(hp_plan p, double* before_ms, double* after_ms, void*
 hp_status hp_plan_time_pass(hp_plan p, int slot) {
   if (!p || slot < -1 || slot > 4) return HP_E_INVALID;
   p->timer_slot = slot;
-  p->timer_open = false;
   p->timer_n = 0;
   return HP_OK;
 }

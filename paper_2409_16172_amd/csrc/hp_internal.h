@@ -97,9 +97,12 @@ int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, Pass
 
 // Pass A: forward transform along the contiguous axis.
 // in_kind: 0 = complex128 input, 1 = complex64 input.  real_kind: 0 = FP64, 1 = FP32.
+// Pass launchers take an optional pair of timing events `tev` (tev[0], tev[1]): the
+// pass's kernel is then launched with hipExtLaunchKernelGGL, which stores the
+// kernel's own start and end times in them.
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
                            size_t in_rs, size_t out_rs, int nrhs, const void* tw, const int* skip,
-                           const PassTune& tune, hipStream_t st);
+                           const PassTune& tune, hipStream_t st, const hipEvent_t* tev = nullptr);
 
 // Strided-axis transform over column tiles: element (o, p, c) at o*n*S + p*S + c.
 // mode 0: plain transform (dir -1/+1) of nfields fields;
@@ -121,6 +124,7 @@ struct ColsArgs {
   const uint8_t* slab_need;     // mode 0 over node fields: [K][outer] != 0 if the slab uses node n
   const uint8_t* store_need;    // mode 1, mixed-radix lengths: [K][n] != 0 if axis-0 index p uses node n
   PassTune tune;
+  const hipEvent_t* tev = nullptr;   // timing events of the launch (see launch_rows_fwd)
 };
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st);
 
@@ -144,6 +148,7 @@ struct CombineArgs {
   const double* posa;  // Ma >= 2: per point, the position among the damping nodes (bilinear in (c, a))
   int Ma;              // damping nodes of the bivariate scheme (0: univariate)
   PassTune tune;
+  const hipEvent_t* tev = nullptr;   // timing events of the launch (see launch_rows_fwd)
 };
 constexpr int kLagTable = kMaxNodes * 5;
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);

@@ -14,7 +14,20 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "hp_internal.h"
+
+// Launch of a pass kernel; with timing events (tev non-null) through
+// hipExtLaunchKernelGGL, which stores the kernel's own start and end times in
+// tev[0] and tev[1] (no marker packets around it).
+#define HP_PASS_LAUNCH(tev, kernel, grid, block, shm, st, ...)                                         \
+  do {                                                                                                 \
+    if ((tev) != nullptr)                                                                              \
+      hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)(shm), st, (tev)[0], (tev)[1], 0, __VA_ARGS__); \
+    else                                                                                               \
+      hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                                    \
+  } while (0)
 
 namespace hp {
 
@@ -740,11 +753,11 @@ struct RowsFwdL {
   template <int N>
   struct F {
     static hipError_t run(const void* in, void* out, int rows, size_t in_rs, size_t out_rs, int nrhs,
-                          const void* tw, const int* skip, hipStream_t st) {
+                          const void* tw, const int* skip, hipStream_t st, const hipEvent_t* tev) {
       using C = RowCfg<R, N>;
       dim3 grid((rows + C::G - 1) / C::G, nrhs);
-      hipLaunchKernelGGL((k_rows_fwd<R, TI, N>), grid, dim3(C::THREADS), 0, st, (const cpx<TI>*)in,
-                         (cpx<R>*)out, rows, in_rs, out_rs, (const cpx<R>*)tw, skip);
+      HP_PASS_LAUNCH(tev, (k_rows_fwd<R, TI, N>), grid, dim3(C::THREADS), 0, st, (const cpx<TI>*)in,
+                     (cpx<R>*)out, rows, in_rs, out_rs, (const cpx<R>*)tw, skip);
       return hipGetLastError();
     }
   };
@@ -862,11 +875,11 @@ static void allow_dynamic_lds(K kernel, size_t bytes) {
 
 template <typename R, typename TI>
 static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int rows, size_t in_rs, size_t out_rs,
-                               int nrhs, const void* tw, const int* skip, hipStream_t st) {
+                               int nrhs, const void* tw, const int* skip, hipStream_t st, const hipEvent_t* tev) {
   const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
   allow_dynamic_lds(k_rows_fwd_gen<R, TI>, lds);
-  hipLaunchKernelGGL((k_rows_fwd_gen<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
-                     (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
+  HP_PASS_LAUNCH(tev, (k_rows_fwd_gen<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
+                 (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
   return hipGetLastError();
 }
 
@@ -879,17 +892,17 @@ static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st)
   const cpx<R>* tw = (const cpx<R>*)a.tw;
   if (a.mode == 1) {
     allow_dynamic_lds(k_cols_gen<R, -1, 1>, lds);
-    hipLaunchKernelGGL((k_cols_gen<R, -1, 1>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
+    HP_PASS_LAUNCH(a.tev, (k_cols_gen<R, -1, 1>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
                        a.store_need);
   } else if (a.dir < 0) {
     allow_dynamic_lds(k_cols_gen<R, -1, 0>, lds);
-    hipLaunchKernelGGL((k_cols_gen<R, -1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
+    HP_PASS_LAUNCH(a.tev, (k_cols_gen<R, -1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
                        a.slab_need);
   } else {
     allow_dynamic_lds(k_cols_gen<R, +1, 0>, lds);
-    hipLaunchKernelGGL((k_cols_gen<R, +1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
+    HP_PASS_LAUNCH(a.tev, (k_cols_gen<R, +1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
                        a.slab_need);
   }
@@ -900,7 +913,7 @@ template <typename R, typename TO, bool ACC, int IM>
 static hipError_t combine_gen_l(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
   const size_t lds = (size_t)gp.n * (HP_GEN_LDS_TW ? 2 : 1) * sizeof(cpx<R>);
   allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC, IM>, lds);
-  hipLaunchKernelGGL((k_rows_combine_gen<R, TO, ACC, IM>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
+  HP_PASS_LAUNCH(a.tev, (k_rows_combine_gen<R, TO, ACC, IM>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
                      (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
                      a.Mt, a.mo, gp, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa, a.Ma);
   return hipGetLastError();
@@ -919,24 +932,24 @@ static hipError_t combine_gen(const GenPlan& gp, const CombineArgs& a, hipStream
 
 hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, void* out, int rows,
                            size_t in_rs, size_t out_rs, int nrhs, const void* tw, const int* skip,
-                           const PassTune& tune, hipStream_t st) {
+                           const PassTune& tune, hipStream_t st, const hipEvent_t* tev) {
   if (!is_pow2_len(n)) {
     GenPlan gp;
     if (!tuned_gen_plan(n, kGenRowE, 512, tune, &gp)) return hipErrorInvalidValue;
     if (real_kind == 0) {
       if (in_kind != 0) return hipErrorInvalidValue;
-      return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+      return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
     }
-    if (in_kind == 0) return rows_fwd_gen<float, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
-    return rows_fwd_gen<float, float>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+    if (in_kind == 0) return rows_fwd_gen<float, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
+    return rows_fwd_gen<float, float>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
   }
   if (real_kind == 0) {
     if (in_kind != 0) return hipErrorInvalidValue;
-    return dispatch_n<RowsFwdL<double, double>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+    return dispatch_n<RowsFwdL<double, double>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
   }
   if (in_kind == 0)
-    return dispatch_n<RowsFwdL<float, double>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
-  return dispatch_n<RowsFwdL<float, float>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st);
+    return dispatch_n<RowsFwdL<float, double>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
+  return dispatch_n<RowsFwdL<float, float>::F>(n, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
 }
 
 template <typename R>
@@ -961,15 +974,15 @@ struct ColsL {
         cpx<R>* out = (cpx<R>*)a.out;
         const cpx<R>* tw = (const cpx<R>*)a.tw;
         if (a.mode == 1)
-          hipLaunchKernelGGL((k_cols<R, R, N, -1, 1>), grid, dim3(C1::THREADS), 0, st, in, out, a.S,
+          HP_PASS_LAUNCH(a.tev, (k_cols<R, R, N, -1, 1>), grid, dim3(C1::THREADS), 0, st, in, out, a.S,
                              a.nfields, a.in_rs, a.out_rs, a.in_fs, a.out_fs, tw, a.skip, a.lam_ax,
                              a.lam_in, a.nodes, a.K, a.scale, a.store_mask, a.slab_need);
         else if (a.dir < 0)
-          hipLaunchKernelGGL((k_cols<R, R, N, -1, 0>), grid, dim3(C0::THREADS), 0, st, in, out, a.S,
+          HP_PASS_LAUNCH(a.tev, (k_cols<R, R, N, -1, 0>), grid, dim3(C0::THREADS), 0, st, in, out, a.S,
                              a.nfields, a.in_rs, a.out_rs, a.in_fs, a.out_fs, tw, a.skip, a.lam_ax,
                              a.lam_in, a.nodes, a.K, a.scale, a.store_mask, a.slab_need);
         else
-          hipLaunchKernelGGL((k_cols<R, R, N, +1, 0>), grid, dim3(C0::THREADS), 0, st, in, out, a.S,
+          HP_PASS_LAUNCH(a.tev, (k_cols<R, R, N, +1, 0>), grid, dim3(C0::THREADS), 0, st, in, out, a.S,
                              a.nfields, a.in_rs, a.out_rs, a.in_fs, a.out_fs, tw, a.skip, a.lam_ax,
                              a.lam_in, a.nodes, a.K, a.scale, a.store_mask, a.slab_need);
         return hipGetLastError();
@@ -995,19 +1008,19 @@ static void combine_launch(const CombineArgs& a, dim3 grid, hipStream_t st) {
   const dim3 block(C::THREADS * NS);
   switch (interp_mode(a)) {
     case kInterpLagrange:
-      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLagrange, NS>), grid, block, 0, st,
+      HP_PASS_LAUNCH(a.tev, (k_rows_combine<R, TO, N, ACC, kInterpLagrange, NS>), grid, block, 0, st,
                          (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
                          a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa,
                          a.Ma);
       break;
     case kInterpBilinear:
-      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpBilinear, NS>), grid, block, 0, st,
+      HP_PASS_LAUNCH(a.tev, (k_rows_combine<R, TO, N, ACC, kInterpBilinear, NS>), grid, block, 0, st,
                          (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
                          a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa,
                          a.Ma);
       break;
     default:
-      hipLaunchKernelGGL((k_rows_combine<R, TO, N, ACC, kInterpLinear, NS>), grid, block, 0, st,
+      HP_PASS_LAUNCH(a.tev, (k_rows_combine<R, TO, N, ACC, kInterpLinear, NS>), grid, block, 0, st,
                          (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.grpmask, a.rowmask, (cpx<TO>*)a.out,
                          a.out_rs, a.rows, a.K, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa,
                          a.Ma);
