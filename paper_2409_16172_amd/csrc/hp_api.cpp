@@ -1262,7 +1262,9 @@ struct Session {
     for (int r = 0; r < nrhs; ++r) {
       const bool ok = W->pinned[r] != 0;
       info[r].iters = hs[r].iters;
-      info[r].cycles = hs[r].cycles;
+      // the device counts a cycle when its start finds the tolerance unmet; the start
+      // that follows the last allowed cycle is counted there but never run
+      info[r].cycles = std::min(hs[r].cycles, o.max_cycles);
       info[r].rel_true_residual = o.side == HP_LEFT && !rhs_prec ? hs[r].relres_plain : hs[r].relres;
       info[r].rel_prec_residual = hs[r].relres;
       info[r].status = ok ? HP_OK : HP_E_NOT_CONVERGED;

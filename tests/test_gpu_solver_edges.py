@@ -1,0 +1,89 @@
+"""Degenerate and boundary cases of the GPU GMRES driver against the oracle: a zero
+right-hand side inside a batch, an initial guess that already solves the system, the
+shortest restart lengths, and a solve stopped by its cycle budget."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2409_16172_amd import inputs
+from tests.util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2409_16172_amd import binding
+    binding.load_library()
+    return binding
+
+
+def test_zero_rhs_in_batch(hp, dev):
+    print("[case] zero right-hand side in a batch of 3, 128^2", flush=True)
+    w = inputs.workload("2d_1024_grf", n=128, nrhs=3)
+    f = torch.from_numpy(w.f).to(dev)
+    f[1] = 0
+    plan = hp.plan_from_workload(w, max_nrhs=3)
+    x, info = plan.solve(f, rtol=1e-9)
+    # the zero right-hand side is solved by x = 0 before any step; the others as alone
+    assert info[1].status == hp.HP_OK and info[1].iters == 0 and info[1].rel_true_residual == 0.0
+    assert torch.count_nonzero(x[1]).item() == 0
+    for r in (0, 2):
+        x1, i1 = plan.solve(f[r:r + 1].contiguous(), rtol=1e-9)
+        assert i1[0].status == hp.HP_OK and i1[0].iters == info[r].iters and torch.equal(x1[0], x[r])
+
+
+def test_exact_initial_guess(orc, hp, dev):
+    print("[case] initial guess that solves the system, bump64", flush=True)
+    w = inputs.workload("2d_64_bump")
+    plan = hp.plan_from_workload(w)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    x, info = plan.solve(f, rtol=1e-10)
+    assert info[0].status == hp.HP_OK
+    x0 = x.clone()
+    x2, info2 = plan.solve(f, x0, rtol=1e-8)   # relative residual 1e-10 <= 1e-8 already
+    assert info2[0].status == hp.HP_OK and info2[0].iters == 0 and info2[0].cycles == 0
+    assert torch.equal(x2, x)
+    assert abs(info2[0].rel_true_residual - rel(ref.matvec(x.cpu().numpy()[0]), w.f[0])) < 1e-14
+
+
+@pytest.mark.parametrize("restart", [2, 3])
+def test_short_restarts_match_oracle(orc, hp, dev, restart):
+    print(f"[case] GMRES({restart}) bump64", flush=True)
+    w = inputs.workload("2d_64_bump")
+    plan = hp.plan_from_workload(w)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    x, info = plan.solve(f, rtol=1e-8, restart=restart, max_cycles=400)
+    xo, io = ref.gmres(w.f[0], rtol=1e-8, restart=restart, max_cycles=400)
+    true = rel(ref.matvec(x.cpu().numpy()[0]), w.f[0])
+    assert info[0].status == hp.HP_OK and io["status"] == 0
+    assert true <= 1e-8 * 1.001
+    assert abs(info[0].iters - io["iters"]) <= 2, (info[0].iters, io["iters"])
+
+
+def test_stagnating_gmres1_and_cycle_budget(orc, hp, dev):
+    """GMRES(1) stagnates on this problem; a solve stopped by max_cycles reports
+    not-converged with the residual the oracle reaches after the same steps."""
+    print("[case] GMRES(1) stagnation and max_cycles=1, bump64", flush=True)
+    w = inputs.workload("2d_64_bump")
+    plan = hp.plan_from_workload(w)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    for restart, cycles in ((1, 40), (30, 1)):
+        x, info = plan.solve(f, rtol=1e-8, restart=restart, max_cycles=cycles)
+        xo, io = ref.gmres(w.f[0], rtol=1e-8, restart=restart, max_cycles=cycles)
+        assert info[0].status == hp.HP_E_NOT_CONVERGED and io["status"] == 8, restart
+        assert info[0].iters == io["iters"] == restart * cycles and info[0].cycles == cycles
+        true = rel(ref.matvec(x.cpu().numpy()[0]), w.f[0])
+        assert abs(info[0].rel_true_residual - true) <= 1e-9 * true
+        assert abs(true - io["rel_true_residual"]) <= 1e-6 * io["rel_true_residual"], (restart, true, io)
+    with pytest.raises(hp.HelmpreError):
+        plan.solve(f, rtol=1e-8, restart=30, max_cycles=1, raise_on_fail=True)
