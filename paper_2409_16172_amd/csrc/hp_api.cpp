@@ -579,9 +579,9 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
       if ((m >> k) & 1ull) { need[(size_t)k * n0 + i0] = 1; P->slabs_used += 1.0; }
   }
   // store masks of the power-of-two symbol pass: bit e of thread j = axis-0 index
-  // j + Tb*e (mixed-radix lengths read `need` directly)
+  // j + Tb*e (the LDS-resident column kernels read `need` directly)
   std::vector<uint16_t> smask(1, 0);
-  if (hp::is_pow2_len(n0)) {
+  if (!hp::cols_use_gen(P->real_kind(), n0)) {
     const int Tb = hp::symbol_pass_line_threads(P->real_kind(), n0);
     const int Eb = n0 / Tb;
     smask.assign((size_t)P->K * Tb, 0);

@@ -77,6 +77,10 @@ constexpr int kGenOrders = 4;
 // Every mixed-radix kernel can take lines of length n.
 bool gen_length_ok(int n);
 inline bool is_pow2_len(int n) { return n > 0 && (n & (n - 1)) == 0; }
+// Column passes (strided axes) take the LDS-resident mixed-radix kernels for
+// lengths that are not powers of two, and for FP64 power-of-two lengths above
+// 2048, whose register-tile column kernel would not fit in LDS.
+bool cols_use_gen(int real_kind, int n);
 
 // Run-time choices of a transform pass (0 = the built-in choice): threads per line,
 // lines per workgroup (column passes) and radix schedule of the mixed-radix passes,

@@ -830,13 +830,16 @@ static bool make_col_plan(int n, int S, GenPlan* gp, const PassTune& t = PassTun
 
 bool combine_splits_ok(int real_kind, int n);   // pass C of this length can split its nodes
 
+bool cols_use_gen(int real_kind, int n) { return !is_pow2_len(n) || (real_kind == 0 && n > 2048); }
+
 int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, PassTune* out, int max) {
   int cnt = 0;
   auto push = [&](const PassTune& t) {
     if (cnt < max) out[cnt++] = t;
   };
-  if (is_pow2_len(n)) {   // compile-time tiles; the node groups of the symbol pass and the
-                          // node splits of pass C vary
+  if (kind == kTuneCols ? !cols_use_gen(real_kind, n) : is_pow2_len(n)) {
+    // compile-time tiles; the node groups of the symbol pass and the node splits
+    // of pass C vary
     if (kind == kTuneCols && mode == 1)
       for (int ng = 1; ng <= K && ng <= kMaxNodes; ng *= 2) push(PassTune{0, 0, 0, ng});
     if (kind == kTuneCombine && combine_splits_ok(real_kind, n)) {
@@ -992,7 +995,7 @@ struct ColsL {
 };
 
 hipError_t launch_cols(const ColsArgs& a, hipStream_t st) {
-  if (!is_pow2_len(a.n)) {
+  if (cols_use_gen(a.real_kind, a.n)) {
     GenPlan gp;
     if (a.real_kind == 0)
       return make_col_plan<double>(a.n, a.S, &gp, a.tune) ? cols_gen<double>(gp, a, st) : hipErrorInvalidValue;

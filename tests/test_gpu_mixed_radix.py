@@ -164,3 +164,25 @@ def test_long_restart_gmres_matches_oracle(orc, hp, dev):
         assert abs(info[0].iters - res["iters"]) <= max(2, res["iters"] // 50), (side, info[0].iters, res["iters"])
         if side == "none":
             assert res["iters"] > 64      # a full cycle of 64 steps and a second one
+
+
+@pytest.mark.parametrize("shape,precision", [((4096, 8), "fp64"), ((8, 4096), "fp64"), ((4096, 8), "mixed"),
+                                             ((8, 4096), "mixed"), ((2048, 16), "fp64"), ((8, 4096, 8), "fp64")])
+def test_longest_power_of_two_lines(orc, hp, dev, shape, precision):
+    """Power-of-two lines at the length limit in every role (strided axis 0, the 3-D middle
+    axis and the contiguous last axis), in both precisions, against the oracle.  FP64 columns
+    longer than 2048 take the LDS-resident kernels (the register-tile one would not fit)."""
+    _case("pow2_limit_apply", shape=shape, precision=precision)
+    c, zeta = _media(shape, 7 + sum(shape), False)
+    omega = 2 * np.pi * min(shape) / 4
+    a = np.full(shape, 0.05 * omega)
+    kw = dict(m_real=6, m_layer=3, a_floor=0.05 * omega)
+    plan = hp.Plan(shape, omega, c, a, zeta, precision=precision, **kw)
+    ref = orc.Problem(shape, omega, c, a, zeta, **kw)
+    v = _rand(shape, 4)
+    if precision == "fp64":
+        u = plan.apply(torch.from_numpy(v).to(dev)).cpu().numpy()
+        assert rel(u, ref.apply(v)) < 1e-12
+    else:
+        u = plan.apply(torch.from_numpy(v).to(dev).to(torch.complex64)).cpu().numpy()
+        assert rel(u, ref.apply(v.astype(np.complex64).astype(np.complex128))) < 1e-5
