@@ -192,7 +192,8 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info);
 /* u = Q_M v (Eqn. 403): one forward FFT of each field, K symbol multiplies and
  * inverse FFTs, and the pointwise combine with the piecewise-linear weights of
  * the local complex speed.  v, u: device, nrhs fields, complex128 for FP64
- * plans and complex64 for mixed plans.  u == v is allowed. */
+ * plans and complex64 for mixed plans.  u == v is allowed.  Any nrhs >= 0: the
+ * fields run in batches of at most the plan's max_nrhs, one after another. */
 hp_status hp_apply_precond(hp_plan p, const void* v, void* u, int nrhs, void* stream);
 
 /* y = P_N u: second-order centred differences of Eqn. 003 with periodic

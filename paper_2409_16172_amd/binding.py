@@ -177,7 +177,8 @@ class SolveInfo:
 class Plan:
     """Preconditioner plan: media, nodes, tables and workspace on the GPU.
 
-    shape: grid points per axis (2 or 3 axes, powers of two); length: side L.
+    shape: grid points per axis (2 or 3 axes; each an even product of 2, 3 and 5 from 8
+    to 4800, see hp_plan_create); length: side L.
     c, a, zeta: host arrays of that shape (a and zeta optional).
     precision: "fp64" (complex128 apply/matvec) or "mixed" (complex64 apply/matvec,
     FP64 orthogonalisation and residuals in solve).
@@ -261,12 +262,20 @@ class Plan:
             raise ValueError(f"{name} has shape {tuple(x.shape)}, grid is {self.shape}")
         return x.numel() // self.npts
 
+    def _same_count(self, nr, x, dtype, name):
+        """Check that the output/guess tensor x holds exactly nr fields (the library
+        writes nr fields into it)."""
+        n = self._fields(x, dtype, name)
+        if n != nr:
+            raise ValueError(f"{name} holds {n} fields, the input {nr}")
+        return n
+
     def apply(self, v, out=None, stream=None):
         """u = Q_M v for one field or a batch [nrhs, *shape]."""
         import torch
         nr = self._fields(v, self.field_dtype, "v")
         u = torch.empty_like(v) if out is None else out
-        self._fields(u, self.field_dtype, "out")
+        self._same_count(nr, u, self.field_dtype, "out")
         _check(load_library().hp_apply_precond(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()),
                                                nr, _stream(stream)), "hp_apply_precond")
         return u
@@ -276,7 +285,7 @@ class Plan:
         import torch
         nr = self._fields(u, self.field_dtype, "u")
         y = torch.empty_like(u) if out is None else out
-        self._fields(y, self.field_dtype, "out")
+        self._same_count(nr, y, self.field_dtype, "out")
         _check(load_library().hp_matvec(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(y.data_ptr()), nr,
                                         _stream(stream)), "hp_matvec")
         return y
@@ -289,7 +298,7 @@ class Plan:
         nr = self._fields(f, torch.complex128, "f")
         if x is None:
             x = torch.zeros_like(f)
-        self._fields(x, torch.complex128, "x")
+        self._same_count(nr, x, torch.complex128, "x")
         o = HpSolveOpts(int(restart), int(max_cycles), float(rtol), SIDES[side])
         infos = (HpSolveInfo * nr)()
         code = load_library().hp_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()), nr,
@@ -325,7 +334,7 @@ class Plan:
         y = np.ascontiguousarray(y, dtype=np.complex128)
         if out is None:
             out = torch.empty(self.shape, dtype=torch.complex128, device="cuda")
-        self._fields(out, torch.complex128, "out")
+        self._same_count(1, out, torch.complex128, "out")
         _check(load_library().hp_arnoldi_vector(self._h, C.c_void_p(y.ctypes.data), int(y.size),
                                                 C.c_void_p(out.data_ptr()), _stream(stream)), "hp_arnoldi_vector")
         return out
@@ -335,7 +344,8 @@ class Plan:
         """Eigenvalue of largest (or smallest) modulus of Q P_N / P_N Q / P_N by restarted
         Arnoldi; returns (lambda, relative residual, Arnoldi runs, converged)."""
         import torch
-        self._fields(v0, torch.complex128, "v0")
+        if self._fields(v0, torch.complex128, "v0") != 1:
+            raise ValueError("extreme_eigenvalue takes one field")
         lam = np.zeros(1, dtype=np.complex128)
         rr = C.c_double(0.0)
         runs = C.c_int(0)
@@ -361,6 +371,7 @@ class Plan:
         import torch
         nr = self._fields(v, self.field_dtype, "v")
         u = torch.empty_like(v) if out is None else out
+        self._same_count(nr, u, self.field_dtype, "out")
         ms = (C.c_double * 5)()
         by = (C.c_double * 5)()
         _check(load_library().hp_profile_apply(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()), nr,
@@ -414,7 +425,7 @@ class Solver:
             raise ValueError(f"f holds {nr} right-hand sides, solver was made for {self.nrhs}")
         if x is None:
             x = torch.zeros_like(f)
-        self.plan._fields(x, torch.complex128, "x")
+        self.plan._same_count(nr, x, torch.complex128, "x")
         self._keep = (f, x, stream)
         _check(load_library().hp_solver_start(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()),
                                               _stream(stream)), "hp_solver_start")

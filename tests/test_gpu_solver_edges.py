@@ -87,3 +87,30 @@ def test_stagnating_gmres1_and_cycle_budget(orc, hp, dev):
         assert abs(true - io["rel_true_residual"]) <= 1e-6 * io["rel_true_residual"], (restart, true, io)
     with pytest.raises(hp.HelmpreError):
         plan.solve(f, rtol=1e-8, restart=30, max_cycles=1, raise_on_fail=True)
+
+
+def test_binding_rejects_mismatched_tensors(hp, dev):
+    """The library writes as many fields as the input holds: an output or initial-guess
+    tensor with another count is refused before any call.  An apply of more fields than
+    max_nrhs runs in batches (the same values as one field at a time); solver options
+    out of range are refused by the library."""
+    w = inputs.workload("2d_64_bump")
+    plan = hp.plan_from_workload(w, max_nrhs=2)
+    two = torch.zeros((2,) + w.shape, dtype=torch.complex128, device=dev)
+    one = torch.zeros((1,) + w.shape, dtype=torch.complex128, device=dev)
+    for call in (lambda: plan.apply(two, out=one), lambda: plan.matvec(two, out=one),
+                 lambda: plan.solve(two, one), lambda: plan.profile_apply(two, out=one, reps=1),
+                 lambda: plan.arnoldi_vector([1.0], out=two)):
+        with pytest.raises(ValueError):
+            call()
+    with pytest.raises(TypeError):
+        plan.apply(two.to(torch.complex64))
+    rng = np.random.default_rng(1)
+    v3 = torch.from_numpy(rng.standard_normal((3,) + w.shape) + 0j).to(dev)
+    u3 = plan.apply(v3)
+    for r in range(3):
+        assert torch.equal(u3[r], plan.apply(v3[r:r + 1].contiguous())[0])
+    for kw in (dict(restart=0), dict(restart=65), dict(max_cycles=0), dict(rtol=0.0), dict(rtol=float("nan"))):
+        with pytest.raises(hp.HelmpreError) as e:
+            plan.solve(one, **kw)
+        assert e.value.code == hp.HP_E_INVALID, kw
