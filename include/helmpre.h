@@ -269,7 +269,10 @@ hp_status hp_extreme_eigenvalue(hp_plan p, const void* v0, int m, int side, int 
  *   hp_solver_create   allocate the workspace (nrhs <= the plan's max_nrhs)
  *   hp_solver_start    enqueue the start of a solve of f (x: initial guess,
  *                      overwritten by the solution); f, x stay owned by the
- *                      caller and must remain valid until the solve finishes
+ *                      caller and must remain valid until the solve finishes.
+ *                      A solve still in progress on the solver is abandoned
+ *                      (its enqueued work is waited for first).
+ *   (hp_solver_advance and hp_solver_wait before any start: HP_E_INVALID.)
  *   hp_solver_advance  enqueue at most max_steps further Arnoldi steps without
  *                      waiting for the device; *finished = 1 once the solve
  *                      has ended (converged or max_cycles)

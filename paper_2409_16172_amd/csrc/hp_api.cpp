@@ -1426,6 +1426,10 @@ hp_status hp_solver_create(hp_solver* out, hp_plan p, int nrhs, const hp_solve_o
 
 hp_status hp_solver_start(hp_solver s, const void* f, void* x, void* stream) {
   if (!s || !f || !x) return HP_E_INVALID;
+  // a solve still in progress is abandoned: its enqueued work uses the same
+  // workspace, so it has to drain first
+  if (s->sess.phase != Session::kIdle && s->sess.phase != Session::kFinished && s->sess.st)
+    HP_TRY(hipStreamSynchronize(s->sess.st));
   HP_TRY(s->sess.start((const cpx<double>*)f, (cpx<double>*)x, (hipStream_t)stream));
   return HP_OK;
 }

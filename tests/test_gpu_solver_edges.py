@@ -114,3 +114,38 @@ def test_binding_rejects_mismatched_tensors(hp, dev):
         with pytest.raises(hp.HelmpreError) as e:
             plan.solve(one, **kw)
         assert e.value.code == hp.HP_E_INVALID, kw
+
+
+def test_session_lifecycle(hp, dev):
+    """Solver sessions: no advance before a start, a session reused after its solve,
+    a solve abandoned by a new start, and a session closed mid-solve."""
+    print("[case] session lifecycle 128^2", flush=True)
+    w = inputs.workload("2d_1024_grf", n=128, nrhs=2)
+    plan = hp.plan_from_workload(w, max_nrhs=2)
+    f = torch.from_numpy(w.f).to(dev)
+    f0, f1 = f[0:1].contiguous(), f[1:2].contiguous()
+    x0, i0 = plan.solve(f0, rtol=1e-9)
+    x1, i1 = plan.solve(f1, rtol=1e-9)
+    s = hp.Solver(plan, rtol=1e-9)
+    with pytest.raises(hp.HelmpreError):
+        s.advance(1)
+    with pytest.raises(hp.HelmpreError):
+        s.result()
+    for fi, xe, ie in ((f0, x0, i0), (f1, x1, i1)):        # reuse after a finished solve
+        s.start(fi)
+        while not s.advance(3):
+            pass
+        x, info = s.result()
+        assert info[0].iters == ie[0].iters and torch.equal(x, xe)
+    s.start(f0)                                            # abandoned after a few steps
+    s.advance(5)
+    s.start(f1)
+    x, info = s.result()
+    assert info[0].iters == i1[0].iters and torch.equal(x, x1)
+    s.start(f0)
+    s.advance(4)
+    s.close()                                              # closed mid-solve
+    x, info = plan.solve(f0, rtol=1e-9)                    # the plan is unaffected
+    assert torch.equal(x, x0)
+    with pytest.raises(ValueError):                        # two fields for a one-field session
+        hp.Solver(plan, rtol=1e-9).start(f)
