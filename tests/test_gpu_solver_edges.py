@@ -149,3 +149,26 @@ def test_session_lifecycle(hp, dev):
     assert torch.equal(x, x0)
     with pytest.raises(ValueError):                        # two fields for a one-field session
         hp.Solver(plan, rtol=1e-9).start(f)
+
+
+@pytest.mark.parametrize("side", ["left", "none"])
+def test_mixed_precision_other_sides(orc, hp, dev, side):
+    """Mixed-precision plans on the left-preconditioned and plain systems: the reported true
+    residual is that of the returned x (oracle matvec), and the step count stays close to
+    the FP64 plan's (plain GMRES never touches Q, so it is the same solve)."""
+    print(f"[case] mixed precision side={side} inclusion36", flush=True)
+    w = inputs.workload("2d_inclusion", n=36, ppw=6.0)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    rtol = 1e-9 if side == "left" else 1e-6
+    p64 = hp.plan_from_workload(w)
+    p32 = hp.plan_from_workload(w, precision="mixed")
+    x64, i64 = p64.solve(f, rtol=rtol, restart=10, max_cycles=400, side=side)
+    x32, i32 = p32.solve(f, rtol=rtol, restart=10, max_cycles=400, side=side)
+    assert i64[0].status == i32[0].status == hp.HP_OK
+    true = rel(ref.matvec(x32.cpu().numpy()[0]), w.f[0])
+    assert abs(i32[0].rel_true_residual - true) <= 1e-6 * true + 1e-15
+    if side == "none":
+        assert i32[0].iters == i64[0].iters and torch.equal(x32, x64)
+    else:
+        assert abs(i32[0].iters - i64[0].iters) <= max(3, i64[0].iters // 10), (i32[0].iters, i64[0].iters)
