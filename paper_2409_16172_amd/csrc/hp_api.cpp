@@ -681,6 +681,17 @@ namespace {
 #endif
 constexpr unsigned kSolverEventFlags = HP_SOLVER_EVENT_FLAGS;
 
+// Right-preconditioned Arnoldi steps on grids of at most kFuseStencilMaxPts
+// points compute w = P_N z inside the dot-product sweep (HP_FUSE_STENCIL=0: always
+// a separate stencil pass).  Measured per FP64 solve: 256^2 5.06 -> 4.89 ms,
+// 512^2 4.20 -> 4.06 ms, 1024^2 11.61 -> 11.55 ms, but 2048^2 65.4 -> 66.5 ms
+// (there the sweep's staging of the neighbour rows costs more than the pass).
+#ifndef HP_FUSE_STENCIL
+#define HP_FUSE_STENCIL 1
+#endif
+constexpr bool kFuseStencil = HP_FUSE_STENCIL != 0;
+constexpr size_t kFuseStencilMaxPts = (size_t)1 << 20;
+
 // Pass timer: launches recorded per read at most (later ones are not timed).
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
@@ -859,8 +870,8 @@ void pass_bytes(const hp_plan_s* P, int nrhs, int in_bytes, int out_bytes, doubl
   b[4] = nr * (np * (8.0 + out_bytes) + P->rows_used * P->n[P->dim - 1] * sf);
 }
 
-hipError_t run_stencil(hp_plan_s* P, int kind, const void* u, size_t u_rs, void* y, size_t y_rs,
-                       const void* f, int nrhs, const int* skip, hipStream_t st) {
+hp::StencilArgs stencil_args(hp_plan_s* P, int kind, const void* u, size_t u_rs, void* y, size_t y_rs,
+                             const void* f, int nrhs, const int* skip) {
   hp::StencilArgs s{};
   s.kind = kind;
   s.dim = P->dim;
@@ -873,7 +884,12 @@ hipError_t run_stencil(hp_plan_s* P, int kind, const void* u, size_t u_rs, void*
   s.coef = (kind == 1 || kind == 2) ? P->coef32.p : P->coef64.p;
   s.nrhs = nrhs;
   s.skip = skip;
-  return hp::launch_stencil(s, st);
+  return s;
+}
+
+hipError_t run_stencil(hp_plan_s* P, int kind, const void* u, size_t u_rs, void* y, size_t y_rs,
+                       const void* f, int nrhs, const int* skip, hipStream_t st) {
+  return hp::launch_stencil(stencil_args(P, kind, u, u_rs, y, y_rs, f, nrhs, skip), st);
 }
 
 }  // namespace
@@ -1080,9 +1096,14 @@ struct Session {
       cpx<double>* pv = (cpx<double>*)W->tvec.p;
       if ((e = run_stencil(P, 0, vj, vrs, pv, np, nullptr, nrhs, K.skip_step, s)) != hipSuccess) return e;
       if ((e = run_apply(P, pv, 0, np, vj1, 0, vrs, false, nrhs, K.skip_step, s)) != hipSuccess) return e;
-    } else {                          // w = P_N Q u_j
+    } else {                          // w = P_N Q u_j, the stencil fused with the sweep
       if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, s)) != hipSuccess)
         return e;
+      if (kFuseStencil && np <= kFuseStencilMaxPts) {
+        const hp::StencilArgs sa = stencil_args(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step);
+        if ((e = hp::launch_arnoldi_dots_stencil(K, j, sa, s)) != hipSuccess) return e;
+        return hp::launch_arnoldi_update(K, j, s);
+      }
       if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, s)) != hipSuccess)
         return e;
     }

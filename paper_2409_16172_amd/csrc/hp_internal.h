@@ -196,6 +196,9 @@ hipError_t launch_scale_v0(const KrylovArgs& a, hipStream_t st);
 // Arnoldi step j (slot j holds u_j, slot j+1 holds w = A u_j): the one reduction
 // of the step (partial sums, then one block per right-hand side finishes it).
 hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st);
+// The same with w = P_N z computed by the sweep from s (s.u = z, kinds 0 and 2 of the
+// stencil, not the residual form) and stored in slot j+1.
+hipError_t launch_arnoldi_dots_stencil(const KrylovArgs& a, int j, const StencilArgs& s, hipStream_t st);
 // Arnoldi step j: slot j <- v_j, slot j+1 <- u_{j+1}.
 hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, hipStream_t st);
 hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);

@@ -1138,24 +1138,15 @@ int combine_group_rows(int real_kind, int n) {
 // (P u)(x) = gamma^2 sum_j (u(x+e_j) + u(x-e_j)) / h_j^2 + beta u(x),
 // beta = omega^2 + i omega a - 2 gamma^2 sum_j 1/h_j^2; periodic indices.
 // coef holds {gamma^2, beta} per point.
-template <typename R, typename TI, typename TO, int DIM, bool RESID>
-__global__ __launch_bounds__(256) void k_stencil(const cpx<TI>* __restrict__ u, cpx<TO>* __restrict__ y,
-                                                 const cpx<R>* __restrict__ coef,
-                                                 const cpx<double>* __restrict__ f, int n0, int n1,
-                                                 int n2, R ih0, R ih1, R ih2, size_t u_rs, size_t y_rs,
-                                                 const int* __restrict__ skip) {
-  const int rhs = blockIdx.y;
-  if (skip != nullptr && skip[rhs] != 0) return;
-  const size_t npts = (size_t)n0 * n1 * (DIM == 3 ? n2 : 1);
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= npts) return;
-  const cpx<TI>* ur = u + (size_t)rhs * u_rs;
+// (P u)(x_i) for one point i of one field ur (periodic neighbours of any length);
+// index arithmetic in 32 bits (every grid has fewer than 2^32 points): 64-bit
+// division is a long software sequence on the GPU.
+template <typename R, typename TI, int DIM>
+__device__ __forceinline__ cpx<R> stencil_point(const cpx<TI>* __restrict__ ur, const cpx<R>* __restrict__ coef,
+                                                size_t i, int n0, int n1, int n2, R ih0, R ih1, R ih2) {
   cpx<R> lap;
-  // periodic neighbours (any length)
   auto nxt = [](int k, int n) { return k + 1 == n ? 0 : k + 1; };
   auto prv = [](int k, int n) { return k == 0 ? n - 1 : k - 1; };
-  // index arithmetic in 32 bits (every grid has fewer than 2^32 points): 64-bit
-  // division is a long software sequence on the GPU
   const uint32_t i32 = (uint32_t)i;
   if constexpr (DIM == 2) {
     const int i1 = (int)(i32 % (uint32_t)n1), i0 = (int)(i32 / (uint32_t)n1);
@@ -1181,7 +1172,21 @@ __global__ __launch_bounds__(256) void k_stencil(const cpx<TI>* __restrict__ u, 
   }
   const cpx<R> g2 = coef[2 * i], be = coef[2 * i + 1];
   const cpx<R> uc = cvt<R>(ur[i]);
-  cpx<R> r = cadd(cmul(g2, lap), cmul(be, uc));
+  return cadd(cmul(g2, lap), cmul(be, uc));
+}
+
+template <typename R, typename TI, typename TO, int DIM, bool RESID>
+__global__ __launch_bounds__(256) void k_stencil(const cpx<TI>* __restrict__ u, cpx<TO>* __restrict__ y,
+                                                 const cpx<R>* __restrict__ coef,
+                                                 const cpx<double>* __restrict__ f, int n0, int n1,
+                                                 int n2, R ih0, R ih1, R ih2, size_t u_rs, size_t y_rs,
+                                                 const int* __restrict__ skip) {
+  const int rhs = blockIdx.y;
+  if (skip != nullptr && skip[rhs] != 0) return;
+  const size_t npts = (size_t)n0 * n1 * (DIM == 3 ? n2 : 1);
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npts) return;
+  const cpx<R> r = stencil_point<R, TI, DIM>(u + (size_t)rhs * u_rs, coef, i, n0, n1, n2, ih0, ih1, ih2);
   if constexpr (RESID) {
     const cpx<double> fv = f[(size_t)rhs * u_rs + i];
     y[(size_t)rhs * y_rs + i] = {(TO)(fv.re - (double)r.re), (TO)(fv.im - (double)r.im)};
@@ -1688,19 +1693,37 @@ constexpr int kDotsTile = 1024;
 constexpr int kDotsBatch = 8;
 constexpr int kDotsSlots = 8;   // basis vectors per wave: j <= NW * kDotsSlots
 
-template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __restrict__ V, size_t npts,
-                                                          size_t vrs, cpx<double>* __restrict__ part,
-                                                          const int* __restrict__ skip_step, int j) {
+// Where the sweep takes w = A u_j from: the stored vector (slot j+1), or, fused
+// with the right-preconditioned step, the stencil applied to z = Q u_j as each
+// tile is staged (w is then also stored in slot j+1 for the update kernel; the
+// separate stencil pass, its read of w and a launch are saved).
+struct WStored {
+  const cpx<double>* W;
+  __device__ __forceinline__ cpx<double> operator()(size_t p) const { return W[p]; }
+};
+template <typename R, typename TI, int DIM>
+struct WStencil {
+  const cpx<TI>* z;
+  const cpx<R>* coef;
+  cpx<double>* W;
+  int n0, n1, n2;
+  R ih0, ih1, ih2;
+  __device__ __forceinline__ cpx<double> operator()(size_t p) const {
+    const cpx<double> w = cvt<double>(stencil_point<R, TI, DIM>(z, coef, p, n0, n1, n2, ih0, ih1, ih2));
+    W[p] = w;
+    return w;
+  }
+};
+
+// The sweep of one block over its range of one right-hand side's basis Vr; pr:
+// this block's partial-sum column.
+template <int NW, typename WSrc>
+__device__ __forceinline__ void arnoldi_dots_body(const cpx<double>* Vr, size_t npts, cpx<double>* pr, int j,
+                                                  const WSrc& wsrc) {
   __shared__ cpx<double> su[kDotsTile], sw[kDotsTile];
   __shared__ double red[NW][6];
-  const int rhs = blockIdx.y;
-  if (skip_step[rhs]) return;
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const cpx<double>* Vr = V + (size_t)rhs * vrs;
   const cpx<double>* U = Vr + (size_t)j * npts;
-  const cpx<double>* W = Vr + (size_t)(j + 1) * npts;
-  cpx<double>* pr = part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x;
   const size_t range = (npts + kRedBlocks - 1) / kRedBlocks;
   const size_t r0 = (size_t)blockIdx.x * range;
   const size_t r1 = r0 + range < npts ? r0 + range : npts;
@@ -1711,7 +1734,7 @@ __global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __r
   for (size_t t0 = r0; t0 < r1; t0 += kDotsTile) {
     const int n = (int)(r1 - t0 < (size_t)kDotsTile ? r1 - t0 : kDotsTile);
     for (int i = threadIdx.x; i < n; i += NW * 64) {
-      const cpx<double> u = U[t0 + i], w = W[t0 + i];
+      const cpx<double> u = U[t0 + i], w = wsrc(t0 + i);
       su[i] = u;
       sw[i] = w;
       uu += u.re * u.re + u.im * u.im;
@@ -1778,6 +1801,32 @@ __global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __r
     pr[(size_t)(2 * j + 1) * kRedBlocks] = {s1, s2};
     pr[(size_t)(2 * j + 2) * kRedBlocks] = {s3, 0.0};
   }
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __restrict__ V, size_t npts,
+                                                          size_t vrs, cpx<double>* __restrict__ part,
+                                                          const int* __restrict__ skip_step, int j) {
+  const int rhs = blockIdx.y;
+  if (skip_step[rhs]) return;
+  const cpx<double>* Vr = V + (size_t)rhs * vrs;
+  arnoldi_dots_body<NW>(Vr, npts, part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x, j,
+                        WStored{Vr + (size_t)(j + 1) * npts});
+}
+
+template <int NW, typename R, typename TI, int DIM>
+__global__ __launch_bounds__(NW * 64) void k_arnoldi_dots_st(cpx<double>* V, size_t npts, size_t vrs,
+                                                             cpx<double>* __restrict__ part,
+                                                             const int* __restrict__ skip_step, int j,
+                                                             const cpx<TI>* __restrict__ z, size_t z_rs,
+                                                             const cpx<R>* __restrict__ coef, int n0, int n1,
+                                                             int n2, R ih0, R ih1, R ih2) {
+  const int rhs = blockIdx.y;
+  if (skip_step[rhs]) return;
+  cpx<double>* Vr = V + (size_t)rhs * vrs;
+  arnoldi_dots_body<NW>(Vr, npts, part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x, j,
+                        WStencil<R, TI, DIM>{z + (size_t)rhs * z_rs, coef, Vr + (size_t)(j + 1) * npts, n0, n1,
+                                             n2, ih0, ih1, ih2});
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_arnoldi_fin(const cpx<double>* __restrict__ part, int* __restrict__ skip_step,
@@ -2157,6 +2206,35 @@ hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st) {
                        a.part, (const int*)a.skip_step, j);
   else
     return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(kFinThreads), 0, st, (const cpx<double>*)a.part, a.skip_step,
+                     a.state, j, a.restart, a.host_stop);
+  return hipGetLastError();
+}
+
+template <int NW, typename R, typename TI, int DIM>
+static void dots_st_launch(const KrylovArgs& a, int j, const StencilArgs& s, hipStream_t st) {
+  hipLaunchKernelGGL((k_arnoldi_dots_st<NW, R, TI, DIM>), dim3(kRedBlocks, a.nrhs), dim3(NW * 64), 0, st, a.V,
+                     a.npts, a.vrs, a.part, (const int*)a.skip_step, j, (const cpx<TI>*)s.u, s.u_rs,
+                     (const cpx<R>*)s.coef, s.n[0], s.n[1], s.dim == 3 ? s.n[2] : 1, (R)s.ih2[0], (R)s.ih2[1],
+                     (R)s.ih2[2]);
+}
+
+template <int NW>
+static hipError_t dots_st_dispatch(const KrylovArgs& a, int j, const StencilArgs& s, hipStream_t st) {
+  if (s.kind == 0 && s.dim == 2) dots_st_launch<NW, double, double, 2>(a, j, s, st);
+  else if (s.kind == 0 && s.dim == 3) dots_st_launch<NW, double, double, 3>(a, j, s, st);
+  else if (s.kind == 2 && s.dim == 2) dots_st_launch<NW, float, float, 2>(a, j, s, st);
+  else if (s.kind == 2 && s.dim == 3) dots_st_launch<NW, float, float, 3>(a, j, s, st);
+  else return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
+hipError_t launch_arnoldi_dots_stencil(const KrylovArgs& a, int j, const StencilArgs& s, hipStream_t st) {
+  hipError_t e;
+  if (kRedBlocks >= 512 && j <= 4 * kDotsSlots) e = dots_st_dispatch<4>(a, j, s, st);
+  else if (j <= 8 * kDotsSlots) e = dots_st_dispatch<8>(a, j, s, st);
+  else return hipErrorInvalidValue;
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(kFinThreads), 0, st, (const cpx<double>*)a.part, a.skip_step,
                      a.state, j, a.restart, a.host_stop);
   return hipGetLastError();

@@ -172,3 +172,20 @@ def test_mixed_precision_other_sides(orc, hp, dev, side):
         assert i32[0].iters == i64[0].iters and torch.equal(x32, x64)
     else:
         assert abs(i32[0].iters - i64[0].iters) <= max(3, i64[0].iters // 10), (i32[0].iters, i64[0].iters)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_grid_solve_separate_stencil(orc, hp, dev, precision):
+    """Grids above 2^20 points keep the separate stencil pass in the Arnoldi step (smaller
+    ones compute w inside the dot-product sweep, which every other solve test covers): the
+    2048^2 workload in both precisions meets rtol in the oracle's own residual."""
+    print(f"[case] 2048^2 solve {precision}", flush=True)
+    w = inputs.workload("2d_2048_grf")
+    plan = hp.plan_from_workload(w, precision=precision)
+    ref = orc.from_workload(w)
+    f = torch.from_numpy(w.f).to(dev)
+    x, info = plan.solve(f, rtol=1e-8)
+    true = rel(ref.matvec(x.cpu().numpy()[0]), w.f[0])
+    assert info[0].status == hp.HP_OK and true <= 1e-8 * 1.001, (info[0], true)
+    assert abs(info[0].rel_true_residual - true) <= 1e-6 * true
+    assert 30 <= info[0].iters <= 50
