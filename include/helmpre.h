@@ -42,7 +42,7 @@ typedef enum {
   HP_E_SHAPE = 2,          /* grid size not supported                                 */
   HP_E_MEDIA = 3,          /* media not finite / not positive, or a zero symbol denominator */
   HP_E_LAYER = 4,          /* c differs from the background c0 where zeta > 0        */
-  HP_E_NONFINITE = 5,      /* non-finite right-hand side                              */
+  HP_E_NONFINITE = 5,      /* non-finite right-hand side or residual (that one stops)  */
   HP_E_DEVICE = 6,         /* a HIP call failed                                       */
   HP_E_NOMEM = 7,          /* device allocation failed                                */
   HP_E_NOT_CONVERGED = 8   /* solve stopped at max_cycles above the tolerance         */
@@ -208,7 +208,9 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
  * info: host array of nrhs entries.  Blocks until every right-hand side has
  * converged or max_cycles is reached.  Krylov storage is allocated on first
  * use and kept by the plan.  Returns HP_E_NOT_CONVERGED if any right-hand side
- * stopped above rtol (x and info are filled in any case).
+ * stopped above rtol, HP_E_NONFINITE if any had a non-finite norm or residual
+ * (that one stops at once, x as it was; the others are solved); x and info are
+ * filled in either case, info[r].status giving each right-hand side's outcome.
  * With the environment variable HP_STEP_GRAPHS=1, grids of fewer than 2^18 points
  * (times nrhs) run each Arnoldi step as a HIP graph captured once per step index
  * and solver configuration (also in hp_solver sessions); results are bitwise those

@@ -303,7 +303,8 @@ class Plan:
         infos = (HpSolveInfo * nr)()
         code = load_library().hp_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()), nr,
                                        C.byref(o), infos, _stream(stream))
-        if code not in (HP_OK, HP_E_NOT_CONVERGED) or (raise_on_fail and code != HP_OK):
+        # per right-hand-side outcomes (not converged, non-finite) are in the infos
+        if code not in (HP_OK, HP_E_NOT_CONVERGED, HP_E_NONFINITE) or (raise_on_fail and code != HP_OK):
             raise HelmpreError(code, "hp_solve")
         return x, [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status, i.rel_prec_residual) for i in infos]
 
@@ -439,7 +440,7 @@ class Solver:
     def result(self):
         infos = (HpSolveInfo * self.nrhs)()
         code = load_library().hp_solver_wait(self._h, infos)
-        if code not in (HP_OK, HP_E_NOT_CONVERGED):
+        if code not in (HP_OK, HP_E_NOT_CONVERGED, HP_E_NONFINITE):
             raise HelmpreError(code, "hp_solver_wait")
         return self._keep[1], [SolveInfo(i.iters, i.cycles, i.rel_true_residual, i.status, i.rel_prec_residual) for i in infos]
 

@@ -1288,8 +1288,13 @@ struct Session {
       info[r].cycles = std::min(hs[r].cycles, o.max_cycles);
       info[r].rel_true_residual = o.side == HP_LEFT && !rhs_prec ? hs[r].relres_plain : hs[r].relres;
       info[r].rel_prec_residual = hs[r].relres;
+      if (!std::isfinite(hs[r].relres)) {   // a non-finite right-hand side or residual
+        info[r].status = HP_E_NONFINITE;
+        ret = HP_E_NONFINITE;
+        continue;
+      }
       info[r].status = ok ? HP_OK : HP_E_NOT_CONVERGED;
-      if (!ok) ret = HP_E_NOT_CONVERGED;
+      if (!ok && ret == HP_OK) ret = HP_E_NOT_CONVERGED;
     }
     return ret;
   }
@@ -1414,8 +1419,8 @@ hp_status hp_solve(hp_plan p, const void* f, void* x, int nrhs, const hp_solve_o
     const int nr = std::min(p->max_nrhs, nrhs - r0);
     hp_status s = solve_batch(p, (const cpx<double>*)f + (size_t)r0 * p->npts, (cpx<double>*)x + (size_t)r0 * p->npts,
                               nr, *opts, info + r0, st);
-    if (s != HP_OK && s != HP_E_NOT_CONVERGED) return s;
-    if (s == HP_E_NOT_CONVERGED) ret = s;
+    if (s != HP_OK && s != HP_E_NOT_CONVERGED && s != HP_E_NONFINITE) return s;
+    if (s == HP_E_NONFINITE || (s == HP_E_NOT_CONVERGED && ret == HP_OK)) ret = s;
   }
   return ret;
 }

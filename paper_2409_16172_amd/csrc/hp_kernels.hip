@@ -1412,8 +1412,10 @@ __device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs
     S.target = c.rtol * S.fnorm;
     S.iters = 0;
     S.cycles = 0;
-    S.relres = S.fnorm > 0.0 ? 1.0 : 0.0;
-    c.done[rhs] = S.fnorm > 0.0 ? 0 : 1;
+    // a non-finite right-hand side stops at once, its residual marked NaN
+    const bool finite = isfinite(S.fnorm);
+    S.relres = !finite ? __builtin_nan("") : S.fnorm > 0.0 ? 1.0 : 0.0;
+    c.done[rhs] = finite && S.fnorm > 0.0 ? 0 : 1;
     c.skip_step[rhs] = c.done[rhs];
     publish_stop(c.host_stop, rhs, c.skip_step[rhs]);
     publish_stop(c.host_done, rhs, c.done[rhs]);
@@ -1426,7 +1428,11 @@ __device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs
     S.beta = beta;
     S.relres = S.fnorm > 0.0 ? beta / S.fnorm : 0.0;
     S.stop_at = -1;
-    if (S.relres <= c.rtol || beta == 0.0) {
+    if (!isfinite(beta)) {               // a non-finite residual (e.g. from the initial guess)
+      S.relres = __builtin_nan("");
+      c.done[rhs] = 1;
+      c.skip_step[rhs] = 1;
+    } else if (S.relres <= c.rtol || beta == 0.0) {
       c.done[rhs] = 1;
       c.skip_step[rhs] = 1;
     } else {

@@ -189,3 +189,33 @@ def test_large_grid_solve_separate_stencil(orc, hp, dev, precision):
     assert info[0].status == hp.HP_OK and true <= 1e-8 * 1.001, (info[0], true)
     assert abs(info[0].rel_true_residual - true) <= 1e-6 * true
     assert 30 <= info[0].iters <= 50
+
+
+def test_nonfinite_right_hand_side_and_guess(hp, dev):
+    """A right-hand side with a NaN stops at once with HP_E_NONFINITE (x untouched) while the
+    others of the batch are solved as alone; a NaN in the initial guess does the same at the
+    first cycle start."""
+    print("[case] non-finite right-hand side in a batch of 3, 128^2", flush=True)
+    w = inputs.workload("2d_1024_grf", n=128, nrhs=3)
+    plan = hp.plan_from_workload(w, max_nrhs=3)
+    f = torch.from_numpy(w.f).to(dev)
+    f[1, 5, 7] = float("nan")
+    x, info = plan.solve(f, rtol=1e-9)
+    assert info[1].status == hp.HP_E_NONFINITE and info[1].iters == 0
+    assert torch.count_nonzero(x[1]).item() == 0
+    for r in (0, 2):
+        x1, i1 = plan.solve(f[r:r + 1].contiguous(), rtol=1e-9)
+        assert info[r].status == hp.HP_OK and i1[0].iters == info[r].iters and torch.equal(x1[0], x[r])
+    with pytest.raises(hp.HelmpreError) as e:
+        plan.solve(f, rtol=1e-9, raise_on_fail=True)
+    assert e.value.code == hp.HP_E_NONFINITE
+    g = f[0:1].contiguous()
+    x0 = torch.zeros_like(g)
+    x0[0, 3, 3] = float("inf")
+    x2, i2 = plan.solve(g, x0, rtol=1e-9)
+    assert i2[0].status == hp.HP_E_NONFINITE and i2[0].iters == 0
+    s = hp.Solver(plan, rtol=1e-9)                      # sessions report it the same way
+    s.start(f[1:2].contiguous())
+    _, i3 = s.result()
+    assert i3[0].status == hp.HP_E_NONFINITE
+    s.close()
