@@ -73,8 +73,13 @@ typedef struct {
  *   nodes_real optional explicit increasing real nodes (host, m_real values)
  *   nodes_zeta optional explicit increasing layer nodes (host, m_layer values > 0)
  *   a_nodes    optional damping a(c_m) at the real nodes (host, m_real values)
- *   a_floor    lower bound applied to the symbol damping of real nodes (the
- *              operator P_N keeps the true a); 0 disables it
+ *   a_floor    lower bound on the symbol damping of every node whose speed
+ *              is real (Im gamma_n = 0: the real-axis nodes, and the bivariate
+ *              and layer-tensor nodes with zero imaginary part), where a = 0
+ *              would put zeros of the symbol denominator on the grid (Section
+ *              3 assumes a_min > 0).  Nodes with Im gamma_n < 0 (layer nodes)
+ *              keep the damping of c0 unfloored.  The operator P_N keeps the
+ *              true a.  0 disables it
  *   symbol     HP_SYMBOL_CONTINUOUS: |xi|^2 as in Eqn. 021;
  *              HP_SYMBOL_DISCRETE: the 5/7-point stencil's own symbol
  *   precision  HP_FP64, or HP_MIXED (FFTs, symbol multiply, combine and the

@@ -398,6 +398,17 @@ static void point_weights_at(const or_problem* p, const or_setup_t* s, long i, d
     else or_point_weights(s, p->c0, p->c[i], p->zeta ? p->zeta[i] : 0.0, w);
 }
 
+/* The floor a_floor on the symbol damping (reading of the standing assumption
+ * a_min > 0 of Section 3, needed where a = 0): it applies to the nodes whose
+ * speed is real, Im gamma_n = 0, whose symbol would otherwise vanish at
+ * |xi| = omega / c_n.  Nodes with Im gamma_n < 0 (the absorbing layer) keep
+ * their damping: their denominator has imaginary part 2 Re(gamma_n) |Im gamma_n|
+ * |xi|^2 > 0 away from xi = 0.  P_N always keeps the true a. */
+static void floor_real_nodes(const or_problem* p, or_setup_t* s) {
+    for (int n = 0; n < s->K; ++n)
+        if (s->gim[n] == 0.0 && s->ahat[n] < p->a_floor) s->ahat[n] = p->a_floor;
+}
+
 /* Set up nodes, per-node damping and per-node complex speed. */
 int or_setup(const or_problem* p, or_setup_t* s) {
     memset(s, 0, sizeof(*s));
@@ -467,8 +478,9 @@ int or_setup(const or_problem* p, or_setup_t* s) {
                 int n = m + s->M * r;
                 s->gre[n] = s->cnode[m];
                 s->gim[n] = s->anode[r];
-                s->ahat[n] = ahat[m] < p->a_floor ? p->a_floor : ahat[m];
+                s->ahat[n] = ahat[m];
             }
+        floor_real_nodes(p, s);
         return OR_OK;
     }
     int rc = real_nodes(p, s, has_layer);
@@ -506,15 +518,17 @@ int or_setup(const or_problem* p, or_setup_t* s) {
                 int n = m + s->M * r;
                 s->gre[n] = s->cnode[m];
                 s->gim[n] = 0.0;
-                s->ahat[n] = s->anode[r] < p->a_floor ? p->a_floor : s->anode[r];
+                s->ahat[n] = s->anode[r];
             }
+        floor_real_nodes(p, s);
         return OR_OK;
     }
 
     /* Symbol damping per real node: the symbol depends on x only through c,
      * so a must be a function of c (Section 4).  Uniform a is used as is;
      * given a(c_m) is used as given; otherwise the hat-weighted mean of a
-     * over the points each real node serves.  Floored by a_floor. */
+     * over the points each real node serves.  Layer nodes take the damping
+     * of c_o (before any floor). */
     int uniform = 1;
     double a0 = p->a ? p->a[0] : 0.0;
     if (p->a) for (long i = 1; i < np; ++i) if (p->a[i] != a0) { uniform = 0; break; }
@@ -531,13 +545,13 @@ int or_setup(const or_problem* p, or_setup_t* s) {
         mean /= (double)np;
         for (int m = 0; m < s->M; ++m) s->ahat[m] = den[m] > 0 ? num[m] / den[m] : mean;
     }
-    for (int m = 0; m < s->M; ++m) if (s->ahat[m] < p->a_floor) s->ahat[m] = p->a_floor;
     for (int m = 0; m < s->M; ++m) { s->gre[m] = s->cnode[m]; s->gim[m] = 0.0; }
     for (int j = 1; j <= s->Mt; ++j) {
         s->ahat[s->M + j - 1] = s->ahat[s->mo];
         s->gre[s->M + j - 1] = p->c0;                  /* gamma = c_o (1 - i zeta_j) */
         s->gim[s->M + j - 1] = -p->c0 * s->znode[j];
     }
+    floor_real_nodes(p, s);
     /* Per-point check of the layer assumption: c = c_o where zeta > 0. */
     if (has_layer)
         for (long i = 0; i < np; ++i)
@@ -629,7 +643,7 @@ int or_exact_psdo(const or_problem* p, const cx* v, cx* u) {
         unravel(p, i, ix);
         cx gam = p->c[i] * (1.0 - I * (p->zeta ? p->zeta[i] : 0.0));
         double ai = p->a ? p->a[i] : 0.0;
-        if (ai < p->a_floor) ai = p->a_floor;
+        if (cimag(gam) == 0.0 && ai < p->a_floor) ai = p->a_floor;   /* floored where the speed is real */
         cx acc = 0;
         for (long k = 0; k < np; ++k) {
             unravel(p, k, ik);

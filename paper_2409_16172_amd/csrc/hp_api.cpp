@@ -488,7 +488,8 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     return failc(from_hip(e));
 
   // symbol damping per node: uniform a as is, a(c_m) if given, otherwise the
-  // weight-averaged a over the points each real node serves; floored.
+  // weight-averaged a over the points each real node serves; layer nodes take
+  // the damping of c_o.  The floor applies at the end to the nodes of real speed.
   const double a0 = a ? a[0] : 0.0;
   for (int m = 0; m < P->M; ++m) P->ahat[m] = a0;
   if (opts->a_nodes) {
@@ -513,7 +514,6 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     mean /= (double)np;
     for (int m = 0; m < P->M; ++m) P->ahat[m] = den[m] > 0 ? num[m] / den[m] : mean;
   }
-  for (int m = 0; m < P->M; ++m) P->ahat[m] = std::max(P->ahat[m], opts->a_floor);
   for (int m = 0; m < P->M; ++m) { P->gre[m] = P->cnode[m]; P->gim[m] = 0; }
   if (P->tensor) {   // layer tensor: node m + M r carries gamma = c_m + i g_r and the damping of c_m
     for (int r = P->Ma - 1; r >= 0; --r)
@@ -527,7 +527,7 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
       for (int m = 0; m < P->M; ++m) {
         P->gre[m + P->M * r] = P->cnode[m];
         P->gim[m + P->M * r] = 0;
-        P->ahat[m + P->M * r] = std::max(P->anode[r], opts->a_floor);
+        P->ahat[m + P->M * r] = P->anode[r];
       }
   }
   for (int j = 1; j <= P->Mt; ++j) {
@@ -535,6 +535,11 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     P->gre[P->M + j - 1] = c0;
     P->gim[P->M + j - 1] = -c0 * P->znode[j];
   }
+  // Floor (the standing assumption a_min > 0 of Section 3 where a = 0): only
+  // nodes of real speed can have a vanishing symbol denominator, at |xi| =
+  // omega / c_n; a node with Im gamma_n < 0 keeps its damping.
+  for (int k = 0; k < P->K; ++k)
+    if (P->gim[k] == 0.0) P->ahat[k] = std::max(P->ahat[k], opts->a_floor);
 
   // symbol constants and tables
   std::vector<hp::NodeConst> nc(P->K);
