@@ -214,7 +214,10 @@ hp_status hp_matvec(hp_plan p, const void* u, void* y, int nrhs, void* stream);
  * converged or max_cycles is reached.  Krylov storage is allocated on first
  * use and kept by the plan.  Returns HP_E_NOT_CONVERGED if any right-hand side
  * stopped above rtol, HP_E_NONFINITE if any had a non-finite norm or residual
- * (that one stops at once, x as it was; the others are solved); x and info are
+ * (that one stops where the value is found: a non-finite f or initial residual
+ * leaves x as it was; a residual that turns non-finite during the solve stops
+ * it at that restart, x holding the update made so far, and its residuals are
+ * reported as NaN; the others are solved); x and info are
  * filled in either case, info[r].status giving each right-hand side's outcome.
  * With the environment variable HP_STEP_GRAPHS=1, grids of fewer than 2^18 points
  * (times nrhs) run each Arnoldi step as a HIP graph captured once per step index
@@ -284,7 +287,9 @@ hp_status hp_extreme_eigenvalue(hp_plan p, const void* v0, int m, int side, int 
  *                      waiting for the device; *finished = 1 once the solve
  *                      has ended (converged or max_cycles)
  *   hp_solver_wait     block until the solve ends; fills info[nrhs]; returns
- *                      HP_E_NOT_CONVERGED if a right-hand side stopped above rtol
+ *                      HP_E_NOT_CONVERGED if a right-hand side stopped above rtol,
+ *                      HP_E_NONFINITE if one met a non-finite norm or residual
+ *                      (as hp_solve; info[r].status tells which)
  * A plan's preconditioner workspace is shared by everything that runs on it:
  * solvers of one plan must not progress concurrently on different streams. */
 typedef struct hp_solver_s* hp_solver;

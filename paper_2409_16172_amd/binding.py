@@ -165,6 +165,22 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _order_on(stream, *tensors):
+    """Work the library enqueues on `stream` must see what the caller's current stream
+    wrote to its tensors (an initial guess zeroed there, a right-hand side produced
+    there): make `stream` wait for the current stream, and tell the caching allocator
+    that the tensors are in use on `stream`."""
+    import torch
+    if stream is None:
+        return
+    cur = torch.cuda.current_stream(stream.device)
+    if stream.cuda_stream == cur.cuda_stream:
+        return
+    stream.wait_stream(cur)
+    for t in tensors:
+        t.record_stream(stream)
+
+
 @dataclass
 class SolveInfo:
     iters: int
@@ -276,6 +292,7 @@ class Plan:
         nr = self._fields(v, self.field_dtype, "v")
         u = torch.empty_like(v) if out is None else out
         self._same_count(nr, u, self.field_dtype, "out")
+        _order_on(stream, v, u)
         _check(load_library().hp_apply_precond(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()),
                                                nr, _stream(stream)), "hp_apply_precond")
         return u
@@ -286,6 +303,7 @@ class Plan:
         nr = self._fields(u, self.field_dtype, "u")
         y = torch.empty_like(u) if out is None else out
         self._same_count(nr, y, self.field_dtype, "out")
+        _order_on(stream, u, y)
         _check(load_library().hp_matvec(self._h, C.c_void_p(u.data_ptr()), C.c_void_p(y.data_ptr()), nr,
                                         _stream(stream)), "hp_matvec")
         return y
@@ -299,6 +317,7 @@ class Plan:
         if x is None:
             x = torch.zeros_like(f)
         self._same_count(nr, x, torch.complex128, "x")
+        _order_on(stream, f, x)
         o = HpSolveOpts(int(restart), int(max_cycles), float(rtol), SIDES[side])
         infos = (HpSolveInfo * nr)()
         code = load_library().hp_solve(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()), nr,
@@ -427,6 +446,7 @@ class Solver:
         if x is None:
             x = torch.zeros_like(f)
         self.plan._same_count(nr, x, torch.complex128, "x")
+        _order_on(stream, f, x)
         self._keep = (f, x, stream)
         _check(load_library().hp_solver_start(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()),
                                               _stream(stream)), "hp_solver_start")

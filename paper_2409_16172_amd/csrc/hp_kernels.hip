@@ -1421,8 +1421,13 @@ __device__ void dots_finalize(const DotsCtl& c, const cpx<double>* part, int rhs
     publish_stop(c.host_done, rhs, c.done[rhs]);
   } else if (c.mode == kDotsPlain) {     // unpreconditioned norms of a left-preconditioned solve
     const double nrm = sqrt(sums[0].re);
-    if (c.j == 0) S.fnorm_plain = nrm;
-    else S.relres_plain = S.fnorm_plain > 0.0 ? nrm / S.fnorm_plain : 0.0;
+    if (c.j == 0) {
+      S.fnorm_plain = nrm;
+    } else {
+      // a non-finite norm on either side propagates as NaN (never reads as converged)
+      const double fp = S.fnorm_plain;
+      S.relres_plain = !(isfinite(fp) && isfinite(nrm)) ? __builtin_nan("") : fp > 0.0 ? nrm / fp : 0.0;
+    }
   } else if (c.mode == kDotsCycle) {     // cycle start: beta = ||r||, residual test
     const double beta = sqrt(sums[0].re);
     S.beta = beta;

@@ -219,3 +219,12 @@ def test_nonfinite_right_hand_side_and_guess(hp, dev):
     _, i3 = s.result()
     assert i3[0].status == hp.HP_E_NONFINITE
     s.close()
+    # left preconditioning: the residual of the plain system is reported as NaN, never as
+    # a value that would pass a tolerance check
+    print("[case] non-finite right-hand side, left preconditioning", flush=True)
+    xl, il = plan.solve(f, rtol=1e-9, side="left")
+    assert il[1].status == hp.HP_E_NONFINITE and il[1].iters == 0
+    assert not (il[1].rel_true_residual <= 1e-9) and not (il[1].rel_prec_residual <= 1e-9), il[1]
+    assert torch.count_nonzero(xl[1]).item() == 0
+    for r in (0, 2):
+        assert il[r].status == hp.HP_OK and il[r].rel_prec_residual <= 1e-9
