@@ -201,6 +201,23 @@ hp_status hp_plan_query(hp_plan p, hp_plan_info* info);
  * fields run in batches of at most the plan's max_nrhs, one after another. */
 hp_status hp_apply_precond(hp_plan p, const void* v, void* u, int nrhs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): u = Q_M v exactly as
+ * hp_apply_precond computes it (same kernels, bitwise the same result), but with
+ * the intermediate spectrum and the K node fields in a static device array of
+ * HP_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on until
+ * the process ends, instead of the plan's workspace.  Calls no hipMalloc,
+ * hipFree or other allocating routine.  One field needs (1 + K) N^d S bytes of it
+ * (S = 16 for FP64 plans, 8 for mixed), rounded up to 256 between the two parts;
+ * a batch runs in chunks of as many fields as fit.  Returns HP_E_INVALID, with
+ * the sizes in hp_last_error(), when one field does not fit.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads, other plans) race and must be serialised by the caller.
+ * Nothing needs clearing between calls: every part of the array a call reads
+ * was written earlier in the same call. */
+#define HP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+hp_status hp_apply_precond_static(hp_plan p, const void* v, void* u, int nrhs, void* stream);
+
 /* y = P_N u: second-order centred differences of Eqn. 003 with periodic
  * boundaries, gamma^2 in place of c^2 (Section 4.4, Section 5).  Same dtypes as
  * apply.  y must not alias u. */

@@ -27,7 +27,7 @@ EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_byt
             "hp_status_str", "hp_last_error", "hp_solver_create", "hp_solver_start", "hp_solver_advance",
             "hp_solver_wait", "hp_solver_destroy", "hp_arnoldi", "hp_ritz_values",
             "hp_arnoldi_vector", "hp_extreme_eigenvalue", "hp_plan_autotune", "hp_plan_time_pass",
-            "hp_plan_pass_times"]
+            "hp_plan_pass_times", "hp_apply_precond_static"]
 
 
 class HpGrid(C.Structure):
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.hp_plan_query.restype = i
     lib.hp_apply_precond.argtypes = [vp, vp, vp, i, vp]
     lib.hp_apply_precond.restype = i
+    lib.hp_apply_precond_static.argtypes = [vp, vp, vp, i, vp]
+    lib.hp_apply_precond_static.restype = i
     lib.hp_matvec.argtypes = [vp, vp, vp, i, vp]
     lib.hp_matvec.restype = i
     lib.hp_solve.argtypes = [vp, vp, vp, i, C.POINTER(HpSolveOpts), C.POINTER(HpSolveInfo), vp]
@@ -295,6 +297,23 @@ class Plan:
         _order_on(stream, v, u)
         _check(load_library().hp_apply_precond(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()),
                                                nr, _stream(stream)), "hp_apply_precond")
+        return u
+
+    def apply_static(self, v, out=None, stream=None):
+        """u = Q_M v through hp_apply_precond_static: the library's static device workspace
+        (HP_STATIC_SCRATCH_BYTES per GPU) instead of the plan's; the C call allocates
+        nothing (pass `out` to allocate nothing here either).  Calls on one GPU must not
+        overlap."""
+        import torch
+        nr = self._fields(v, self.field_dtype, "v")
+        u = torch.empty_like(v) if out is None else out
+        self._same_count(nr, u, self.field_dtype, "out")
+        _order_on(stream, v, u)
+        lib = load_library()
+        code = lib.hp_apply_precond_static(self._h, C.c_void_p(v.data_ptr()), C.c_void_p(u.data_ptr()), nr,
+                                           _stream(stream))
+        if code != HP_OK:   # the sizes of a refused call are in hp_last_error
+            raise HelmpreError(code, "hp_apply_precond_static: " + lib.hp_last_error().decode())
         return u
 
     def matvec(self, u, out=None, stream=None):

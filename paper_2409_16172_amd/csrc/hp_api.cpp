@@ -718,10 +718,19 @@ hipError_t timer_events(hp_plan_s* P, hipStream_t st, const hipEvent_t** tev) {
   return hipSuccess;
 }
 
+// Where an apply keeps its intermediate spectrum t and its K node fields: the
+// plan's workspace, or (hp_apply_precond_static) the static device array.
+struct ApplyWs {
+  void* t;
+  void* fields;
+};
+
 hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, void* u, int out_kind,
                      size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st,
-                     hipEvent_t* ev = nullptr, int reps = 1) {
+                     hipEvent_t* ev = nullptr, int reps = 1, const ApplyWs* ws = nullptr) {
   const int rk = P->real_kind();
+  void* const wt = ws ? ws->t : P->t.p;
+  void* const wf = ws ? ws->fields : P->fields.p;
   const size_t np = P->npts;
   hipError_t e;
   const int nl = P->n[P->dim - 1];
@@ -733,7 +742,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   // launch of pass `slot`, with the timer's events when that pass is timed
   auto timed = [&](int slot, auto&& launch) -> hipError_t {
     const hipEvent_t* tev = nullptr;
-    if (P->timer_slot == slot) {
+    if (P->timer_slot == slot && ws == nullptr) {   // the static-workspace path creates no events
       hipError_t e2 = timer_events(P, st, &tev);
       if (e2 != hipSuccess) return e2;
     }
@@ -742,7 +751,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   if ((e = mark(0)) != hipSuccess) return e;
   for (int r = 0; r < reps; ++r) {
     e = timed(0, [&](const hipEvent_t* tev) {
-      return hp::launch_rows_fwd(rk, in_kind, nl, v, P->t.p, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip,
+      return hp::launch_rows_fwd(rk, in_kind, nl, v, wt, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip,
                                  P->tune[0], st, tev);
     });
     if (e != hipSuccess) return e;
@@ -751,7 +760,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   if (P->dim == 3) {   // forward along the middle axis, in place
     hp::ColsArgs m{};
     m.real_kind = rk; m.n = P->n[1]; m.dir = -1; m.mode = 0;
-    m.in = P->t.p; m.out = P->t.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = 1; m.nrhs = nrhs;
+    m.in = wt; m.out = wt; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = 1; m.nrhs = nrhs;
     m.in_rs = np; m.out_rs = np; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.tune = P->tune[1];
     if ((e = timed(1, [&](const hipEvent_t* tev) { m.tev = tev; return hp::launch_cols(m, st); })) != hipSuccess)
@@ -760,7 +769,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   if ((e = mark(2)) != hipSuccess) return e;
   hp::ColsArgs b{};
   b.real_kind = rk; b.n = P->n[0]; b.dir = -1; b.mode = 1;
-  b.in = P->t.p; b.out = P->fields.p; b.S = (int)(np / P->n[0]); b.outer = 1; b.nfields = 1; b.nrhs = nrhs;
+  b.in = wt; b.out = wf; b.S = (int)(np / P->n[0]); b.outer = 1; b.nfields = 1; b.nrhs = nrhs;
   b.in_rs = np; b.out_rs = np * P->K; b.in_fs = np; b.out_fs = np; b.tw = P->tw(0); b.skip = skip;
   b.lam_ax = (const double*)P->lam_ax.p; b.lam_in = (const double*)P->lam_in.p;
   b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
@@ -774,7 +783,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   if (P->dim == 3) {   // inverse along the middle axis for the K fields, in place
     hp::ColsArgs m{};
     m.real_kind = rk; m.n = P->n[1]; m.dir = +1; m.mode = 0;
-    m.in = P->fields.p; m.out = P->fields.p; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = P->K; m.nrhs = nrhs;
+    m.in = wf; m.out = wf; m.S = P->n[2]; m.outer = P->n[0]; m.nfields = P->K; m.nrhs = nrhs;
     m.in_rs = np * P->K; m.out_rs = np * P->K; m.in_fs = np; m.out_fs = np; m.tw = P->tw(1); m.skip = skip;
     m.slab_need = (const uint8_t*)P->slabneed.p;
     m.tune = P->tune[3];
@@ -784,7 +793,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   if ((e = mark(4)) != hipSuccess) return e;
   hp::CombineArgs c{};
   c.real_kind = rk; c.out_kind = out_kind; c.accumulate = acc ? 1 : 0; c.n = nl;
-  c.fields = P->fields.p; c.fs = np; c.frs = np * P->K; c.pos = (const double*)P->pos.p;
+  c.fields = wf; c.fs = np; c.frs = np * P->K; c.pos = (const double*)P->pos.p;
   c.grpmask = (const uint64_t*)P->grpmask.p; c.rowmask = (const uint64_t*)P->rowmask.p; c.out = u; c.out_rs = out_rs; c.rows = rows; c.K = P->K;
   c.M = P->M; c.Mt = P->Mt; c.mo = P->mo; c.nrhs = nrhs; c.tw = P->tw(P->dim - 1); c.skip = skip;
   c.order = P->order; c.lag = (const double*)P->lagtab.p;
@@ -911,6 +920,35 @@ hp_status hp_apply_precond(hp_plan p, const void* v, void* u, int nrhs, void* st
     const char* vi = (const char*)v + (size_t)r0 * p->npts * fs;
     char* uo = (char*)u + (size_t)r0 * p->npts * fs;
     HP_TRY(run_apply(p, vi, kind, p->npts, uo, kind, p->npts, false, nr, nullptr, st));
+  }
+  return HP_OK;
+}
+
+hp_status hp_apply_precond_static(hp_plan p, const void* v, void* u, int nrhs, void* stream) {
+  if (!p || !v || !u || nrhs < 0) return HP_E_INVALID;
+  const size_t fb = p->npts * p->fsize();                 // one field
+  auto round256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  auto need = [&](size_t nr) { return round256(nr * fb) + nr * fb * (size_t)p->K; };
+  if (need(1) > HP_STATIC_SCRATCH_BYTES) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "hp_apply_precond_static: one field needs %zu bytes ((1 + K) N^d S with K = %d), the static "
+                  "workspace holds %zu",
+                  need(1), p->K, (size_t)HP_STATIC_SCRATCH_BYTES);
+    return HP_E_INVALID;
+  }
+  if (nrhs == 0) return HP_OK;
+  void* base = nullptr;
+  HP_TRY(hp::static_scratch(&base));
+  size_t chunk = 1;
+  while (chunk < (size_t)nrhs && need(chunk + 1) <= HP_STATIC_SCRATCH_BYTES) ++chunk;
+  const ApplyWs ws{base, (char*)base + round256(chunk * fb)};
+  hipStream_t st = (hipStream_t)stream;
+  const int kind = p->prec == HP_FP64 ? 0 : 1;
+  for (size_t r0 = 0; r0 < (size_t)nrhs; r0 += chunk) {
+    const int nr = (int)std::min(chunk, (size_t)nrhs - r0);
+    const char* vi = (const char*)v + r0 * fb;
+    char* uo = (char*)u + r0 * fb;
+    HP_TRY(run_apply(p, vi, kind, p->npts, uo, kind, p->npts, false, nr, nullptr, st, nullptr, 1, &ws));
   }
   return HP_OK;
 }

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/helmpre.h"
 #include "hp_fft.h"
 
 namespace hp {
@@ -207,6 +208,9 @@ hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_plain_norm(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int which, hipStream_t st);
 hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, bool accumulate, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// Device address of this device's copy of the static apply workspace
+// (HP_STATIC_SCRATCH_BYTES), looked up once per device, on the current device.
+hipError_t static_scratch(void** out);
 hipError_t launch_rsub(const cpx<double>* b, size_t b_rs, cpx<double>* v, size_t v_rs, size_t n, int nrhs,
                        const int* skip, hipStream_t st);
 

@@ -12,6 +12,7 @@
 // d = 3 adds the forward and inverse transforms along the middle axis as plain
 // strided passes (A' and M) between A/B and B/C.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -2281,6 +2282,37 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_zero, dim3(stream_blocks(n)), dim3(256), 0, st, (uint32_t*)p, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- static scratch
+// Apply workspace of hp_apply_precond_static: a file-scope device array that every
+// GPU the library runs on holds from module load to process exit.  Host code never
+// uses the array's name as an address (on the host it names a stand-in): the
+// device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress, with that device current, and kept here.
+static __device__ __align__(256) unsigned char scratch[HP_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    if (ptr == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace hp
