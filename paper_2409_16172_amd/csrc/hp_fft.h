@@ -141,6 +141,20 @@ __device__ __forceinline__ void xsync() {
   }
 }
 
+// Returns p unchanged, but hides its value from the optimiser (an empty asm
+// statement with side effects).  Twiddle loads addressed through it can be
+// neither hoisted out of a loop nor scheduled ahead of an earlier stage, so only
+// one stage's twiddles are live at a time.
+// The pointer must address global memory; it goes through the asm as a
+// global-address-space pointer so that the loads stay global (not flat) loads.
+template <typename T>
+__device__ __forceinline__ const T* reload_each_time(const T* p) {
+  using GP = const __attribute__((address_space(1))) T*;
+  GP g = (GP)p;
+  asm volatile("" : "+s"(g));
+  return (const T*)g;
+}
+
 template <int N, int NS, int E>
 __host__ __device__ constexpr int stage_radix() {
   return (N / NS) < E ? (N / NS) : E;
@@ -151,9 +165,10 @@ __host__ __device__ constexpr int stage_radix() {
 // ILV: several transforms share one LDS array with their elements interleaved
 // (element p of transform g at lpad(p) * ILV + g; the caller passes lds + g),
 // so that lanes of neighbouring transforms touch neighbouring banks.
-template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV>
+template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV, bool RELOAD = false>
 struct Stage {
   __device__ __forceinline__ static void run(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
+    if constexpr (RELOAD && NS > 1) tw = reload_each_time(tw);
     constexpr int RS = stage_radix<N, NS, E>();
     constexpr int B = E / RS;
     constexpr int T = N / E;
@@ -187,7 +202,7 @@ struct Stage {
 #pragma unroll
       for (int s = 0; s < E; ++s) x[s] = lds[lpad<E>(j + T * s) * ILV];
       xsync<WAVE>();
-      Stage<R, N, E, DIR, NS * RS, WAVE, ILV>::run(x, lds, j, tw);
+      Stage<R, N, E, DIR, NS * RS, WAVE, ILV, RELOAD>::run(x, lds, j, tw);
     }
   }
 };
@@ -200,10 +215,12 @@ __host__ __device__ constexpr int lds_elems(int n) { return lds_elems_e<elems_pe
 // of a transform are consecutive, in which case transforms of at most 64
 // threads synchronise within their wavefront only).
 // fft_e takes the elements per thread E explicitly (LDS: lds_elems_e<E>(N) per transform).
-template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1>
+// RELOAD: each stage reads its twiddles through reload_each_time (wave-resident
+// lines of many elements per lane, whose registers cannot hold every stage's).
+template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1, bool RELOAD = false>
 __device__ __forceinline__ void fft_e(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
   constexpr int T = N / E;
-  Stage<R, N, E, DIR, 1, CONTIG && (T <= 64), ILV>::run(x, lds, j, tw);
+  Stage<R, N, E, DIR, 1, CONTIG && (T <= 64), ILV, RELOAD>::run(x, lds, j, tw);
 }
 template <typename R, int N, int DIR, bool CONTIG = false, int ILV = 1>
 __device__ __forceinline__ void fft(cpx<R> (&x)[elems_per_thread<R>(N)], cpx<R>* lds, int j,

@@ -103,6 +103,14 @@ using ColsCfg = std::conditional_t<MODE == 1, SymCfg<R, N>, ColCfg<R, N, 1024>>;
 #ifndef HP_XCD_REMAP
 #define HP_XCD_REMAP 1
 #endif
+// Pass C with one row per wavefront (k_comb_wave) for the precisions in
+// HP_WAVE_COMB (bit 0: FP32 lines, bit 1: FP64 lines).  FP32 1024-point rows:
+// 56.9 -> 53-54 us per 1024^2 combine; FP64 1024-point rows need more than 256
+// registers at 16 elements per lane (spills, 64 -> 131 us), so they keep the
+// two-wavefront rows of k_rows_combine.
+#ifndef HP_WAVE_COMB
+#define HP_WAVE_COMB 1
+#endif
 
 // ---------------------------------------------------------------- pass A
 template <typename R, typename TI, int N>
@@ -451,6 +459,90 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
       } else {
         dst[j + C::T * s] = cvt<TO>(acc[s]);
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- wave-resident lines
+// A line of N = 64 E points held by one wavefront, E elements per lane (E = 16 at
+// N = 1024): every exchange of its transform stays inside the wavefront, so the
+// transform needs no workgroup barrier and each wavefront runs at its own pace;
+// with radix-E stages a 1024-point line takes two exchanges instead of three.
+// At E = 16 the twiddles of all stages would take more registers than the line
+// itself if the compiler kept them live across a node loop (they are loop
+// invariant), so each stage reads its own again from the cache (fft_e with
+// RELOAD).
+template <typename R, int N>
+struct WaveLine {
+  static constexpr int E = N / 64;
+  static constexpr int LDS = lds_elems_e<E>(N);
+};
+template <typename R, int N>
+constexpr bool wave_line_fits() {
+  // lines of one full wavefront with at most 16 elements per lane
+  return N >= 256 && N / 64 <= 16;
+}
+constexpr int kWaveRows = 4;   // rows (one per wavefront) per workgroup of the wave combine
+
+// Pass C with one row per wavefront: inverse transform of each node row the row
+// uses (its own node list, not its workgroup's) and the weighted sum; loads and
+// stores of a wavefront cover 64 E consecutive elements.
+template <typename R, typename TO, int N, bool ACC, int IM>
+__global__ __launch_bounds__(64 * kWaveRows, 2) void k_comb_wave(
+    const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
+    const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out, size_t out_rs, int rows, int M, int Mt,
+    int mo, const cpx<R>* tw, const int* __restrict__ skip, int ord, const double* __restrict__ lag,
+    const double* __restrict__ posa, int Ma) {
+  constexpr int E = WaveLine<R, N>::E;
+  constexpr bool LAG = IM == kInterpLagrange;
+  __shared__ cpx<R> lds[kWaveRows * WaveLine<R, N>::LDS];
+  __shared__ double slag[LAG ? kLagTable : 1];
+  const int rhs = blockIdx.y;
+  if (skip != nullptr && skip[rhs] != 0) return;
+  if constexpr (LAG) {
+    for (int i = threadIdx.x; i < kLagTable; i += 64 * kWaveRows) slag[i] = lag[i];
+    __syncthreads();
+  }
+  const int wv = (int)threadIdx.x / 64, j = (int)threadIdx.x % 64;
+  const int row = blockIdx.x * kWaveRows + wv;
+  if (row >= rows) return;   // no workgroup barrier follows
+  const size_t rbase = (size_t)row * N;
+  int ab[E];
+  R tt[E], uu[E];
+  cpx<R> acc[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const size_t pi = rbase + j + 64 * s;
+    uu[s] = (R)0;
+    interp_record<R, IM>(pos[pi], IM == kInterpBilinear ? posa[pi] : 0.0, M, Mt, mo, Ma, ord, slag, ab[s], tt[s],
+                         uu[s]);
+    acc[s] = {0, 0};
+  }
+  cpx<R>* lw = lds + wv * WaveLine<R, N>::LDS;
+  const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
+  uint64_t left = rowmask[row];
+  while (left != 0) {
+    const int n = __builtin_ctzll(left);
+    left &= left - 1;
+    cpx<R> x[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) x[s] = fr[(size_t)n * fs + j + 64 * s];
+    fft_e<R, N, E, +1, true, 1, true>(x, lw, j, tw);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const R w = interp_weight<R, IM>(ab[s], tt[s], uu[s], n, ord, slag);
+      acc[s].re += w * x[s].re;
+      acc[s].im += w * x[s].im;
+    }
+  }
+  cpx<TO>* dst = out + (size_t)rhs * out_rs + rbase;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    if constexpr (ACC) {
+      cpx<TO> o = dst[j + 64 * s];
+      dst[j + 64 * s] = {o.re + (TO)acc[s].re, o.im + (TO)acc[s].im};
+    } else {
+      dst[j + 64 * s] = cvt<TO>(acc[s]);
     }
   }
 }
@@ -833,6 +925,7 @@ bool combine_splits_ok(int real_kind, int n);   // pass C of this length can spl
 
 bool cols_use_gen(int real_kind, int n) { return !is_pow2_len(n) || (real_kind == 0 && n > 2048); }
 
+
 int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, PassTune* out, int max) {
   int cnt = 0;
   auto push = [&](const PassTune& t) {
@@ -1037,6 +1130,26 @@ struct CombineL {
   struct F {
     static hipError_t run(const CombineArgs& a, hipStream_t st) {
       using C = CombCfg<R, N>;
+      if constexpr (wave_line_fits<R, N>() && (HP_WAVE_COMB & (sizeof(R) == 8 ? 2 : 1)) != 0) {
+        const dim3 wgrid((a.rows + kWaveRows - 1) / kWaveRows, a.nrhs);
+        switch (interp_mode(a)) {
+          case kInterpLagrange:
+            HP_PASS_LAUNCH(a.tev, (k_comb_wave<R, TO, N, ACC, kInterpLagrange>), wgrid, dim3(64 * kWaveRows), 0, st,
+                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs,
+                           a.rows, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa, a.Ma);
+            break;
+          case kInterpBilinear:
+            HP_PASS_LAUNCH(a.tev, (k_comb_wave<R, TO, N, ACC, kInterpBilinear>), wgrid, dim3(64 * kWaveRows), 0, st,
+                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs,
+                           a.rows, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa, a.Ma);
+            break;
+          default:
+            HP_PASS_LAUNCH(a.tev, (k_comb_wave<R, TO, N, ACC, kInterpLinear>), wgrid, dim3(64 * kWaveRows), 0, st,
+                           (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs,
+                           a.rows, a.M, a.Mt, a.mo, (const cpx<R>*)a.tw, a.skip, a.order, a.lag, a.posa, a.Ma);
+        }
+        return hipGetLastError();
+      }
       dim3 grid((a.rows + C::G - 1) / C::G, a.nrhs);
       if constexpr (combine_splits_fit<R, N>()) {
         // node splits when the row groups alone would leave most of the chip idle, or

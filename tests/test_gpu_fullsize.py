@@ -179,3 +179,29 @@ def test_mixed_served_mix_with_3d_requests(orc, dev):
               flush=True)
         assert res <= 1e-8 * 1.001, (r.rid, res)
         plan.close()
+
+
+@pytest.mark.parametrize("shape,mode", [((32, 256), "lagrange"), ((16, 1024), "lagrange"), ((24, 512), "bilinear"),
+                                        ((16, 1024), "bilinear"), ((16, 16, 256), "lagrange")])
+def test_mixed_combine_modes_on_long_rows(orc, hp, dev, shape, mode):
+    """Mixed-precision combines of 256- to 1024-point rows (one row per wavefront) in the
+    higher-degree and bilinear interpolation modes, against the oracle."""
+    _case("combine_modes_long_rows", shape=shape, mode=mode)
+    nmin = min(shape)
+    omega = 2 * np.pi * nmin / 4
+    if mode == "lagrange":
+        c, zeta = _media(shape, seed=sum(shape) + 5)
+        a = np.full(shape, 0.05 * omega)
+        kw = dict(m_real=7, m_layer=3, a_floor=0.05 * omega, interp_order=3)
+    else:
+        c = inputs.gaussian_random_field(shape, max(2.0, nmin / 4), sum(shape), lo=0.8, hi=1.3)
+        a = inputs.gaussian_random_field(shape, max(2.0, nmin / 3), sum(shape) + 1, lo=0.05 * omega, hi=0.6 * omega)
+        zeta = None
+        kw = dict(m_real=5, m_damp=3)
+    v = _v32(shape, 53, nrhs=2)
+    ue = orc.Problem(shape, omega, c, a, zeta, **kw).apply(v)
+    plan = hp.Plan(shape, omega, c, a, zeta, precision="mixed", max_nrhs=2, **kw)
+    u = plan.apply(torch.from_numpy(v).to(dev).to(torch.complex64)).cpu().numpy()
+    for r in range(2):
+        _check(u[r], ue[r], 1e-5, f"mixed {mode} {shape} rhs {r}")
+    plan.close()
