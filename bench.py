@@ -64,41 +64,139 @@ def traffic_from_profiles(workload, kernel_slot):
     return None if v is None else float(v)
 
 
-def cpu_baseline(w, gpu_iters, gpu_cycles, steps=6):
-    """The FP64 oracle, single-threaded, timed on a bounded sample: `steps` Arnoldi steps
-    (each one Q_M apply, one P_N matvec and modified Gram-Schmidt) plus one apply and one
-    matvec (the per-cycle solution update and true residual), extrapolated to a whole solve
-    with the GPU run's iteration and cycle counts."""
+def _cycle_lengths(iters, cycles, restart):
+    """Arnoldi steps per cycle of a restarted solve: full cycles, then the rest."""
+    if cycles <= 0:
+        return []
+    full = [restart] * (cycles - 1)
+    return full + [max(0, iters - restart * (cycles - 1))]
+
+
+def cpu_baseline(w, gpu_iters, gpu_cycles, restart=30, rtol=1e-8):
+    """The FP64 C oracle on the host cores.
+
+    All cores: the oracle built with OpenMP over its independent loops (transform lines,
+    points, dot-product reductions) solves the benchmark workload once, whole (restarted
+    GMRES(30) to rtol), timed; that is the reported value, with the threads it used.
+    One core: the single-threaded oracle runs Arnoldi processes of 2 and 4 steps; their
+    times fix the per-step cost (one Q_M apply, one P_N matvec, norms) and the
+    modified Gram-Schmidt cost per basis vector, from which a whole solve with the GPU
+    run's cycle lengths is computed (the Gram-Schmidt cost grows with the step index, so
+    a linear extrapolation from the first steps would undercount it).  The 64^2 bump
+    workload is solved whole on one core and on all cores."""
     import oracle
-    p = oracle.from_workload(w)
     f = w.f[0]
+    out = {"kind": "oracle", "unit": "solves/s"}
+    nthreads = oracle.use_openmp(True)
+    p = oracle.from_workload(w)
     t0 = time.perf_counter()
-    p.arnoldi(f, steps)
-    t_step = (time.perf_counter() - t0) / steps
+    x, res = p.gmres(f, rtol=rtol, restart=restart)
+    t_omp = time.perf_counter() - t0
+    out.update({"value": 1.0 / t_omp, "cores": nthreads, "nproc": os.cpu_count(),
+                "sample": f"one whole solve of {w.name} ({w.shape[0]}^2, K={w.m_real + w.m_layer}, GMRES({restart}) "
+                          f"to {rtol:g}: {res['iters']} steps, {res['cycles']} cycles, true residual "
+                          f"{res['rel_true_residual']:.2e}) by the FP64 C oracle built with OpenMP, "
+                          f"{nthreads} threads: {t_omp:.1f} s"})
+    from paper_2409_16172_amd import inputs
+    w0 = inputs.workload("2d_64_bump")
+    cfg0 = {}
+    for omp in (False, True):
+        nt = oracle.use_openmp(omp)
+        p0 = oracle.from_workload(w0)
+        t0 = time.perf_counter()
+        reps = 0
+        while reps < 3 or time.perf_counter() - t0 < 1.0:
+            _, r0 = p0.gmres(w0.f[0], rtol=rtol, restart=restart)
+            reps += 1
+        cfg0[f"{nt}_threads"] = {"solves_per_s": reps / (time.perf_counter() - t0), "iters": r0["iters"]}
+    out["bump_64"] = cfg0
+    oracle.use_openmp(False)
+    p1 = oracle.from_workload(w)
+    t = {}
+    for m in (2, 4):
+        t0 = time.perf_counter()
+        p1.arnoldi(f, m)
+        t[m] = time.perf_counter() - t0
+    # arnoldi(m) = m A + B m (m + 1) / 2:  A per step, B per basis vector of the sweep
+    B = (t[4] - 2.0 * t[2]) / (10.0 - 6.0)
+    A = (t[2] - 3.0 * B) / 2.0
+    B = max(B, 0.0)
     t0 = time.perf_counter()
-    p.matvec(p.apply(f))
+    p1.matvec(p1.apply(f))
     t_cycle = time.perf_counter() - t0
-    t_solve = gpu_iters * t_step + gpu_cycles * t_cycle
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} Arnoldi steps + 1 apply/matvec of {w.name} ({w.shape[0]}^2, K="
-                      f"{w.m_real + w.m_layer}), FP64 C oracle; {t_step:.2f} s/step, solve extrapolated "
-                      f"to {gpu_iters} steps and {gpu_cycles} cycles = {t_solve:.1f} s"}
+    ks = _cycle_lengths(gpu_iters, gpu_cycles, restart)
+    t_single = sum(k * A + B * k * (k + 1) / 2.0 for k in ks) + len(ks) * t_cycle
+    out["single_core"] = {"value": 1.0 / t_single, "unit": "solves/s", "cores": 1,
+                          "sample": f"Arnoldi runs of 2 and 4 steps ({t[2]:.1f} s, {t[4]:.1f} s) give "
+                                    f"{A:.2f} s per step and {B:.3f} s per Gram-Schmidt basis vector; one "
+                                    f"apply + matvec per cycle {t_cycle:.2f} s; a solve of cycles {ks} = "
+                                    f"{t_single:.1f} s (computed, not run whole)"}
+    return out
 
 
 SERVING_GRIDS = ((256, 256), (512, 512), (1024, 1024), (2048, 2048), (128, 128, 128))
 
 
-def serving_run(dev, n_requests=30, rate=25.0):
-    """Continuous-batching stream: Poisson arrivals of mixed-precision solves on
-    256^2 / 512^2 / 1024^2 / 2048^2 / 128^3 random media, 20-150 wavelengths (at most
-    N/4), rtol 1e-8; latency from arrival to solution, including plan set-up."""
-    from paper_2409_16172_amd import serve
-    reqs = serve.stream_requests(n_requests, rate_per_s=rate, grids=SERVING_GRIDS, precision="mixed")
-    srv = serve.Server(hbm_budget_bytes=200 << 30, max_active=8, steps_per_turn=2)
-    done = srv.run(reqs, dev=dev)
+def serving_run(dev, n_requests=500, rate=None, budget_gib=16.0, capacity_requests=100, fp64_compare=True):
+    """The serving stream: Poisson arrivals of mixed-precision solves on 256^2 / 512^2 /
+    1024^2 / 2048^2 / 128^3 random media (three media per grid, each request with its
+    own frequency, 20-150 wavelengths clamped to N/4, and its own Gaussian source),
+    rtol 1e-8, admitted by HBM footprint under a budget that binds; latency from
+    arrival to solution, including plan set-up.  The closed-loop capacity (all of the
+    first `capacity_requests` requests present at time 0) is measured first and the
+    arrival rate set to 0.8 times it unless given.  The same problem set is then
+    solved one request at a time with FP64 plans, for comparison."""
+    import torch
+    from paper_2409_16172_amd import binding, serve
+    t0 = time.perf_counter()
+    base = serve.stream_requests(n_requests, rate_per_s=1.0, grids=SERVING_GRIDS, precision="mixed", pool=3)
+    t_gen = time.perf_counter() - t0
+    budget = int(budget_gib * 2 ** 30)
+    print(f"[bench] serving: {n_requests} requests generated in {t_gen:.1f} s, budget {budget_gib} GiB",
+          file=sys.stderr, flush=True)
+    cap = serve.Server(budget, max_active=8, steps_per_turn=2, keep_x=False)
+    cap_done = cap.run(serve.retimed(base[:capacity_requests], None), dev=dev)
+    capacity = serve.latency_stats(cap_done)["solves_per_s"]
+    rate = 0.8 * capacity if rate is None else rate
+    print(f"[bench] serving: closed-loop capacity {capacity:.1f} solves/s, arrivals at {rate:.1f}/s",
+          file=sys.stderr, flush=True)
+    srv = serve.Server(budget, max_active=8, steps_per_turn=2, keep_x=False)
+    done = srv.run(serve.retimed(base, rate), dev=dev)
     st = serve.latency_stats(done)
-    st.update({"arrival_rate_per_s": rate, "grids": ["x".join(map(str, g)) for g in SERVING_GRIDS],
-               "precision": "mixed", "peak_workspace_GiB": srv.peak_in_use / 2 ** 30})
+    st.update({"closed_loop_capacity_solves_per_s": capacity, "capacity_requests": len(cap_done),
+               "arrival_rate_per_s": rate, "grids": ["x".join(map(str, g)) for g in SERVING_GRIDS],
+               "precision": "mixed", "hbm_budget_GiB": budget_gib,
+               "peak_workspace_GiB": srv.peak_in_use / 2 ** 30,
+               "requests_deferred_by_budget": len(srv.deferred_rids),
+               "max_iters": max(r.info[0].iters for r in done)})
+    print(f"[bench] serving: {st['solves_per_s']:.1f} solves/s, p50 {st['latency_ms_p50']:.1f} ms, "
+          f"p99 {st['latency_ms_p99']:.1f} ms, {st['converged']}/{len(done)} converged", file=sys.stderr, flush=True)
+    if fp64_compare:
+        # the same problems one at a time with FP64 plans (plan set-up included, as in serving)
+        for shape in SERVING_GRIDS:   # untimed warm-up of each grid's FP64 kernels
+            r = next((q for q in base if q.workload.shape == shape), None)
+            if r is not None:
+                p = binding.plan_from_workload(r.workload, precision="fp64", max_nrhs=1)
+                p.solve(torch.from_numpy(r.workload.f[:1]).to(dev), rtol=1e-8)
+                p.close()
+        torch.cuda.synchronize()
+        lat = []
+        conv = 0
+        t0 = time.perf_counter()
+        for r in base:
+            ts = time.perf_counter()
+            p = binding.plan_from_workload(r.workload, precision="fp64", max_nrhs=1)
+            x, info = p.solve(torch.from_numpy(r.workload.f[:1]).to(dev), rtol=1e-8)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+            conv += int(info[0].status == 0)
+            p.close()
+            del x
+        t_fp64 = time.perf_counter() - t0
+        st["fp64_one_at_a_time"] = {"solves_per_s": len(base) / t_fp64, "solve_ms_p50": float(np.percentile(lat, 50)) * 1e3,
+                                    "solve_ms_p99": float(np.percentile(lat, 99)) * 1e3, "converged": conv}
+        st["served_mixed_over_fp64_one_at_a_time"] = st["solves_per_s"] / st["fp64_one_at_a_time"]["solves_per_s"]
+        st["capacity_mixed_over_fp64_one_at_a_time"] = capacity / st["fp64_one_at_a_time"]["solves_per_s"]
     return st
 
 
@@ -132,10 +230,12 @@ def large_grid_compare(dev, reps=2, tune=True):
     return out
 
 
-def batch3d(args, dev):
+def batch3d(args, dev, emit=True):
     """3-D batch: nrhs Gaussian sources on one random medium with a sphere, solved
     together (every pass is one launch over all right-hand sides), mixed precision,
-    rtol 1e-8; compared with solving right-hand sides one at a time."""
+    rtol 1e-8; compared with solving right-hand sides one at a time.  The roofline of
+    the batch is that of its dominant pass kernel launched over the whole batch
+    (event-timed, back to back)."""
     import torch
     from paper_2409_16172_amd import binding, inputs
     w = inputs.workload("3d_256_grf", n=args.n3d, nrhs=args.nrhs3d)
@@ -167,6 +267,15 @@ def batch3d(args, dev):
     rng = np.random.default_rng(0)
     v = torch.from_numpy((rng.standard_normal(w.shape) + 1j * rng.standard_normal(w.shape))[None]).to(dev).to(plan.field_dtype)
     ms, by = plan.profile_apply(v, reps=3)
+    vb = v.expand((w.f.shape[0],) + tuple(w.shape)).contiguous()
+    del v
+    msb, byb = plan.profile_apply(vb, reps=3)
+    del vb
+    dom = int(np.argmax(msb))
+    achieved = byb[dom] / (msb[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "pass": PASS_NAMES[dom], "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes": byb[dom],
+            "launch_us": msb[dom] * 1e3, "nrhs_per_launch": int(w.f.shape[0]), "timed_in": "back-to-back launches"}
     out = {"mode": "batch3d", "workload": f"{w.name}: {w.shape[0]}^3, 7-point FD, {w.info['n_lambda']:.0f} wavelengths, "
                                          f"random field in [0.8,1.2] + c=1.4 sphere, {w.info['layer_cells']}-cell layer, "
                                          f"{w.m_real}+{w.m_layer} nodes, mixed precision, rtol 1e-8",
@@ -177,8 +286,14 @@ def batch3d(args, dev):
            "iters": [i.iters for i in infos], "max_rel_true_residual": max(i.rel_true_residual for i in infos),
            "converged": all(i.status == 0 for i in infos),
            "apply_1rhs_us": sum(ms) * 1e3, "apply_1rhs_GBps": sum(by) / (sum(ms) * 1e-3) / 1e9,
-           "pass_us": dict(zip(PASS_NAMES, [t * 1e3 for t in ms]))}
-    print(json.dumps(out))
+           "pass_us": dict(zip(PASS_NAMES, [t * 1e3 for t in ms])),
+           "batch_apply_us": sum(msb) * 1e3, "batch_apply_GBps": sum(byb) / (sum(msb) * 1e-3) / 1e9,
+           "batch_pass_us": dict(zip(PASS_NAMES, [t * 1e3 for t in msb])),
+           "batch_pass_bytes": dict(zip(PASS_NAMES, byb)), "roofline": roof}
+    plan.close()
+    if emit:
+        print(json.dumps(out))
+    return out
 
 
 def example1(args, dev):
@@ -468,8 +583,11 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 mixed vs FP64 comparison")
-    ap.add_argument("--serve-requests", type=int, default=30)
-    ap.add_argument("--serve-rate", type=float, default=25.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="Poisson arrival rate (requests/s); default 0.8 x the measured closed-loop capacity")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving admission")
+    ap.add_argument("--no-batch3d", action="store_true", help="skip the 256^3 x 16 batch leg")
     ap.add_argument("--n3d", type=int, default=256)
     ap.add_argument("--nrhs3d", type=int, default=16)
     ap.add_argument("--ex1-sizes", type=int, nargs="+", default=[180, 360, 720, 1440, 2880])
@@ -607,8 +725,10 @@ def main():
                  "converged": im[0].status == 0}
         pm.close()
 
-    serving = None if args.no_serve else serving_run(dev, args.serve_requests, args.serve_rate)
+    serving = None if args.no_serve else serving_run(dev, args.serve_requests, args.serve_rate,
+                                                     args.serve_budget_gib)
     large = None if args.no_large else large_grid_compare(dev, tune=not args.no_autotune)
+    b3 = None if args.no_batch3d else batch3d(args, dev, emit=False)
     cpu = None if args.no_cpu else cpu_baseline(w, info.iters, info.cycles)
     lat_ms = sorted(t * 1e3 for t in lat)
     out = {
@@ -637,6 +757,7 @@ def main():
         "mixed": mixed,
         "serving": serving,
         "grid_2048": large,
+        "batch3d": b3,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes": by[dom], "launch_us": launch_ms * 1e3,

@@ -23,13 +23,20 @@ _LIB = os.path.join(_HERE, "libhelm_oracle.so")
 OK, E_INVALID, E_SHAPE, E_MEDIA, E_LAYER, E_NOMEM, E_NOT_CONVERGED = 0, 1, 2, 3, 4, 7, 8
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (single-threaded, -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+_LIB_OMP = os.path.join(_HERE, "libhelm_oracle_omp.so")
+
+
+def build(force: bool = False, openmp: bool = False) -> str:
+    """Compile the oracle with gcc, -O2: single-threaded (the library the tests use), or
+    with OpenMP over its independent loops (transform lines, points, the reductions of
+    the Gram-Schmidt dot products), used only to time the oracle on every host core."""
+    lib_path = _LIB_OMP if openmp else _LIB
+    if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(_SRC):
+        tmp = lib_path + ".tmp%d" % os.getpid()
+        extra = ["-fopenmp"] if openmp else []
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 class _Problem(C.Structure):
@@ -56,10 +63,25 @@ class _Info(C.Structure):
 
 
 _lib = None
+_lib_omp = None
+_use_openmp = False
+
+
+def use_openmp(on: bool) -> int:
+    """Route the oracle's calls to the OpenMP build (on) or the single-threaded one;
+    returns the threads the selected library uses."""
+    global _use_openmp
+    _use_openmp = bool(on)
+    return int(lib().or_num_threads())
 
 
 def lib():
-    global _lib
+    global _lib, _lib_omp
+    if _use_openmp:
+        if _lib_omp is None:
+            _lib_omp = C.CDLL(build(openmp=True))
+            assert _lib_omp.or_setup_sizeof() == C.sizeof(_Setup)
+        return _lib_omp
     if _lib is None:
         _lib = C.CDLL(build())
         assert _lib.or_setup_sizeof() == C.sizeof(_Setup)

@@ -28,6 +28,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cx;
 
@@ -219,20 +222,42 @@ int or_fftnd(int dim, const int* n, cx* x, int inverse) {
         long stride = 1;
         for (int d = ax + 1; d < dim; ++d) stride *= n[d];
         long outer = tot / (stride * len);
-        cx* line = (cx*)malloc(sizeof(cx) * (size_t)len);
-        if (!line) return OR_E_NOMEM;
-        for (long o = 0; o < outer; ++o)
-            for (long s = 0; s < stride; ++s) {
+        long nlines = outer * stride;
+        int err = OR_OK;
+        /* the lines are independent (OpenMP builds take them in parallel) */
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+        {
+            cx* line = (cx*)malloc(sizeof(cx) * (size_t)len);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (long q = 0; q < nlines; ++q) {
+                long o = q / stride, s = q % stride;
                 cx* base = x + o * stride * len + s;
-                for (int i = 0; i < len; ++i) line[i] = base[(long)i * stride];
-                int rc = fft_line(len, line, sign);
-                if (rc) { free(line); return rc; }
-                for (int i = 0; i < len; ++i) base[(long)i * stride] = line[i];
+                int rc = line ? OR_OK : OR_E_NOMEM;
+                if (rc == OR_OK) {
+                    for (int i = 0; i < len; ++i) line[i] = base[(long)i * stride];
+                    rc = fft_line(len, line, sign);
+                    for (int i = 0; i < len; ++i) base[(long)i * stride] = line[i];
+                }
+                if (rc) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+                    err = rc;
+                }
             }
-        free(line);
+            free(line);
+        }
+        if (err) return err;
     }
     if (inverse) {
         double sc = 1.0 / (double)tot;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (long i = 0; i < tot; ++i) x[i] *= sc;
     }
     return OR_OK;
@@ -620,8 +645,14 @@ int or_apply(const or_problem* p, int nrhs, const cx* v, cx* u) {
         for (long i = 0; i < np; ++i) ur[i] = 0;
         for (int n = 0; n < s.K; ++n) {
             cx g = s.gre[n] + I * s.gim[n];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
             for (long i = 0; i < np; ++i) z[i] = symbol_q(p->omega, s.ahat[n], g, lam[i]) * vh[i];
             or_fftnd(p->dim, p->n, z, 1);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
             for (long i = 0; i < np; ++i) ur[i] += wgt[i * s.K + n] * z[i];
         }
     }
@@ -667,11 +698,14 @@ int or_matvec(const or_problem* p, int nrhs, const cx* u, cx* y) {
     long np = npoints(p);
     long stride[3] = {1, 1, 1};
     for (int d = p->dim - 2; d >= 0; --d) stride[d] = stride[d + 1] * p->n[d + 1];
-    int idx[3];
     for (int r = 0; r < nrhs; ++r) {
         const cx* ur = u + (long)r * np;
         cx* yr = y + (long)r * np;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (long i = 0; i < np; ++i) {
+            int idx[3];
             unravel(p, i, idx);
             cx lap = 0;
             for (int d = 0; d < p->dim; ++d) {
@@ -702,13 +736,40 @@ int or_matvec(const or_problem* p, int nrhs, const cx* u, cx* y) {
 /* ------------------------------------------------------------------ */
 static double nrm2(long n, const cx* x) {
     double s = 0;
+#ifdef _OPENMP
+#pragma omp parallel for reduction(+ : s) schedule(static)
+#endif
     for (long i = 0; i < n; ++i) s += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
     return sqrt(s);
 }
 static cx dotc(long n, const cx* x, const cx* y) {     /* x^H y */
-    cx s = 0;
-    for (long i = 0; i < n; ++i) s += conj(x[i]) * y[i];
-    return s;
+    double sr = 0, si = 0;
+#ifdef _OPENMP
+#pragma omp parallel for reduction(+ : sr, si) schedule(static)
+#endif
+    for (long i = 0; i < n; ++i) {
+        cx t = conj(x[i]) * y[i];
+        sr += creal(t);
+        si += cimag(t);
+    }
+    return sr + I * si;
+}
+
+/* w -= h v over n points */
+static void axpy_sub(long n, cx h, const cx* v, cx* w) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (long t = 0; t < n; ++t) w[t] -= h * v[t];
+}
+
+/* Threads the library uses (1 unless built with OpenMP). */
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 typedef struct {
@@ -751,13 +812,13 @@ int or_arnoldi(const or_problem* p, int side, int m, int reorth, const cx* v0, c
         for (int i = 0; i <= j; ++i) {
             cx hij = dotc(np, V + (long)i * np, w);
             H[(long)i * m + j] = hij;
-            for (long t = 0; t < np; ++t) w[t] -= hij * V[(long)i * np + t];
+            axpy_sub(np, hij, V + (long)i * np, w);
         }
         if (reorth) {
             for (int i = 0; i <= j; ++i) {
                 cx d = dotc(np, V + (long)i * np, w);
                 H[(long)i * m + j] += d;
-                for (long t = 0; t < np; ++t) w[t] -= d * V[(long)i * np + t];
+                axpy_sub(np, d, V + (long)i * np, w);
             }
         }
         double hn = nrm2(np, w);
@@ -819,7 +880,7 @@ int or_gmres(const or_problem* p, int side, int m, int max_cycles, double rtol,
             for (int i = 0; i <= j; ++i) {                      /* modified Gram-Schmidt */
                 cx hij = dotc(np, V + (long)i * np, w);
                 H[(long)i * m + j] = hij;
-                for (long t = 0; t < np; ++t) w[t] -= hij * V[(long)i * np + t];
+                axpy_sub(np, hij, V + (long)i * np, w);
             }
             double hn = nrm2(np, w);
             H[(long)(j + 1) * m + j] = hn;

@@ -35,27 +35,48 @@ class Request:
     x: object = None
 
 
+def _pooled_workload(base, n_lambda, seed):
+    """A request on a pooled medium: its own frequency (n_lambda wavelengths), damping
+    a = 0.05 omega and Gaussian source at a seeded position; the medium (c, layer)
+    is shared with the other requests drawn from the same pool entry."""
+    shape = base.shape
+    omega = inputs.omega_for_wavelengths(n_lambda)
+    width = base.info["layer_cells"]
+    ctr = inputs.random_source_centres(shape, 1, width, 2.0, seed)[0]
+    f = inputs.gaussian_source(shape, 2.0, ctr)[None]
+    info = dict(base.info)
+    info.update({"n_lambda": n_lambda, "source": ctr, "pool_seed": base.info.get("seed")})
+    return inputs.Workload(base.name, shape, base.length, omega, base.c, np.full(shape, 0.05 * omega), base.zeta, f,
+                           base.m_real, base.m_layer, a_floor=0.05 * omega, precision=base.precision, info=info)
+
+
 def stream_requests(n_requests, rate_per_s, seed=20240920, grids=((256, 256), (512, 512), (1024, 1024)),
-                    precision="mixed", n_lambda=(20.0, 150.0), restart=30):
+                    precision="mixed", n_lambda=(20.0, 150.0), restart=30, pool=None):
     """Seeded request stream: Poisson arrivals; grid drawn from `grids`; wavelengths
     across the domain drawn uniformly and clamped to at most N/4 (4 points per
     wavelength); media and source from the random-field recipes (2-D: correlation 20
-    cells, layer max(8, N/32) cells; 3-D: correlation 12 cells scaled, sphere)."""
+    cells, layer max(8, N/32) cells; 3-D: correlation 12 cells scaled, sphere).
+    pool: None, a new medium per request; an integer P, P media per grid generated
+    once and drawn from by the requests (each still with its own frequency and
+    source), which keeps the host-side generation of long streams short."""
     rng = np.random.default_rng(seed)
     t = 0.0
     reqs = []
+    media = {}
     for rid in range(n_requests):
         t += rng.exponential(1.0 / rate_per_s)
         shape = tuple(grids[rng.integers(len(grids))])
         n = shape[0]
         nl = min(rng.uniform(*n_lambda), n / 4.0)
         wseed = int(rng.integers(1 << 30))
-        if len(shape) == 2:
-            w = inputs.workload("2d_1024_grf", n=n, n_lambda=nl, width=max(8, n // 32), seed=wseed,
-                                m_real=24 if n >= 2048 else 16, precision=precision)
+        if pool:
+            slot = (shape, int(rng.integers(pool)))
+            if slot not in media:
+                mseed = int(np.random.default_rng([seed, n, len(shape), slot[1]]).integers(1 << 30))
+                media[slot] = _fresh_workload(shape, nl, mseed, precision)
+            w = _pooled_workload(media[slot], nl, wseed)
         else:
-            w = inputs.workload("3d_256_grf", n=n, n_lambda=nl, nrhs=1, seed=wseed)
-            w.precision = precision
+            w = _fresh_workload(shape, nl, wseed, precision)
         r = Request(rid, t, w)
         r.k_nodes = w.m_real + w.m_layer
         r.footprint = binding.workspace_bytes(w.shape, precision, r.k_nodes, 1, restart)
@@ -63,15 +84,45 @@ def stream_requests(n_requests, rate_per_s, seed=20240920, grids=((256, 256), (5
     return reqs
 
 
+def _fresh_workload(shape, nl, wseed, precision):
+    n = shape[0]
+    if len(shape) == 2:
+        return inputs.workload("2d_1024_grf", n=n, n_lambda=nl, width=max(8, n // 32), seed=wseed,
+                               m_real=24 if n >= 2048 else 16, precision=precision)
+    w = inputs.workload("3d_256_grf", n=n, n_lambda=nl, nrhs=1, seed=wseed)
+    w.precision = precision
+    return w
+
+
+def retimed(requests, rate_per_s=None, seed=20240921):
+    """Fresh copies of `requests` (same problems, no results) with new arrival times:
+    Poisson arrivals at rate_per_s, or all at time 0 when rate_per_s is None (a closed
+    loop that measures capacity)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in requests:
+        if rate_per_s is not None:
+            t += rng.exponential(1.0 / rate_per_s)
+        c = Request(r.rid, t, r.workload, r.k_nodes, r.footprint)
+        out.append(c)
+    return out
+
+
 class Server:
+    """keep_x: keep each request's solution tensor on the GPU (False: only its info,
+    so that long streams do not hold every solution)."""
+
     def __init__(self, hbm_budget_bytes, max_active=8, steps_per_turn=2, restart=30, rtol=1e-8,
-                 max_cycles=200):
+                 max_cycles=200, keep_x=True):
         self.budget = int(hbm_budget_bytes)
         self.max_active = int(max_active)
         self.steps = int(steps_per_turn)
         self.restart, self.rtol, self.max_cycles = restart, rtol, max_cycles
+        self.keep_x = bool(keep_x)
         self.in_use = 0
         self.peak_in_use = 0
+        self.deferred_rids = set()   # requests held back by the HBM budget while a slot was free
         self.active = []
         self.done = []
 
@@ -98,7 +149,7 @@ class Server:
         x, info = solver.result()
         r.finished = time.perf_counter() - t0
         r.info = info
-        r.x = x
+        r.x = x if self.keep_x else None
         solver.close()
         plan.close()
         return True
@@ -122,6 +173,7 @@ class Server:
             while queue and len(self.active) < self.max_active:
                 r = queue[0][2]
                 if self.in_use + r.footprint > self.budget and self.active:
+                    self.deferred_rids.add(r.rid)
                     break
                 heapq.heappop(queue)
                 self._admit(r, time.perf_counter() - t0, dev, torch)
