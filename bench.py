@@ -154,16 +154,23 @@ def serving_run(dev, n_requests=500, rate=None, budget_gib=16.0, capacity_reques
     budget = int(budget_gib * 2 ** 30)
     print(f"[bench] serving: {n_requests} requests generated in {t_gen:.1f} s, budget {budget_gib} GiB",
           file=sys.stderr, flush=True)
-    cap = serve.Server(budget, max_active=8, steps_per_turn=2, keep_x=False)
-    cap_done = cap.run(serve.retimed(base[:capacity_requests], None), dev=dev)
-    capacity = serve.latency_stats(cap_done)["solves_per_s"]
+    # closed-loop capacity with a stream per request, and with grouped launches on four
+    # streams; the stream is served in the faster of the two
+    caps = {}
+    for mode in ("per_request_streams", "grouped"):
+        cap = serve.Server(budget, max_active=8, steps_per_turn=2, keep_x=False, grouped=mode == "grouped")
+        cap_done = cap.run(serve.retimed(base[:capacity_requests], None), dev=dev)
+        caps[mode] = serve.latency_stats(cap_done)["solves_per_s"]
+    mode = max(caps, key=caps.get)
+    capacity = caps[mode]
     rate = 0.8 * capacity if rate is None else rate
-    print(f"[bench] serving: closed-loop capacity {capacity:.1f} solves/s, arrivals at {rate:.1f}/s",
+    print(f"[bench] serving: closed-loop capacity {caps}, serving {mode}, arrivals at {rate:.1f}/s",
           file=sys.stderr, flush=True)
-    srv = serve.Server(budget, max_active=8, steps_per_turn=2, keep_x=False)
+    srv = serve.Server(budget, max_active=8, steps_per_turn=2, keep_x=False, grouped=mode == "grouped")
     done = srv.run(serve.retimed(base, rate), dev=dev)
     st = serve.latency_stats(done)
-    st.update({"closed_loop_capacity_solves_per_s": capacity, "capacity_requests": len(cap_done),
+    st.update({"closed_loop_capacity_solves_per_s": capacity, "capacity_by_mode": caps, "mode": mode,
+               "capacity_requests": capacity_requests,
                "arrival_rate_per_s": rate, "grids": ["x".join(map(str, g)) for g in SERVING_GRIDS],
                "precision": "mixed", "hbm_budget_GiB": budget_gib,
                "peak_workspace_GiB": srv.peak_in_use / 2 ** 30,
@@ -395,6 +402,50 @@ def interp_compare(args, dev):
     print(json.dumps({"mode": "interp", "workload": w.name, "rows": rows}))
 
 
+def restarted_extreme(plan, v0, smallest, side, m, max_restarts, tol, deadline):
+    """The restarted Arnoldi of hp_extreme_eigenvalue, driven from here so that a wall
+    clock deadline can end it between restarts: runs of m steps of the operator (its
+    inverse for the smallest end, by inner GMRES solves), each restarted from the Ritz
+    vector of largest modulus until its residual relative to |theta| is <= tol.
+    Returns (lambda, relative residual, runs, converged, reason)."""
+    import ctypes as C
+    import torch
+    from paper_2409_16172_amd import binding
+    lib = binding.load_library()
+    op = ("none_inverse" if side == "none" else "left_inverse") if smallest else side
+    start = v0.clone()
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    steps = C.c_int(0)
+    inner_short = False
+    best, best_rel, runs, reason = 0j, float("inf"), 0, "restarts"
+    for r in range(max_restarts + 1):
+        if time.perf_counter() > deadline:
+            reason = "time budget"
+            break
+        code = lib.hp_arnoldi(plan._h, C.c_void_p(start.data_ptr()), int(m), binding.ARNOLDI_OPS[op],
+                              C.c_void_p(H.ctypes.data), C.byref(steps), binding._stream(None))
+        if code == binding.HP_E_NOT_CONVERGED:
+            inner_short = True
+        elif code != binding.HP_OK:
+            raise binding.HelmpreError(code, "hp_arnoldi")
+        runs += 1
+        k = steps.value
+        theta, Y, res = binding.ritz_pairs(H, k)
+        w = int(np.argmax(np.abs(theta)))
+        best = complex(theta[w])
+        best_rel = float(res[w] / abs(theta[w])) if abs(theta[w]) > 0 else float("inf")
+        if best_rel <= tol or k < m:
+            reason = "converged" if best_rel <= tol else "invariant subspace"
+            break
+        start = plan.arnoldi_vector(Y[w], out=start)
+    lam = (1.0 / best if abs(best) > 0 else complex("inf")) if smallest else best
+    conv = best_rel <= tol and not inner_short
+    if inner_short and reason == "converged":
+        reason = "inner solves stopped above their tolerance"
+    torch.cuda.synchronize()
+    return lam, best_rel, runs, conv, reason
+
+
 def spectrum(args, dev):
     """Spectral condition numbers of Eqn. Cond (Section 5) on the Example 1 media, the
     sweeps of Tables 2-6: frequency (PPW 12), points per wavelength (omega = 80 pi),
@@ -443,12 +494,16 @@ def spectrum(args, dev):
                 p = binding.plan_from_workload(w, m_real=mm if side != "none" else 8)
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                hi = p.extreme_eigenvalue(v0, False, side, m, args.spec_restarts, args.spec_tol)
+                # each end of each entry has its own wall-clock budget, checked between restarts
+                hi = restarted_extreme(p, v0, False, side, m, args.spec_restarts, args.spec_tol,
+                                       t + args.spec_entry_seconds)
                 if side == "none" and not args.spec_pn_inverse:
                     # every eigenvalue of P_N has imaginary part omega a: min |lambda| >= omega a
-                    lo = (complex(0.0, w.omega * kw["a"]), float("nan"), 0, False)
+                    lo = (complex(0.0, w.omega * kw["a"]), float("nan"), 0, False, "bound")
                 else:
-                    lo = p.extreme_eigenvalue(v0, True, side, args.spec_m_inv, args.spec_restarts, args.spec_tol)
+                    t_lo = time.perf_counter()
+                    lo = restarted_extreme(p, v0, True, side, args.spec_m_inv, args.spec_restarts, args.spec_tol,
+                                           t_lo + args.spec_entry_seconds)
                 dt = time.perf_counter() - t
                 cond = abs(hi[0]) / abs(lo[0])
                 det = {"max": hi[0], "min": lo[0], "max_rel_resid": hi[1], "min_rel_resid": lo[1],
@@ -457,7 +512,8 @@ def spectrum(args, dev):
                 runs += det["runs"]
                 e = {"cond": cond, "max_abs": abs(det["max"]), "min_abs": abs(det["min"]),
                      "max_rel_resid": det["max_rel_resid"], "min_rel_resid": det["min_rel_resid"],
-                     "converged": det["converged"], "arnoldi_runs": det["runs"], "seconds": dt}
+                     "converged": det["converged"], "arnoldi_runs": det["runs"], "seconds": dt,
+                     "max_end": hi[4], "min_end": lo[4]}
                 if side == "none":
                     e["omega_a"] = w.omega * kw["a"]
                     e["cond_upper_bound"] = abs(det["max"]) / e["omega_a"]
@@ -465,8 +521,11 @@ def spectrum(args, dev):
                 tab.setdefault(rname, {})[cname] = e
                 print(f"[bench] spectrum {tname} {cname} N={w.shape[0]} {rname}: cond {cond:.3g} "
                       f"(|lambda| in [{e['min_abs']:.4g}, {e['max_abs']:.4g}], residuals "
-                      f"{e['min_rel_resid']:.1e}/{e['max_rel_resid']:.1e}, {det['runs']} runs, {dt:.2f} s)",
-                      file=sys.stderr, flush=True)
+                      f"{e['min_rel_resid']:.1e}/{e['max_rel_resid']:.1e}, {det['runs']} runs, {dt:.2f} s, "
+                      f"ends: {hi[4]} / {lo[4]})", file=sys.stderr, flush=True)
+                # every entry is written as soon as it is known, so a run cut short keeps it
+                print(json.dumps({"mode": "spectrum_entry", "table": tname, "column": cname, "row": rname,
+                                  "n": w.shape[0], **e}), flush=True)
                 p.close()
             del v0
         out[tname] = tab
@@ -595,6 +654,8 @@ def main():
     ap.add_argument("--spec-m", type=int, default=64, help="Arnoldi steps per run")
     ap.add_argument("--spec-tol", type=float, default=1e-4, help="relative residual of a converged end")
     ap.add_argument("--spec-restarts", type=int, default=10)
+    ap.add_argument("--spec-entry-seconds", type=float, default=20.0,
+                    help="wall-clock budget of each end of each spectrum entry (checked between restarts)")
     ap.add_argument("--spec-m-inv", type=int, default=16, help="Arnoldi steps per run on the inverse")
     ap.add_argument("--spec-max-n", type=int, default=480, help="largest grid of the sweeps")
     ap.add_argument("--spec-pn-inverse", action="store_true",

@@ -313,6 +313,22 @@ typedef struct hp_solver_s* hp_solver;
 hp_status hp_solver_create(hp_solver* out, hp_plan p, int nrhs, const hp_solve_opts* opts);
 hp_status hp_solver_start(hp_solver s, const void* f, void* x, void* stream);
 hp_status hp_solver_advance(hp_solver s, int max_steps, int* finished);
+/* Batching of several solves (different grids, media and frequencies) into shared
+ * launches: like hp_solver_advance for each of the n distinct solvers s[0..n-1],
+ * without waiting for the device, but every round takes the next Arnoldi step of all
+ * of them that are ready for one, and the steps of the solvers the grouped kernels
+ * take run as one launch per pass over all of them (passes A, A', B, M, C of Q_M in
+ * Eqn. 403, the Gram-Schmidt sweep with the stencil P_N, the least-squares update and
+ * the basis update; at most 8 per launch).  Those are: one right-hand side, right
+ * preconditioning (HP_RIGHT), a mixed-precision plan, grids of at most 2^21 points
+ * with power-of-two lines of 256-1024 points (2-D) or 128-512 (3-D), restart <= 32,
+ * the combine's built-in workgroup shape (single solves of such sessions run the same
+ * kernels as a group of one).  The others step with their own launches in the same
+ * rounds.  The solvers started on one stream form one group, launched on that stream;
+ * groups on different streams overlap on the device.  Results are bitwise those of
+ * hp_solver_advance.  HP_E_INVALID for a solver not started or listed twice.
+ * finished: n entries (may be NULL), 1 where the solve has ended. */
+hp_status hp_solver_advance_group(hp_solver* s, int n, int max_steps, int* finished);
 hp_status hp_solver_wait(hp_solver s, hp_solve_info* info);
 hp_status hp_solver_destroy(hp_solver s);
 

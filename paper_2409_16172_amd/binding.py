@@ -27,7 +27,7 @@ EXPORTED = ["hp_plan_create", "hp_plan_workspace_bytes", "hp_solve_workspace_byt
             "hp_status_str", "hp_last_error", "hp_solver_create", "hp_solver_start", "hp_solver_advance",
             "hp_solver_wait", "hp_solver_destroy", "hp_arnoldi", "hp_ritz_values",
             "hp_arnoldi_vector", "hp_extreme_eigenvalue", "hp_plan_autotune", "hp_plan_time_pass",
-            "hp_plan_pass_times", "hp_apply_precond_static"]
+            "hp_plan_pass_times", "hp_apply_precond_static", "hp_solver_advance_group"]
 
 
 class HpGrid(C.Structure):
@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH):
     lib.hp_solver_start.restype = i
     lib.hp_solver_advance.argtypes = [vp, i, C.POINTER(i)]
     lib.hp_solver_advance.restype = i
+    lib.hp_solver_advance_group.argtypes = [C.POINTER(vp), i, i, C.POINTER(i)]
+    lib.hp_solver_advance_group.restype = i
     lib.hp_solver_wait.argtypes = [vp, C.POINTER(HpSolveInfo)]
     lib.hp_solver_wait.restype = i
     lib.hp_solver_destroy.argtypes = [vp]
@@ -493,6 +495,20 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def advance_group(solvers, max_steps=4):
+    """Advance several started Solver sessions together (hp_solver_advance_group): each
+    round takes the next step of every one that is ready, those the grouped kernels take
+    in one launch per pass.  All must have been started on the same stream.  Returns the
+    list of finished flags."""
+    n = len(solvers)
+    if n == 0:
+        return []
+    hs = (C.c_void_p * n)(*[s._h for s in solvers])
+    fin = (C.c_int * n)()
+    _check(load_library().hp_solver_advance_group(hs, n, int(max_steps), fin), "hp_solver_advance_group")
+    return [bool(v) for v in fin]
 
 
 def ritz_values(H, steps, harmonic=False):

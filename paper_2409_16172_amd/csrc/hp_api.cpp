@@ -696,6 +696,13 @@ constexpr unsigned kSolverEventFlags = HP_SOLVER_EVENT_FLAGS;
 #endif
 constexpr bool kFuseStencil = HP_FUSE_STENCIL != 0;
 constexpr size_t kFuseStencilMaxPts = (size_t)1 << 20;
+// Grids of grouped steps (hp_solver_advance_group): up to 1024^2 and 128^3; their
+// steps always compute the stencil inside the sweep.
+constexpr size_t kGroupMaxPts = (size_t)1 << 21;
+#ifndef HP_SOLO_GROUPED
+#define HP_SOLO_GROUPED 1
+#endif
+constexpr bool kSoloGrouped = HP_SOLO_GROUPED != 0;
 
 // Pass timer: launches recorded per read at most (later ones are not timed).
 constexpr size_t kMaxTimedLaunches = 1 << 16;
@@ -1140,6 +1147,10 @@ struct Session {
       if ((e = run_stencil(P, 0, vj, vrs, pv, np, nullptr, nrhs, K.skip_step, s)) != hipSuccess) return e;
       if ((e = run_apply(P, pv, 0, np, vj1, 0, vrs, false, nrhs, K.skip_step, s)) != hipSuccess) return e;
     } else {                          // w = P_N Q u_j, the stencil fused with the sweep
+      // a step the grouped kernels take runs them (as a group of one), so that it gives
+      // bitwise the result of the same step inside a grouped launch
+      hp::GroupMember gm;
+      if (kSoloGrouped && group_member(&gm)) return hp::launch_group_step(&gm, 1, s);
       if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, s)) != hipSuccess)
         return e;
       if (kFuseStencil && np <= kFuseStencilMaxPts) {
@@ -1265,25 +1276,26 @@ struct Session {
     return true;
   }
 
-  // Enqueue up to max_steps Arnoldi steps (and the cycle transitions they
-  // reach).  block = false never waits: it returns when the next action needs
-  // a result the device has not produced yet.
-  hipError_t advance(int max_steps, bool block) {
-    hipError_t e = hipSuccess;
-    int steps = 0;
+  // Enqueue the cycle transitions that are due, up to the point where the next
+  // action is an Arnoldi step (kPollStep), needs a result the device has not
+  // produced yet (kPollWait; only with block = false) or the solve has ended
+  // (kPollDone).
+  enum Poll { kPollStep, kPollWait, kPollDone };
+  Poll poll(bool block, hipError_t& e) {
+    e = hipSuccess;
     while (phase != kFinished) {
       if (phase == kCycleStart) {
-        if (!ready(W->cyc_ev, block, e)) return e;
+        if (!ready(W->cyc_ev, block, e)) return kPollWait;
         if (all(K.host_done) || cycles_run >= o.max_cycles) {
           phase = kFinished;
           if (o.side == HP_LEFT && !rhs_prec) {   // the true residual of the returned x
             cpx<double>* r = (cpx<double>*)W->tvec.p;
-            if ((e = run_stencil(P, 3, x, P->npts, r, P->npts, f, nrhs, nullptr, st)) != hipSuccess) return e;
-            if ((e = hp::launch_plain_norm(K, r, P->npts, 1, st)) != hipSuccess) return e;
+            if ((e = run_stencil(P, 3, x, P->npts, r, P->npts, f, nrhs, nullptr, st)) != hipSuccess) return kPollWait;
+            if ((e = hp::launch_plain_norm(K, r, P->npts, 1, st)) != hipSuccess) return kPollWait;
           }
-          return hipSuccess;
+          return kPollDone;
         }
-        if ((e = hp::launch_scale_v0(K, st)) != hipSuccess) return e;
+        if ((e = hp::launch_scale_v0(K, st)) != hipSuccess) return kPollWait;
         j = 0;
         phase = kArnoldi;
         continue;
@@ -1292,28 +1304,100 @@ struct Session {
       if (j >= o.restart) {
         if (arnoldi_only) {
           phase = kFinished;
-          return hipSuccess;
+          return kPollDone;
         }
-        if ((e = enqueue_cycle_end()) != hipSuccess) return e;
+        if ((e = enqueue_cycle_end()) != hipSuccess) return kPollWait;
         continue;
       }
       if (j >= SolverWs::kLag && (throttle || !block)) {
         // keep at most kLag steps in flight; end the cycle once every
         // right-hand side has ended it
-        if (!ready(W->step_ev[(j - SolverWs::kLag) % (SolverWs::kLag + 1)], block, e)) return e;
+        if (!ready(W->step_ev[(j - SolverWs::kLag) % (SolverWs::kLag + 1)], block, e)) return kPollWait;
         if (all(K.host_stop)) {
           if (arnoldi_only) {
             phase = kFinished;
-            return hipSuccess;
+            return kPollDone;
           }
-          if ((e = enqueue_cycle_end()) != hipSuccess) return e;
+          if ((e = enqueue_cycle_end()) != hipSuccess) return kPollWait;
           continue;
         }
       }
+      return kPollStep;
+    }
+    return kPollDone;
+  }
+
+  // Enqueue up to max_steps Arnoldi steps (and the cycle transitions they
+  // reach).  block = false never waits: it returns when the next action needs
+  // a result the device has not produced yet.
+  hipError_t advance(int max_steps, bool block) {
+    hipError_t e = hipSuccess;
+    int steps = 0;
+    while (true) {
+      if (poll(block, e) != kPollStep || e != hipSuccess) return e;
       if (steps >= max_steps) return hipSuccess;
       if ((e = enqueue_step()) != hipSuccess) return e;
       ++steps;
     }
+  }
+
+  // This session's current Arnoldi step as a member of a grouped launch, when the
+  // grouped kernels take it: one right-hand side, right preconditioning, the FP32
+  // preconditioner, grids of at most kGroupMaxPts points with power-of-two lines the
+  // grouped passes cover, and the combine's built-in workgroup shape.
+  bool group_member(hp::GroupMember* g) const {
+    if (o.side != HP_RIGHT || arnoldi_only || nrhs != 1 || P->prec != HP_MIXED || P->tune[4].ng > 1 ||
+        W->z.p == nullptr || P->npts > kGroupMaxPts)
+      return false;
+    hp::GroupMember m{};
+    m.dim = P->dim;
+    for (int d = 0; d < 3; ++d) m.n[d] = P->n[d];
+    m.npts = P->npts;
+    m.K = P->K;
+    m.M = P->M;
+    m.Mt = P->Mt;
+    m.mo = P->mo;
+    m.order = P->order;
+    m.Ma = P->Ma;
+    m.interp = P->Ma >= 2 ? 2 : (P->order >= 2 ? 1 : 0);
+    m.scale = 1.0 / (double)P->npts;
+    for (int d = 0; d < P->dim; ++d) m.tw[d] = P->tw(d);
+    m.lam_ax = (const double*)P->lam_ax.p;
+    m.lam_in = (const double*)P->lam_in.p;
+    m.nodes = (const hp::NodeConst*)P->nodes.p;
+    m.store_mask = (const uint16_t*)P->storemask.p;
+    m.slab_need = (const uint8_t*)P->slabneed.p;
+    m.pos = (const double*)P->pos.p;
+    m.posa = (const double*)P->posa.p;
+    m.grpmask = (const uint64_t*)P->grpmask.p;
+    m.rowmask = (const uint64_t*)P->rowmask.p;
+    m.lag = (const double*)P->lagtab.p;
+    m.coef32 = P->coef32.p;
+    for (int d = 0; d < 3; ++d) {
+      const double h = P->len[d] / P->n[d];
+      m.ih2[d] = d < P->dim ? 1.0 / (h * h) : 0.0;
+    }
+    m.t = P->t.p;
+    m.fields = P->fields.p;
+    m.z = W->z.p;
+    m.V = K.V;
+    m.state = K.state;
+    m.part = K.part;
+    m.skip_step = K.skip_step;
+    m.host_stop = K.host_stop;
+    m.j = j;
+    m.restart = o.restart;
+    m.ng_b = P->tune[2].ng;
+    if (!hp::group_member_ok(m)) return false;
+    *g = m;
+    return true;
+  }
+
+  // After a grouped launch that included this session's step j.
+  hipError_t stepped_in_group() {
+    hipError_t e = hipEventRecord(W->step_ev[j % (SolverWs::kLag + 1)], st);
+    if (e != hipSuccess) return e;
+    ++j;
     return hipSuccess;
   }
 
@@ -1507,6 +1591,67 @@ hp_status hp_solver_advance(hp_solver s, int max_steps, int* finished) {
   if (!s || max_steps < 0 || s->sess.phase == Session::kIdle) return HP_E_INVALID;
   HP_TRY(s->sess.advance(max_steps, false));
   if (finished) *finished = s->sess.phase == Session::kFinished;
+  return HP_OK;
+}
+
+hp_status hp_solver_advance_group(hp_solver* ss, int n, int max_steps, int* finished) {
+  if (!ss || n < 1 || max_steps < 0) return HP_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    if (!ss[i] || ss[i]->sess.phase == Session::kIdle) return HP_E_INVALID;
+    for (int k = 0; k < i; ++k)
+      if (ss[k] == ss[i]) return HP_E_INVALID;
+  }
+  // the sessions of one stream form a group (several groups on several streams overlap)
+  std::vector<hipStream_t> streams;
+  std::vector<int> gidx(n);
+  for (int i = 0; i < n; ++i) {
+    size_t g = 0;
+    while (g < streams.size() && streams[g] != ss[i]->sess.st) ++g;
+    if (g == streams.size()) streams.push_back(ss[i]->sess.st);
+    gidx[i] = (int)g;
+  }
+  std::vector<std::vector<hp::GroupMember>> grp(streams.size());
+  std::vector<std::vector<Session*>> who(streams.size());
+  for (int round = 0; round < max_steps; ++round) {
+    for (size_t g = 0; g < streams.size(); ++g) {
+      grp[g].clear();
+      who[g].clear();
+    }
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      Session& S = ss[i]->sess;
+      hipError_t e;
+      const Session::Poll r = S.poll(false, e);
+      HP_TRY(e);
+      if (r != Session::kPollStep) continue;
+      any = true;
+      hp::GroupMember m;
+      if (S.group_member(&m)) {
+        grp[gidx[i]].push_back(m);
+        who[gidx[i]].push_back(&S);
+      } else {
+        HP_TRY(S.enqueue_step());   // a session the grouped kernels do not take steps alone
+      }
+    }
+    for (size_t g = 0; g < streams.size(); ++g)
+      for (size_t g0 = 0; g0 < grp[g].size(); g0 += hp::kMaxGroup) {
+        const int cnt = (int)std::min(grp[g].size() - g0, (size_t)hp::kMaxGroup);
+        if (cnt == 1) {
+          HP_TRY(who[g][g0]->enqueue_step());   // alone: the same kernels as a group of one
+          continue;
+        }
+        HP_TRY(hp::launch_group_step(&grp[g][g0], cnt, streams[g]));
+        for (int q = 0; q < cnt; ++q) HP_TRY(who[g][g0 + q]->stepped_in_group());
+      }
+    if (!any) break;
+  }
+  // cycle transitions that became due after the last step
+  for (int i = 0; i < n; ++i) {
+    hipError_t e;
+    (void)ss[i]->sess.poll(false, e);
+    HP_TRY(e);
+    if (finished) finished[i] = ss[i]->sess.phase == Session::kFinished;
+  }
   return HP_OK;
 }
 

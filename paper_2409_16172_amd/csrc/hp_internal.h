@@ -208,6 +208,48 @@ hipError_t launch_backsolve(const KrylovArgs& a, hipStream_t st);
 hipError_t launch_plain_norm(const KrylovArgs& a, const cpx<double>* w, size_t wrs, int which, hipStream_t st);
 hipError_t launch_lincomb(const KrylovArgs& a, cpx<double>* out, size_t out_rs, bool accumulate, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// ---- grouped Arnoldi steps (several solver sessions, any mix of the grids below,
+// one launch per pass) ----
+constexpr int kMaxGroup = 8;
+// One right-hand side of a right-preconditioned session whose preconditioner runs in
+// FP32 (mixed precision): its plan's tables and its buffers for the current step j.
+struct GroupMember {
+  int dim, n[3];
+  size_t npts;
+  int K, M, Mt, mo, order, Ma;
+  int interp;                 // InterpMode of the combine
+  double scale;               // 1 / npts
+  const void* tw[3];          // FP32 twiddles per axis
+  const double* lam_ax;
+  const double* lam_in;
+  const NodeConst* nodes;
+  const uint16_t* store_mask;
+  const uint8_t* slab_need;
+  const double* pos;
+  const double* posa;
+  const uint64_t* grpmask;
+  const uint64_t* rowmask;
+  const double* lag;
+  const void* coef32;         // stencil coefficients {gamma^2, beta} in FP32
+  double ih2[3];
+  void* t;                    // pass A output
+  void* fields;               // node fields
+  void* z;                    // Q u_j (complex64)
+  cpx<double>* V;             // the member's basis
+  KState* state;
+  cpx<double>* part;
+  int* skip_step;
+  int* host_stop;
+  int j, restart;
+  int ng_b;                   // node groups of the symbol pass (0: the single-plan choice)
+};
+// Whether a member's grid and options are ones the grouped kernels take (the grouped
+// step then gives bitwise the result of the member's own step).
+bool group_member_ok(const GroupMember& m);
+// Arnoldi step of every member (count <= kMaxGroup): passes A (A'), B, (M), C, the
+// dot-product sweep with the stencil, the finishing kernel and the update, one
+// launch each over all members.
+hipError_t launch_group_step(const GroupMember* m, int count, hipStream_t st);
 // Device address of this device's copy of the static apply workspace
 // (HP_STATIC_SCRATCH_BYTES), looked up once per device, on the current device.
 hipError_t static_scratch(void** out);

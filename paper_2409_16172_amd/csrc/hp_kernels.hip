@@ -113,18 +113,16 @@ using ColsCfg = std::conditional_t<MODE == 1, SymCfg<R, N>, ColCfg<R, N, 1024>>;
 #endif
 
 // ---------------------------------------------------------------- pass A
+// Pass bodies take their workgroup's indices and LDS as arguments, so that the
+// grouped launches (several plans, several line lengths in one launch) run the
+// same code as the single-plan kernels.
 template <typename R, typename TI, int N>
-__global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_fwd(const cpx<TI>* __restrict__ in,
-                                                                  cpx<R>* __restrict__ out, int rows,
-                                                                  size_t in_rs, size_t out_rs,
-                                                                  const cpx<R>* __restrict__ tw,
-                                                                  const int* __restrict__ skip) {
+__device__ __forceinline__ void rows_fwd_body(const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int rows,
+                                              size_t in_rs, size_t out_rs, const cpx<R>* __restrict__ tw, int bx,
+                                              int rhs, cpx<R>* lds) {
   using C = RowCfg<R, N>;
-  __shared__ cpx<R> lds[C::LDS];
-  const int rhs = blockIdx.y;
-  if (skip != nullptr && skip[rhs] != 0) return;
   const int g = threadIdx.x / C::T, j = threadIdx.x % C::T;
-  const int row = blockIdx.x * C::G + g;
+  const int row = bx * C::G + g;
   const bool act = row < rows;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)row * N;
   cpx<R> x[C::E];
@@ -136,6 +134,18 @@ __global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_fwd(const cpx<
 #pragma unroll
     for (int s = 0; s < C::E; ++s) dst[j + C::T * s] = x[s];
   }
+}
+
+template <typename R, typename TI, int N>
+__global__ __launch_bounds__((RowCfg<R, N>::THREADS)) void k_rows_fwd(const cpx<TI>* __restrict__ in,
+                                                                  cpx<R>* __restrict__ out, int rows,
+                                                                  size_t in_rs, size_t out_rs,
+                                                                  const cpx<R>* __restrict__ tw,
+                                                                  const int* __restrict__ skip) {
+  __shared__ cpx<R> lds[RowCfg<R, N>::LDS];
+  const int rhs = blockIdx.y;
+  if (skip != nullptr && skip[rhs] != 0) return;
+  rows_fwd_body<R, TI, N>(in, out, rows, in_rs, out_rs, tw, blockIdx.x, rhs, lds);
 }
 
 // ---------------------------------------------------------------- strided passes
@@ -177,41 +187,46 @@ __device__ __forceinline__ void symbol_mul(const cpx<R> (&vh)[E], cpx<R> (&x)[E]
   }
 }
 
+// The column pass of one workgroup: (bx, by, bz) and (gx, gy) stand for blockIdx
+// and gridDim.
+template <typename R, int N, int MODE>
+constexpr int cols_smask_words() {
+  return MODE == 1 ? kMaxNodes * ColsCfg<R, N, MODE>::T : 1;
+}
+
 template <typename R, typename TI, int N, int DIR, int MODE>
-__global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
+__device__ __forceinline__ void cols_body(
     const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
     size_t out_rs, size_t in_fs, size_t out_fs, const cpx<R>* __restrict__ tw,
     const int* __restrict__ skip, const double* __restrict__ lam_ax, const double* __restrict__ lam_in,
     const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
-    const uint8_t* __restrict__ slab_need) {
+    const uint8_t* __restrict__ slab_need, int bx, int by, int bz, int gx, int gy, cpx<R>* lds, uint16_t* smask) {
   using C = ColsCfg<R, N, MODE>;
-  __shared__ cpx<R> lds[C::LDS];
-  const int z = blockIdx.z;
+  const int z = bz;
   const int rhs = (MODE == 0) ? z / nfields : z;
   const int fld = (MODE == 0) ? z % nfields : 0;
   if (skip != nullptr && skip[rhs] != 0) return;
   // plain passes over node fields: slabs whose points never use this node are skipped
-  if (MODE == 0 && slab_need != nullptr && slab_need[(size_t)fld * gridDim.y + blockIdx.y] == 0) return;
+  if (MODE == 0 && slab_need != nullptr && slab_need[(size_t)fld * gy + by] == 0) return;
   const int g = threadIdx.x % C::TC, j = threadIdx.x / C::TC;
   // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
   // L2).  Give the workgroups of one XCD consecutive column tiles so that tiles
   // sharing cache lines meet in the same L2.
-  int tile = blockIdx.x;
+  int tile = bx;
 #if HP_XCD_REMAP
-  if ((gridDim.x & 7) == 0) tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  if ((gx & 7) == 0) tile = (bx & 7) * (gx >> 3) + (bx >> 3);
 #endif
   const int c = tile * C::TC + g;
   const bool act = c < S;
-  // MODE 0: blockIdx.y is the outer (slab) index.  MODE 1 (outer = 1): blockIdx.y
-  // is the node group; small grids split the nodes over several workgroups per
-  // column tile (each redoes the forward transform) so that the launch fills the GPU.
-  const size_t obase = (MODE == 0 ? (size_t)blockIdx.y * N * S : 0) + c;
+  // MODE 0: by is the outer (slab) index.  MODE 1 (outer = 1): by is the node
+  // group; small grids split the nodes over several workgroups per column tile
+  // (each redoes the forward transform) so that the launch fills the GPU.
+  const size_t obase = (MODE == 0 ? (size_t)by * N * S : 0) + c;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
   cpx<R>* lg = lds + g;   // the TC columns are interleaved in LDS
   // Symbol pass: the store masks of all nodes are staged in LDS up front, so that
   // the node loop issues no global load (waiting for one would also wait for the
   // previous node's stores: vector memory operations retire in order).
-  __shared__ uint16_t smask[MODE == 1 ? kMaxNodes * C::T : 1];
   if constexpr (MODE == 1) {
     for (int i = threadIdx.x; i < K * C::T; i += C::THREADS) smask[i] = store_mask[i];
     __syncthreads();
@@ -238,7 +253,7 @@ __global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
       lam[s] = lam_ax[j + C::T * s] + lc;
     }
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
-    const int n_lo = (int)(((long)blockIdx.y * K) / gridDim.y), n_hi = (int)(((long)(blockIdx.y + 1) * K) / gridDim.y);
+    const int n_lo = (int)(((long)by * K) / gy), n_hi = (int)(((long)(by + 1) * K) / gy);
     for (int n = n_lo; n < n_hi; ++n) {
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
       fft_e<R, N, C::E, +1, false, C::TC>(x, lg, j, tw);
@@ -249,6 +264,20 @@ __global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
         if ((m >> s) & 1u) dst[(size_t)n * out_fs + (size_t)(j + C::T * s) * S] = x[s];
     }
   }
+}
+
+template <typename R, typename TI, int N, int DIR, int MODE>
+__global__ __launch_bounds__((ColsCfg<R, N, MODE>::THREADS)) void k_cols(
+    const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
+    size_t out_rs, size_t in_fs, size_t out_fs, const cpx<R>* __restrict__ tw,
+    const int* __restrict__ skip, const double* __restrict__ lam_ax, const double* __restrict__ lam_in,
+    const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
+    const uint8_t* __restrict__ slab_need) {
+  __shared__ cpx<R> lds[ColsCfg<R, N, MODE>::LDS];
+  __shared__ uint16_t smask[cols_smask_words<R, N, MODE>()];
+  cols_body<R, TI, N, DIR, MODE>(in, out, S, nfields, in_rs, out_rs, in_fs, out_fs, tw, skip, lam_ax, lam_in, nodes,
+                                 K, scale, store_mask, slab_need, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x,
+                                 gridDim.y, lds, smask);
 }
 
 // ---------------------------------------------------------------- pass C
@@ -342,19 +371,24 @@ constexpr bool combine_splits_fit() {
 }
 constexpr int kCombineSplits = 4;
 
-template <typename R, typename TO, int N, bool ACC, int IM, int NS = 1>
-__global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
+template <typename R, int N, int NS>
+constexpr int combine_lds_elems() {
+  using C = CombCfg<R, N>;
+  constexpr int XCH = NS * C::LDS, RED = (NS - 1) * C::G * N;
+  return XCH > RED ? XCH : RED;
+}
+
+// bx: the row group (blockIdx.x of the single-plan kernel)
+template <typename R, typename TO, int N, bool ACC, int IM, int NS>
+__device__ __forceinline__ void rows_combine_body(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
     const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
     size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
-    const int* __restrict__ skip, int ord, const double* __restrict__ lag, const double* __restrict__ posa, int Ma) {
+    const int* __restrict__ skip, int ord, const double* __restrict__ lag, const double* __restrict__ posa, int Ma,
+    int bx, int rhs, cpx<R>* lds, double* slag) {
   using C = CombCfg<R, N>;
   static_assert(NS == 1 || combine_splits_fit<R, N>(), "node splits need transforms within one wavefront");
   constexpr bool LAG = IM == kInterpLagrange;
-  constexpr int XCH = NS * C::LDS, RED = (NS - 1) * C::G * N;
-  __shared__ cpx<R> lds[XCH > RED ? XCH : RED];
-  __shared__ double slag[LAG ? kLagTable : 1];
-  const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
   if constexpr (LAG) {
     for (int i = threadIdx.x; i < kLagTable; i += C::THREADS * NS) slag[i] = lag[i];
@@ -363,7 +397,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
   const int sp = NS > 1 ? (int)threadIdx.x / C::THREADS : 0;
   const int tl = NS > 1 ? (int)threadIdx.x % C::THREADS : (int)threadIdx.x;
   const int g = tl / C::T, j = tl % C::T;
-  const int row = blockIdx.x * C::G + g;
+  const int row = bx * C::G + g;
   const bool act = row < rows;
   const size_t rbase = (size_t)row * N;
   int ab[C::E];
@@ -381,7 +415,7 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
     }
     acc[s] = {0, 0};
   }
-  const uint64_t mask = grpmask[blockIdx.x];
+  const uint64_t mask = grpmask[bx];
   const uint64_t rmask = act ? rowmask[row] : 0ull;
   const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
   cpx<R>* lg = lds + (sp * C::G + g) * lds_elems<R>(N);
@@ -463,6 +497,18 @@ __global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
   }
 }
 
+template <typename R, typename TO, int N, bool ACC, int IM, int NS = 1>
+__global__ __launch_bounds__((CombCfg<R, N>::THREADS * NS)) void k_rows_combine(
+    const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
+    const uint64_t* __restrict__ grpmask, const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out,
+    size_t out_rs, int rows, int K, int M, int Mt, int mo, const cpx<R>* __restrict__ tw,
+    const int* __restrict__ skip, int ord, const double* __restrict__ lag, const double* __restrict__ posa, int Ma) {
+  __shared__ cpx<R> lds[combine_lds_elems<R, N, NS>()];
+  __shared__ double slag[IM == kInterpLagrange ? kLagTable : 1];
+  rows_combine_body<R, TO, N, ACC, IM, NS>(fields, fs, frs, pos, grpmask, rowmask, out, out_rs, rows, K, M, Mt, mo, tw,
+                                           skip, ord, lag, posa, Ma, blockIdx.x, blockIdx.y, lds, slag);
+}
+
 // ---------------------------------------------------------------- wave-resident lines
 // A line of N = 64 E points held by one wavefront, E elements per lane (E = 16 at
 // N = 1024): every exchange of its transform stays inside the wavefront, so the
@@ -487,24 +533,22 @@ constexpr int kWaveRows = 4;   // rows (one per wavefront) per workgroup of the 
 // Pass C with one row per wavefront: inverse transform of each node row the row
 // uses (its own node list, not its workgroup's) and the weighted sum; loads and
 // stores of a wavefront cover 64 E consecutive elements.
-template <typename R, typename TO, int N, bool ACC, int IM>
-__global__ __launch_bounds__(64 * kWaveRows, 2) void k_comb_wave(
+// WR rows per workgroup (one per wavefront); bx: the workgroup's row block
+template <typename R, typename TO, int N, bool ACC, int IM, int WR>
+__device__ __forceinline__ void comb_wave_body(
     const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
     const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out, size_t out_rs, int rows, int M, int Mt,
     int mo, const cpx<R>* tw, const int* __restrict__ skip, int ord, const double* __restrict__ lag,
-    const double* __restrict__ posa, int Ma) {
+    const double* __restrict__ posa, int Ma, int bx, int rhs, cpx<R>* lds, double* slag) {
   constexpr int E = WaveLine<R, N>::E;
   constexpr bool LAG = IM == kInterpLagrange;
-  __shared__ cpx<R> lds[kWaveRows * WaveLine<R, N>::LDS];
-  __shared__ double slag[LAG ? kLagTable : 1];
-  const int rhs = blockIdx.y;
   if (skip != nullptr && skip[rhs] != 0) return;
   if constexpr (LAG) {
-    for (int i = threadIdx.x; i < kLagTable; i += 64 * kWaveRows) slag[i] = lag[i];
+    for (int i = threadIdx.x; i < kLagTable; i += 64 * WR) slag[i] = lag[i];
     __syncthreads();
   }
   const int wv = (int)threadIdx.x / 64, j = (int)threadIdx.x % 64;
-  const int row = blockIdx.x * kWaveRows + wv;
+  const int row = bx * WR + wv;
   if (row >= rows) return;   // no workgroup barrier follows
   const size_t rbase = (size_t)row * N;
   int ab[E];
@@ -545,6 +589,18 @@ __global__ __launch_bounds__(64 * kWaveRows, 2) void k_comb_wave(
       dst[j + 64 * s] = cvt<TO>(acc[s]);
     }
   }
+}
+
+template <typename R, typename TO, int N, bool ACC, int IM>
+__global__ __launch_bounds__(64 * kWaveRows, 2) void k_comb_wave(
+    const cpx<R>* __restrict__ fields, size_t fs, size_t frs, const double* __restrict__ pos,
+    const uint64_t* __restrict__ rowmask, cpx<TO>* __restrict__ out, size_t out_rs, int rows, int M, int Mt,
+    int mo, const cpx<R>* tw, const int* __restrict__ skip, int ord, const double* __restrict__ lag,
+    const double* __restrict__ posa, int Ma) {
+  __shared__ cpx<R> lds[kWaveRows * WaveLine<R, N>::LDS];
+  __shared__ double slag[IM == kInterpLagrange ? kLagTable : 1];
+  comb_wave_body<R, TO, N, ACC, IM, kWaveRows>(fields, fs, frs, pos, rowmask, out, out_rs, rows, M, Mt, mo, tw, skip,
+                                               ord, lag, posa, Ma, blockIdx.x, blockIdx.y, lds, slag);
 }
 
 // ---------------------------------------------------------------- mixed-radix lines
@@ -1637,8 +1693,8 @@ constexpr int kHPacked = kMaxRestart * (kMaxRestart + 3) / 2;
 constexpr int kFinThreads = 1024;
 constexpr int kHPrefetch = ((kMaxRestart - 1) * (kMaxRestart + 1) + kFinThreads - 1) / kFinThreads;
 
-__device__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, int j, int restart,
-                                 int* skip_step, int* host_stop) {
+__device__ __forceinline__ void arnoldi_finalize(KState& S, const cpx<double>* part, int rhs, int j, int restart,
+                                                 int* skip_step, int* host_stop) {
   __shared__ cpx<double> sums[kPartSlots];
   __shared__ cpx<double> zz[kMaxRestart + 1], hp[kMaxRestart + 1], raw[kMaxRestart + 2];
   __shared__ cpx<double> hsh[kHPacked];
@@ -1844,13 +1900,13 @@ struct WStencil {
 // this block's partial-sum column.
 template <int NW, typename WSrc>
 __device__ __forceinline__ void arnoldi_dots_body(const cpx<double>* Vr, size_t npts, cpx<double>* pr, int j,
-                                                  const WSrc& wsrc) {
+                                                  const WSrc& wsrc, int bx) {
   __shared__ cpx<double> su[kDotsTile], sw[kDotsTile];
   __shared__ double red[NW][6];
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const cpx<double>* U = Vr + (size_t)j * npts;
   const size_t range = (npts + kRedBlocks - 1) / kRedBlocks;
-  const size_t r0 = (size_t)blockIdx.x * range;
+  const size_t r0 = (size_t)bx * range;
   const size_t r1 = r0 + range < npts ? r0 + range : npts;
   cpx<double> acc[2 * kDotsSlots];
 #pragma unroll
@@ -1936,7 +1992,7 @@ __global__ __launch_bounds__(NW * 64) void k_arnoldi_dots(const cpx<double>* __r
   if (skip_step[rhs]) return;
   const cpx<double>* Vr = V + (size_t)rhs * vrs;
   arnoldi_dots_body<NW>(Vr, npts, part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x, j,
-                        WStored{Vr + (size_t)(j + 1) * npts});
+                        WStored{Vr + (size_t)(j + 1) * npts}, blockIdx.x);
 }
 
 template <int NW, typename R, typename TI, int DIM>
@@ -1951,7 +2007,7 @@ __global__ __launch_bounds__(NW * 64) void k_arnoldi_dots_st(cpx<double>* V, siz
   cpx<double>* Vr = V + (size_t)rhs * vrs;
   arnoldi_dots_body<NW>(Vr, npts, part + (size_t)rhs * kPartSlots * kRedBlocks + blockIdx.x, j,
                         WStencil<R, TI, DIM>{z + (size_t)rhs * z_rs, coef, Vr + (size_t)(j + 1) * npts, n0, n1,
-                                             n2, ih0, ih1, ih2});
+                                             n2, ih0, ih1, ih2}, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_arnoldi_fin(const cpx<double>* __restrict__ part, int* __restrict__ skip_step,
@@ -2040,6 +2096,75 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(cpx<double>* __restrict_
     }
   }
 }
+
+
+// The update of k_arnoldi_update for the grouped launches (bx, gx: this workgroup's
+// index among the gx of one right-hand side).  The single-plan kernel keeps its own
+// copy: its code, and so its rounding, stays exactly as it was.
+__device__ __forceinline__ void arnoldi_update_body(cpx<double>* __restrict__ V, size_t npts, size_t vrs,
+                                                    const KState* __restrict__ state,
+                                                    const int* __restrict__ skip_step, int j, int rhs, int bx,
+                                                    int gx) {
+  __shared__ cpx<double> ca[kMaxRestart + 8], cc[kMaxRestart + 8];
+  const KState& S = state[rhs];
+  if (skip_step[rhs] && S.stop_at != j) return;
+  for (int i = threadIdx.x; i < kMaxRestart + 8; i += blockDim.x) {
+    ca[i] = i < j ? S.av[i] : cpx<double>{0.0, 0.0};
+    cc[i] = i < j ? S.cv[i] : cpx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  const double isg = S.inv_sigma;
+  const cpx<double> cu = S.cu;
+  cpx<double>* Vr = V + (size_t)rhs * vrs;
+  cpx<double>* U = Vr + (size_t)j * npts;
+  cpx<double>* W = Vr + (size_t)(j + 1) * npts;
+  constexpr size_t span = 256 * kUpdPts;
+  for (size_t base = (size_t)bx * span; base < npts; base += (size_t)gx * span) {
+    const size_t i0 = base + threadIdx.x;
+    if (base + span <= npts) {
+      cpx<double> sa[kUpdPts], sc[kUpdPts];
+#pragma unroll
+      for (int p = 0; p < kUpdPts; ++p) { sa[p] = {0.0, 0.0}; sc[p] = {0.0, 0.0}; }
+      for (int v0 = 0; v0 < j; v0 += kUpdChunk) {
+        cpx<double> x[kUpdChunk][kUpdPts];
+#pragma unroll
+        for (int t = 0; t < kUpdChunk; ++t) {
+          const int k = v0 + t < j ? v0 + t : j - 1;
+#pragma unroll
+          for (int p = 0; p < kUpdPts; ++p) x[t][p] = Vr[(size_t)k * npts + i0 + 256 * p];
+        }
+#pragma unroll
+        for (int t = 0; t < kUpdChunk; ++t) {
+          const cpx<double> a = ca[v0 + t], c = cc[v0 + t];
+#pragma unroll
+          for (int p = 0; p < kUpdPts; ++p) {
+            sa[p].re += a.re * x[t][p].re - a.im * x[t][p].im;
+            sa[p].im += a.re * x[t][p].im + a.im * x[t][p].re;
+            sc[p].re += c.re * x[t][p].re - c.im * x[t][p].im;
+            sc[p].im += c.re * x[t][p].im + c.im * x[t][p].re;
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < kUpdPts; ++p) update_point(U, W, i0 + 256 * p, sa[p], sc[p], isg, cu);
+    } else {
+      for (int p = 0; p < kUpdPts; ++p) {
+        const size_t i = i0 + 256 * p;
+        if (i >= npts) break;
+        cpx<double> sa = {0.0, 0.0}, sc = {0.0, 0.0};
+        for (int k = 0; k < j; ++k) {
+          const cpx<double> x = Vr[(size_t)k * npts + i], a = ca[k], c = cc[k];
+          sa.re += a.re * x.re - a.im * x.im;
+          sa.im += a.re * x.im + a.im * x.re;
+          sc.re += c.re * x.re - c.im * x.im;
+          sc.im += c.re * x.im + c.im * x.re;
+        }
+        update_point(U, W, i, sa, sc, isg, cu);
+      }
+    }
+  }
+}
+
 
 // y = R^{-1} g over the k finished columns (upper triangular back substitution),
 // with R and g staged in LDS.
@@ -2394,6 +2519,396 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   const size_t n = bytes / 4;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_zero, dim3(stream_blocks(n)), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- grouped steps
+// One launch per pass over several sessions of different grids and media (FP32
+// preconditioner, right preconditioning, one right-hand side each): the member
+// tables travel in the kernel arguments, each workgroup finds its member from the
+// block offsets and runs the same body as the member's own kernel, with the same
+// workgroup shape, so the results are bitwise those of the member's own step.
+// Line lengths: 256-1024 on 2-D grids, 128-512 on 3-D grids.
+template <typename D>
+struct GroupArgs {
+  int count;
+  D m[kMaxGroup];
+};
+
+template <typename D>
+__device__ __forceinline__ int group_member_of(const GroupArgs<D>& a) {
+  int q = 0;
+  while (q + 1 < a.count && (int)blockIdx.x >= a.m[q + 1].block0) ++q;
+  return q;
+}
+
+constexpr int group_rows_lds() {
+  return std::max({RowCfg<float, 128>::LDS, RowCfg<float, 256>::LDS, RowCfg<float, 512>::LDS,
+                   RowCfg<float, 1024>::LDS});
+}
+constexpr int group_cols_lds() {
+  return std::max({ColsCfg<float, 128, 1>::LDS, ColsCfg<float, 256, 1>::LDS, ColsCfg<float, 512, 1>::LDS,
+                   ColsCfg<float, 1024, 1>::LDS, ColsCfg<float, 128, 0>::LDS, ColsCfg<float, 256, 0>::LDS,
+                   ColsCfg<float, 512, 0>::LDS});
+}
+constexpr int group_cols_smask() {
+  return std::max({cols_smask_words<float, 128, 1>(), cols_smask_words<float, 256, 1>(),
+                   cols_smask_words<float, 512, 1>(), cols_smask_words<float, 1024, 1>()});
+}
+constexpr int group_comb_lds() {
+  return std::max({WaveLine<float, 256>::LDS, WaveLine<float, 512>::LDS, WaveLine<float, 1024>::LDS,
+                   combine_lds_elems<float, 128, 1>()});
+}
+static_assert(RowCfg<float, 128>::THREADS == 256 && RowCfg<float, 1024>::THREADS == 256, "grouped pass A shape");
+static_assert(ColsCfg<float, 128, 1>::THREADS == 256 && ColsCfg<float, 1024, 1>::THREADS == 256 &&
+                  ColsCfg<float, 128, 0>::THREADS == 256 && ColsCfg<float, 512, 0>::THREADS == 256,
+              "grouped column pass shape");
+static_assert(CombCfg<float, 128>::THREADS == 64, "grouped combine shape");
+
+struct GRowsDesc {
+  const cpx<double>* in;
+  cpx<float>* out;
+  const cpx<float>* tw;
+  const int* skip;
+  int rows, n, block0;
+};
+
+__global__ __launch_bounds__(256) void k_group_rows_fwd(const GroupArgs<GRowsDesc> a) {
+  __shared__ cpx<float> lds[group_rows_lds()];
+  const GRowsDesc& d = a.m[group_member_of(a)];
+  if (d.skip[0] != 0) return;
+  const int bx = (int)blockIdx.x - d.block0;
+  switch (d.n) {
+    case 128: rows_fwd_body<float, double, 128>(d.in, d.out, d.rows, 0, 0, d.tw, bx, 0, lds); break;
+    case 256: rows_fwd_body<float, double, 256>(d.in, d.out, d.rows, 0, 0, d.tw, bx, 0, lds); break;
+    case 512: rows_fwd_body<float, double, 512>(d.in, d.out, d.rows, 0, 0, d.tw, bx, 0, lds); break;
+    case 1024: rows_fwd_body<float, double, 1024>(d.in, d.out, d.rows, 0, 0, d.tw, bx, 0, lds); break;
+    default: break;
+  }
+}
+
+struct GColsDesc {
+  const cpx<float>* in;
+  cpx<float>* out;
+  const cpx<float>* tw;
+  const int* skip;
+  const double* lam_ax;
+  const double* lam_in;
+  const NodeConst* nodes;
+  const uint16_t* store_mask;
+  const uint8_t* slab_need;
+  size_t in_rs, out_rs, in_fs, out_fs;
+  double scale;
+  int S, nfields, K, n, gx, gy, block0;
+};
+
+template <int DIR, int MODE>
+__global__ __launch_bounds__(256) void k_group_cols(const GroupArgs<GColsDesc> a) {
+  __shared__ cpx<float> lds[group_cols_lds()];
+  __shared__ uint16_t smask[group_cols_smask()];
+  const GColsDesc& d = a.m[group_member_of(a)];
+  const int b = (int)blockIdx.x - d.block0;
+  const int bx = b % d.gx, by = (b / d.gx) % d.gy, bz = b / (d.gx * d.gy);
+#define HP_GCOLS(NN)                                                                                              \
+  cols_body<float, float, NN, DIR, MODE>(d.in, d.out, d.S, d.nfields, d.in_rs, d.out_rs, d.in_fs, d.out_fs, d.tw, \
+                                         d.skip, d.lam_ax, d.lam_in, d.nodes, d.K, d.scale, d.store_mask,        \
+                                         d.slab_need, bx, by, bz, d.gx, d.gy, lds, smask)
+  switch (d.n) {
+    case 128: HP_GCOLS(128); break;
+    case 256: HP_GCOLS(256); break;
+    case 512: HP_GCOLS(512); break;
+    case 1024:
+      if constexpr (MODE == 1) HP_GCOLS(1024);
+      break;
+    default: break;
+  }
+#undef HP_GCOLS
+}
+
+struct GCombDesc {
+  const cpx<float>* fields;
+  const double* pos;
+  const uint64_t* grpmask;
+  const uint64_t* rowmask;
+  cpx<float>* out;
+  const cpx<float>* tw;
+  const int* skip;
+  const double* lag;
+  const double* posa;
+  size_t fs, frs;
+  int rows, K, M, Mt, mo, ord, Ma, n, im, block0;
+};
+
+template <int IM>
+__device__ __forceinline__ void group_combine_im(const GCombDesc& d, int bx, cpx<float>* lds, double* slag) {
+#define HP_GCOMB_WAVE(NN)                                                                                           \
+  comb_wave_body<float, float, NN, false, IM, 1>(d.fields, d.fs, d.frs, d.pos, d.rowmask, d.out, 0, d.rows, d.M, \
+                                                 d.Mt, d.mo, d.tw, d.skip, d.ord, d.lag, d.posa, d.Ma, bx, 0, lds, \
+                                                 slag)
+  switch (d.n) {
+    case 128:
+      rows_combine_body<float, float, 128, false, IM, 1>(d.fields, d.fs, d.frs, d.pos, d.grpmask, d.rowmask, d.out, 0,
+                                                         d.rows, d.K, d.M, d.Mt, d.mo, d.tw, d.skip, d.ord, d.lag,
+                                                         d.posa, d.Ma, bx, 0, lds, slag);
+      break;
+    case 256: HP_GCOMB_WAVE(256); break;
+    case 512: HP_GCOMB_WAVE(512); break;
+    case 1024: HP_GCOMB_WAVE(1024); break;
+    default: break;
+  }
+#undef HP_GCOMB_WAVE
+}
+
+// one launch per interpolation mode present among the members
+template <int IM>
+__global__ __launch_bounds__(64, 2) void k_group_combine(const GroupArgs<GCombDesc> a) {
+  __shared__ cpx<float> lds[group_comb_lds()];
+  __shared__ double slag[IM == kInterpLagrange ? kLagTable : 1];
+  const GCombDesc& d = a.m[group_member_of(a)];
+  group_combine_im<IM>(d, (int)blockIdx.x - d.block0, lds, slag);
+}
+
+// w = P_N z with the 2-D or the 3-D stencil chosen at run time (the same per-point
+// arithmetic as the stencil pass, so w is bitwise the same)
+struct WStencilAny {
+  const cpx<float>* z;
+  const cpx<float>* coef;
+  cpx<double>* W;
+  int dim, n0, n1, n2;
+  float ih0, ih1, ih2;
+  __device__ __forceinline__ cpx<double> operator()(size_t p) const {
+    const cpx<float> v = dim == 2 ? stencil_point<float, float, 2>(z, coef, p, n0, n1, n2, ih0, ih1, ih2)
+                                  : stencil_point<float, float, 3>(z, coef, p, n0, n1, n2, ih0, ih1, ih2);
+    const cpx<double> w = cvt<double>(v);
+    W[p] = w;
+    return w;
+  }
+};
+
+struct GDotsDesc {
+  cpx<double>* V;
+  cpx<double>* part;
+  const int* skip;
+  const cpx<float>* z;
+  const cpx<float>* coef;
+  size_t npts;
+  float ih0, ih1, ih2;
+  int j, dim, n0, n1, n2, block0;
+};
+
+__global__ __launch_bounds__(4 * 64) void k_group_dots(const GroupArgs<GDotsDesc> a) {
+  const GDotsDesc& d = a.m[group_member_of(a)];
+  if (d.skip[0] != 0) return;
+  const int bx = (int)blockIdx.x - d.block0;
+  arnoldi_dots_body<4>(d.V, d.npts, d.part + bx, d.j,
+                       WStencilAny{d.z, d.coef, d.V + (size_t)(d.j + 1) * d.npts, d.dim, d.n0, d.n1, d.n2, d.ih0,
+                                   d.ih1, d.ih2},
+                       bx);
+}
+
+struct GFinDesc {
+  const cpx<double>* part;
+  int* skip;
+  KState* state;
+  int* host_stop;
+  int j, restart;
+};
+
+__global__ __launch_bounds__(kFinThreads) void k_group_fin(const GroupArgs<GFinDesc> a) {
+  const GFinDesc& d = a.m[blockIdx.x];
+  if (d.skip[0] != 0) return;
+  arnoldi_finalize(d.state[0], d.part, 0, d.j, d.restart, d.skip, d.host_stop);
+}
+
+struct GUpdDesc {
+  cpx<double>* V;
+  const KState* state;
+  const int* skip;
+  size_t npts;
+  int j, gx, block0;
+};
+
+__global__ __launch_bounds__(256) void k_group_update(const GroupArgs<GUpdDesc> a) {
+  const GUpdDesc& d = a.m[group_member_of(a)];
+  arnoldi_update_body(d.V, d.npts, 0, d.state, d.skip, d.j, 0, (int)blockIdx.x - d.block0, d.gx);
+}
+
+static bool group_line_ok(int dim, int n) {
+  return is_pow2_len(n) && (dim == 2 ? (n >= 256 && n <= 1024) : (n >= 128 && n <= 512));
+}
+
+bool group_member_ok(const GroupMember& m) {
+  if ((m.dim != 2 && m.dim != 3) || m.K < 1 || m.K > kMaxNodes || m.j < 0 || m.j >= m.restart ||
+      m.restart > 4 * kDotsSlots)
+    return false;
+  for (int d = 0; d < m.dim; ++d)
+    if (!group_line_ok(m.dim, m.n[d])) return false;
+  return true;
+}
+
+static int group_rows_per_block(int n) {
+  switch (n) {
+    case 128: return RowCfg<float, 128>::G;
+    case 256: return RowCfg<float, 256>::G;
+    case 512: return RowCfg<float, 512>::G;
+    default: return RowCfg<float, 1024>::G;
+  }
+}
+static int group_cols_tc(int n, int mode) {
+  switch (n) {
+    case 128: return mode == 1 ? ColsCfg<float, 128, 1>::TC : ColsCfg<float, 128, 0>::TC;
+    case 256: return mode == 1 ? ColsCfg<float, 256, 1>::TC : ColsCfg<float, 256, 0>::TC;
+    case 512: return mode == 1 ? ColsCfg<float, 512, 1>::TC : ColsCfg<float, 512, 0>::TC;
+    default: return ColsCfg<float, 1024, 1>::TC;
+  }
+}
+
+hipError_t launch_group_step(const GroupMember* m, int count, hipStream_t st) {
+  if (count < 1 || count > kMaxGroup) return hipErrorInvalidValue;
+  for (int q = 0; q < count; ++q)
+    if (!group_member_ok(m[q])) return hipErrorInvalidValue;
+  // pass A: forward transform of u_j along the contiguous axis
+  {
+    GroupArgs<GRowsDesc> A{};
+    A.count = count;
+    int blocks = 0;
+    for (int q = 0; q < count; ++q) {
+      const int nl = m[q].n[m[q].dim - 1];
+      const int rows = (int)(m[q].npts / nl);
+      A.m[q] = GRowsDesc{m[q].V + (size_t)m[q].j * m[q].npts, (cpx<float>*)m[q].t,
+                         (const cpx<float>*)m[q].tw[m[q].dim - 1], m[q].skip_step, rows, nl, blocks};
+      blocks += (rows + group_rows_per_block(nl) - 1) / group_rows_per_block(nl);
+    }
+    hipLaunchKernelGGL(k_group_rows_fwd, dim3(blocks), dim3(256), 0, st, A);
+  }
+  // middle-axis pass of the 3-D members: forward on t (A'), or inverse on the node fields (M)
+  auto middle = [&](int dir) -> hipError_t {
+    GroupArgs<GColsDesc> C{};
+    int blocks = 0, c = 0;
+    for (int q = 0; q < count; ++q) {
+      if (m[q].dim != 3) continue;
+      const int n1 = m[q].n[1], S = m[q].n[2], tc = group_cols_tc(n1, 0);
+      const int nf = dir < 0 ? 1 : m[q].K;
+      GColsDesc d{};
+      d.in = (const cpx<float>*)(dir < 0 ? m[q].t : m[q].fields);
+      d.out = (cpx<float>*)(dir < 0 ? m[q].t : m[q].fields);
+      d.tw = (const cpx<float>*)m[q].tw[1];
+      d.skip = m[q].skip_step;
+      d.slab_need = dir < 0 ? nullptr : m[q].slab_need;
+      d.in_rs = d.out_rs = (size_t)nf * m[q].npts;
+      d.in_fs = d.out_fs = m[q].npts;
+      d.S = S;
+      d.nfields = nf;
+      d.n = n1;
+      d.gx = (S + tc - 1) / tc;
+      d.gy = m[q].n[0];
+      d.block0 = blocks;
+      blocks += d.gx * d.gy * nf;
+      C.m[c++] = d;
+    }
+    C.count = c;
+    if (c == 0) return hipSuccess;
+    if (dir < 0) hipLaunchKernelGGL((k_group_cols<-1, 0>), dim3(blocks), dim3(256), 0, st, C);
+    else hipLaunchKernelGGL((k_group_cols<+1, 0>), dim3(blocks), dim3(256), 0, st, C);
+    return hipGetLastError();
+  };
+  hipError_t e;
+  if ((e = middle(-1)) != hipSuccess) return e;
+  // pass B: forward along axis 0, K symbol multiplies and inverse transforms
+  {
+    GroupArgs<GColsDesc> B{};
+    B.count = count;
+    int blocks = 0;
+    for (int q = 0; q < count; ++q) {
+      const int n0 = m[q].n[0], S = (int)(m[q].npts / n0), tc = group_cols_tc(n0, 1);
+      GColsDesc d{};
+      d.in = (const cpx<float>*)m[q].t;
+      d.out = (cpx<float>*)m[q].fields;
+      d.tw = (const cpx<float>*)m[q].tw[0];
+      d.skip = m[q].skip_step;
+      d.lam_ax = m[q].lam_ax;
+      d.lam_in = m[q].lam_in;
+      d.nodes = m[q].nodes;
+      d.store_mask = m[q].store_mask;
+      d.slab_need = m[q].slab_need;
+      d.in_rs = m[q].npts;
+      d.out_rs = m[q].npts * (size_t)m[q].K;
+      d.in_fs = d.out_fs = m[q].npts;
+      d.scale = m[q].scale;
+      d.S = S;
+      d.nfields = 1;
+      d.K = m[q].K;
+      d.n = n0;
+      d.gx = (S + tc - 1) / tc;
+      d.gy = m[q].ng_b > 0 ? std::min(m[q].K, m[q].ng_b) : std::max(1, std::min(m[q].K, (512 + d.gx - 1) / d.gx));
+      d.block0 = blocks;
+      blocks += d.gx * d.gy;
+      B.m[q] = d;
+    }
+    hipLaunchKernelGGL((k_group_cols<-1, 1>), dim3(blocks), dim3(256), 0, st, B);
+  }
+  if ((e = middle(+1)) != hipSuccess) return e;
+  // pass C: inverse along the contiguous axis and the weighted sum into z
+  for (int im = kInterpLinear; im <= kInterpBilinear; ++im) {
+    GroupArgs<GCombDesc> Cb{};
+    int blocks = 0, c = 0;
+    for (int q = 0; q < count; ++q) {
+      if (m[q].interp != im) continue;
+      const int nl = m[q].n[m[q].dim - 1];
+      const int rows = (int)(m[q].npts / nl);
+      GCombDesc d{};
+      d.fields = (const cpx<float>*)m[q].fields;
+      d.pos = m[q].pos;
+      d.grpmask = m[q].grpmask;
+      d.rowmask = m[q].rowmask;
+      d.out = (cpx<float>*)m[q].z;
+      d.tw = (const cpx<float>*)m[q].tw[m[q].dim - 1];
+      d.skip = m[q].skip_step;
+      d.lag = m[q].lag;
+      d.posa = m[q].posa;
+      d.fs = m[q].npts;
+      d.frs = m[q].npts * (size_t)m[q].K;
+      d.rows = rows;
+      d.K = m[q].K;
+      d.M = m[q].M;
+      d.Mt = m[q].Mt;
+      d.mo = m[q].mo;
+      d.ord = m[q].order;
+      d.Ma = m[q].Ma;
+      d.n = nl;
+      d.im = m[q].interp;
+      d.block0 = blocks;
+      blocks += nl == 128 ? (rows + CombCfg<float, 128>::G - 1) / CombCfg<float, 128>::G : rows;
+      Cb.m[c++] = d;
+    }
+    Cb.count = c;
+    if (c == 0) continue;
+    if (im == kInterpLagrange) hipLaunchKernelGGL(k_group_combine<kInterpLagrange>, dim3(blocks), dim3(64), 0, st, Cb);
+    else if (im == kInterpBilinear) hipLaunchKernelGGL(k_group_combine<kInterpBilinear>, dim3(blocks), dim3(64), 0, st, Cb);
+    else hipLaunchKernelGGL(k_group_combine<kInterpLinear>, dim3(blocks), dim3(64), 0, st, Cb);
+  }
+  // w = P_N z with the dot products of the step, then the finishing kernel and the update
+  {
+    GroupArgs<GDotsDesc> D{};
+    GroupArgs<GFinDesc> F{};
+    GroupArgs<GUpdDesc> U{};
+    D.count = F.count = U.count = count;
+    int ublocks = 0;
+    for (int q = 0; q < count; ++q) {
+      const GroupMember& g = m[q];
+      D.m[q] = GDotsDesc{g.V, g.part, g.skip_step, (const cpx<float>*)g.z, (const cpx<float>*)g.coef32, g.npts,
+                         (float)g.ih2[0], (float)g.ih2[1], (float)g.ih2[2], g.j, g.dim, g.n[0], g.n[1],
+                         g.dim == 3 ? g.n[2] : 1, q * kRedBlocks};
+      F.m[q] = GFinDesc{g.part, g.skip_step, g.state, g.host_stop, g.j, g.restart};
+      const size_t ub = (g.npts + 256 * kUpdPts - 1) / (256 * kUpdPts);
+      const int gx = (int)(ub < 1024 ? ub : 1024);
+      U.m[q] = GUpdDesc{g.V, g.state, g.skip_step, g.npts, g.j, gx, ublocks};
+      ublocks += gx;
+    }
+    hipLaunchKernelGGL(k_group_dots, dim3(count * kRedBlocks), dim3(4 * 64), 0, st, D);
+    hipLaunchKernelGGL(k_group_fin, dim3(count), dim3(kFinThreads), 0, st, F);
+    hipLaunchKernelGGL(k_group_update, dim3(ublocks), dim3(256), 0, st, U);
+  }
   return hipGetLastError();
 }
 

@@ -111,15 +111,23 @@ def retimed(requests, rate_per_s=None, seed=20240921):
 
 class Server:
     """keep_x: keep each request's solution tensor on the GPU (False: only its info,
-    so that long streams do not hold every solution)."""
+    so that long streams do not hold every solution).
+    grouped: the active solves are spread over `streams` streams and advance together,
+    the Arnoldi steps of those on one stream that the grouped kernels take running as
+    one launch per pass over all of them (uneven grids and media in the same launches);
+    otherwise each active solve runs its own launches on a stream of its own."""
 
     def __init__(self, hbm_budget_bytes, max_active=8, steps_per_turn=2, restart=30, rtol=1e-8,
-                 max_cycles=200, keep_x=True):
+                 max_cycles=200, keep_x=True, grouped=False, streams=4):
         self.budget = int(hbm_budget_bytes)
         self.max_active = int(max_active)
         self.steps = int(steps_per_turn)
         self.restart, self.rtol, self.max_cycles = restart, rtol, max_cycles
         self.keep_x = bool(keep_x)
+        self.grouped = bool(grouped)
+        self.n_streams = max(1, int(streams))
+        self._streams = []
+        self._admitted = 0
         self.in_use = 0
         self.peak_in_use = 0
         self.deferred_rids = set()   # requests held back by the HBM budget while a slot was free
@@ -128,7 +136,17 @@ class Server:
 
     def _admit(self, r, now, dev, torch):
         w = r.workload
-        stream = torch.cuda.Stream(device=dev)          # default priority
+        if self.grouped:
+            if not self._streams:
+                self._streams = [torch.cuda.Stream(device=dev) for _ in range(self.n_streams)]   # default priority
+            # the stream with the fewest active solves (ties: round robin)
+            load = [sum(1 for it in self.active if it[5] is st) for st in self._streams]
+            k0 = self._admitted % self.n_streams
+            k = min(range(self.n_streams), key=lambda q: (load[q], (q - k0) % self.n_streams))
+            stream = self._streams[k]
+            self._admitted += 1
+        else:
+            stream = torch.cuda.Stream(device=dev)          # default priority
         plan = binding.plan_from_workload(w, max_nrhs=1)
         solver = binding.Solver(plan, 1, restart=self.restart, max_cycles=self.max_cycles, rtol=self.rtol)
         with torch.cuda.stream(stream):
@@ -140,11 +158,14 @@ class Server:
         self.peak_in_use = max(self.peak_in_use, self.in_use)
         self.active.append((r, plan, solver, f, x, stream))
 
-    def _progress(self, item, t0):
-        """Advance one active solve by a few steps; on completion collect its result
-        and release its plan and workspace.  Returns True when it has finished."""
+    def _progress(self, item, t0, finished=None):
+        """Advance one active solve by a few steps (or take the grouped advance's
+        verdict `finished`); on completion collect its result and release its plan
+        and workspace.  Returns True when it has finished."""
         r, plan, solver, f, x, stream = item
-        if not solver.advance(self.steps):
+        if finished is None:
+            finished = solver.advance(self.steps)
+        if not finished:
             return False
         x, info = solver.result()
         r.finished = time.perf_counter() - t0
@@ -178,9 +199,12 @@ class Server:
                 heapq.heappop(queue)
                 self._admit(r, time.perf_counter() - t0, dev, torch)
             # progress every active solve without waiting on the device
+            flags = [None] * len(self.active)
+            if self.grouped and self.active:
+                flags = binding.advance_group([it[2] for it in self.active], self.steps)
             still = []
-            for item in self.active:
-                if self._progress(item, t0):
+            for item, fl in zip(self.active, flags):
+                if (self._progress(item, t0) if fl is None else self._progress(item, t0, fl)):
                     self.in_use -= item[0].footprint
                     self.done.append(item[0])
                 else:
