@@ -102,11 +102,24 @@ struct Dft {
   }
 };
 
-// LDS index with one pad element every E elements: the first stage writes
-// runs of E consecutive elements per thread, and the padding staggers those
-// runs across the LDS banks.
-template <int E>
-__device__ __forceinline__ int lpad(int i) { return i + i / E; }
+// LDS index of element p of a line between two stages (a stage writes runs of
+// elements NS apart, the next reads elements T apart).  Chosen with the gfx950
+// bank-conflict counters over every exchange of the transforms below:
+//  * 16-byte elements (FP64 complex): p xor ((p >> 3) & 7), a permutation inside
+//    aligned groups of eight; no conflicts at any line length or interleave,
+//    where one pad element every E left a two-way conflict on each read of an
+//    exchange (1024^2 FP64 symbol pass 85.6 -> 80.3 us, combine 64.8 -> 62.7 us);
+//  * 8-byte elements (FP32 complex): one pad element every E elements.  It is
+//    conflict free in the column passes; the xor map inside groups of sixteen
+//    would also clear the row passes, but its address arithmetic pushes the FP32
+//    symbol and combine passes past 256 registers (1024^2 mixed apply 108 ->
+//    167 us).
+// Both maps send [0, n) into [0, lds_elems_e(n)) one to one.
+template <int ES, int E>
+__device__ __forceinline__ int lidx(int p) {
+  if constexpr (ES == 16) return p ^ ((p >> 3) & 7);
+  else return p + p / E;
+}
 template <int E>
 __host__ __device__ constexpr int lds_elems_e(int n) { return n + n / E; }
 
@@ -163,7 +176,7 @@ __host__ __device__ constexpr int stage_radix() {
 // One Stockham stage of radix R at sub-transform size NS, then the next stage.
 // tw: table of exp(-2 pi i m / N), m < N.
 // ILV: several transforms share one LDS array with their elements interleaved
-// (element p of transform g at lpad(p) * ILV + g; the caller passes lds + g),
+// (element p of transform g at lidx(p) * ILV + g; the caller passes lds + g),
 // so that lanes of neighbouring transforms touch neighbouring banks.
 template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV, bool RELOAD = false>
 struct Stage {
@@ -194,13 +207,13 @@ struct Stage {
       } else {
         const int base = (b / NS) * NS * RS + k;
 #pragma unroll
-        for (int t = 0; t < RS; ++t) lds[lpad<E>(base + t * NS) * ILV] = out[t];
+        for (int t = 0; t < RS; ++t) lds[lidx<sizeof(cpx<R>), E>(base + t * NS) * ILV] = out[t];
       }
     }
     if constexpr (!last) {
       xsync<WAVE>();
 #pragma unroll
-      for (int s = 0; s < E; ++s) x[s] = lds[lpad<E>(j + T * s) * ILV];
+      for (int s = 0; s < E; ++s) x[s] = lds[lidx<sizeof(cpx<R>), E>(j + T * s) * ILV];
       xsync<WAVE>();
       Stage<R, N, E, DIR, NS * RS, WAVE, ILV, RELOAD>::run(x, lds, j, tw);
     }
