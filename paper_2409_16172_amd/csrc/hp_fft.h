@@ -168,6 +168,29 @@ __device__ __forceinline__ const T* reload_each_time(const T* p) {
   return (const T*)g;
 }
 
+// Exchange between lanes l and l ^ 32 of a wavefront (v_permlane32_swap): lanes
+// 0-31 keep a and receive into b the a of lanes 32-63; lanes 32-63 keep b and
+// receive into a the b of lanes 0-31.  All 64 lanes must be active.
+__device__ __forceinline__ void lane_swap32(double& a, double& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+  b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ void lane_swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  a = __builtin_bit_cast(float, r[0]);
+  b = __builtin_bit_cast(float, r[1]);
+}
+template <typename R>
+__device__ __forceinline__ void lane_swap32(cpx<R>& a, cpx<R>& b) {
+  lane_swap32(a.re, b.re);
+  lane_swap32(a.im, b.im);
+}
+
 template <int N, int NS, int E>
 __host__ __device__ constexpr int stage_radix() {
   return (N / NS) < E ? (N / NS) : E;
@@ -178,7 +201,13 @@ __host__ __device__ constexpr int stage_radix() {
 // ILV: several transforms share one LDS array with their elements interleaved
 // (element p of transform g at lidx(p) * ILV + g; the caller passes lds + g),
 // so that lanes of neighbouring transforms touch neighbouring banks.
-template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV, bool RELOAD = false>
+// SWP: when the last stage has radix 2 and this one radix E (one butterfly per
+// thread), the exchange between them goes through lanes instead of LDS.  Thread j
+// then holds positions (j / (T/2)) N/2 + j % (T/2) + (T/2) t, t < E, and needs
+// j % (T/2) + (T/2)(j / (T/2) + 2 s), s < E: it keeps the odd or even t (by
+// j / (T/2)) and trades the other half with thread j ^ (T/2), which the caller
+// must place at lane ^ 32 of the same wavefront, with j / (T/2) = 0 in lanes 0-31.
+template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV, bool RELOAD = false, bool SWP = false>
 struct Stage {
   __device__ __forceinline__ static void run(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
     if constexpr (RELOAD && NS > 1) tw = reload_each_time(tw);
@@ -186,6 +215,7 @@ struct Stage {
     constexpr int B = E / RS;
     constexpr int T = N / E;
     constexpr bool last = (NS * RS == N);
+    constexpr bool swap_next = SWP && !last && RS == E && 2 * NS * RS == N;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       const int b = j + T * i;
@@ -204,18 +234,28 @@ struct Stage {
       if constexpr (last) {
 #pragma unroll
         for (int t = 0; t < RS; ++t) x[i + B * t] = out[t];
+      } else if constexpr (swap_next) {
+#pragma unroll
+        for (int u = 0; u < E / 2; ++u) {
+          cpx<R> a = out[2 * u], c = out[2 * u + 1];
+          lane_swap32(a, c);
+          x[u] = a;
+          x[u + E / 2] = c;
+        }
       } else {
         const int base = (b / NS) * NS * RS + k;
 #pragma unroll
         for (int t = 0; t < RS; ++t) lds[lidx<sizeof(cpx<R>), E>(base + t * NS) * ILV] = out[t];
       }
     }
-    if constexpr (!last) {
+    if constexpr (swap_next) {
+      Stage<R, N, E, DIR, NS * RS, WAVE, ILV, RELOAD, SWP>::run(x, lds, j, tw);
+    } else if constexpr (!last) {
       xsync<WAVE>();
 #pragma unroll
       for (int s = 0; s < E; ++s) x[s] = lds[lidx<sizeof(cpx<R>), E>(j + T * s) * ILV];
       xsync<WAVE>();
-      Stage<R, N, E, DIR, NS * RS, WAVE, ILV, RELOAD>::run(x, lds, j, tw);
+      Stage<R, N, E, DIR, NS * RS, WAVE, ILV, RELOAD, SWP>::run(x, lds, j, tw);
     }
   }
 };
@@ -230,10 +270,11 @@ __host__ __device__ constexpr int lds_elems(int n) { return lds_elems_e<elems_pe
 // fft_e takes the elements per thread E explicitly (LDS: lds_elems_e<E>(N) per transform).
 // RELOAD: each stage reads its twiddles through reload_each_time (wave-resident
 // lines of many elements per lane, whose registers cannot hold every stage's).
-template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1, bool RELOAD = false>
+// SWP: the exchange before a last radix-2 stage goes through lanes (see Stage).
+template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1, bool RELOAD = false, bool SWP = false>
 __device__ __forceinline__ void fft_e(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
   constexpr int T = N / E;
-  Stage<R, N, E, DIR, 1, CONTIG && (T <= 64), ILV, RELOAD>::run(x, lds, j, tw);
+  Stage<R, N, E, DIR, 1, CONTIG && (T <= 64), ILV, RELOAD, SWP>::run(x, lds, j, tw);
 }
 template <typename R, int N, int DIR, bool CONTIG = false, int ILV = 1>
 __device__ __forceinline__ void fft(cpx<R> (&x)[elems_per_thread<R>(N)], cpx<R>* lds, int j,

@@ -112,6 +112,23 @@ using ColsCfg = std::conditional_t<MODE == 1, SymCfg<R, N>, ColCfg<R, N, 1024>>;
 #define HP_WAVE_COMB 1
 #endif
 
+// 1024-point FP64 lines take the exchange before their last radix-2 stage through
+// lanes (v_permlane32_swap) instead of LDS and two barriers; threads j and j ^ 64
+// of a line must then sit at lanes l and l ^ 32 of one wavefront.
+#ifndef HP_LANE_SWAP
+#define HP_LANE_SWAP 1
+#endif
+// rows: 128 threads per row (two wavefronts), wavefront w = (j >> 5) & 1 and
+// lane = (j >> 6) << 5 | (j & 31); tl is the thread's index within its row
+template <typename R, int N, int G>
+constexpr bool rows_lane_swap() {
+  return HP_LANE_SWAP && sizeof(R) == 8 && N == 1024 && elems_per_thread<R>(N) == 8;
+}
+__device__ __forceinline__ int rows_swap_thread(int tl) {
+  const int lane = tl & 63;
+  return (lane & 31) | (((tl >> 6) & 1) << 5) | ((lane >> 5) << 6);
+}
+
 // ---------------------------------------------------------------- pass A
 // Pass bodies take their workgroup's indices and LDS as arguments, so that the
 // grouped launches (several plans, several line lengths in one launch) run the
@@ -121,14 +138,16 @@ __device__ __forceinline__ void rows_fwd_body(const cpx<TI>* __restrict__ in, cp
                                               size_t in_rs, size_t out_rs, const cpx<R>* __restrict__ tw, int bx,
                                               int rhs, cpx<R>* lds) {
   using C = RowCfg<R, N>;
-  const int g = threadIdx.x / C::T, j = threadIdx.x % C::T;
+  constexpr bool SWP = rows_lane_swap<R, N, C::G>();
+  const int tl = (int)threadIdx.x % C::T;
+  const int g = threadIdx.x / C::T, j = SWP ? rows_swap_thread(tl) : tl;
   const int row = bx * C::G + g;
   const bool act = row < rows;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)row * N;
   cpx<R> x[C::E];
 #pragma unroll
   for (int s = 0; s < C::E; ++s) x[s] = act ? cvt<R>(src[j + C::T * s]) : cpx<R>{0, 0};
-  fft<R, N, -1, true>(x, lds + g * lds_elems<R>(N), j, tw);
+  fft_e<R, N, C::E, -1, true, 1, false, SWP>(x, lds + g * lds_elems<R>(N), j, tw);
   if (act) {
     cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)row * N;
 #pragma unroll
@@ -194,6 +213,15 @@ constexpr int cols_smask_words() {
   return MODE == 1 ? kMaxNodes * ColsCfg<R, N, MODE>::T : 1;
 }
 
+// The symbol pass of 1024-point FP64 columns (two columns of 128 threads per
+// workgroup) takes the same lane exchange.
+template <typename R, int N, int MODE>
+constexpr bool cols_lane_swap() {
+  using C = ColsCfg<R, N, MODE>;
+  return HP_LANE_SWAP && MODE == 1 && sizeof(R) == 8 && N == 1024 && C::E == 8 && C::T == 128 && C::TC == 2 &&
+         C::THREADS == 256;
+}
+
 template <typename R, typename TI, int N, int DIR, int MODE>
 __device__ __forceinline__ void cols_body(
     const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, int S, int nfields, size_t in_rs,
@@ -202,13 +230,19 @@ __device__ __forceinline__ void cols_body(
     const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
     const uint8_t* __restrict__ slab_need, int bx, int by, int bz, int gx, int gy, cpx<R>* lds, uint16_t* smask) {
   using C = ColsCfg<R, N, MODE>;
+  constexpr bool SWP = cols_lane_swap<R, N, MODE>();
   const int z = bz;
   const int rhs = (MODE == 0) ? z / nfields : z;
   const int fld = (MODE == 0) ? z % nfields : 0;
   if (skip != nullptr && skip[rhs] != 0) return;
   // plain passes over node fields: slabs whose points never use this node are skipped
   if (MODE == 0 && slab_need != nullptr && slab_need[(size_t)fld * gy + by] == 0) return;
-  const int g = threadIdx.x % C::TC, j = threadIdx.x / C::TC;
+  // With the lane exchange (SWP) threads j and j ^ 64 of a column sit at lanes l and
+  // l ^ 32 of one wavefront: lane = (j >> 6) << 5 | (j & 15) << 1 | g, wavefront (j >> 4) & 3.
+  const int lane = threadIdx.x & 63;
+  const int g = SWP ? (lane & 1) : (int)threadIdx.x % C::TC;
+  const int j = SWP ? (((lane >> 1) & 15) | ((int)(threadIdx.x >> 6) << 4) | ((lane >> 5) << 6))
+                    : (int)threadIdx.x / C::TC;
   // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
   // L2).  Give the workgroups of one XCD consecutive column tiles so that tiles
   // sharing cache lines meet in the same L2.
@@ -243,7 +277,7 @@ __device__ __forceinline__ void cols_body(
       for (int s = 0; s < C::E; ++s) dst[(size_t)(j + C::T * s) * S] = x[s];
     }
   } else {
-    fft_e<R, N, C::E, -1, false, C::TC>(x, lg, j, tw);
+    fft_e<R, N, C::E, -1, false, C::TC, false, SWP>(x, lg, j, tw);
     cpx<R> vh[C::E];
     double lam[C::E];
     const double lc = act ? lam_in[c] : 0.0;
@@ -256,7 +290,7 @@ __device__ __forceinline__ void cols_body(
     const int n_lo = (int)(((long)by * K) / gy), n_hi = (int)(((long)(by + 1) * K) / gy);
     for (int n = n_lo; n < n_hi; ++n) {
       symbol_mul<R, C::E>(vh, x, lam, nodes[n], scale);
-      fft_e<R, N, C::E, +1, false, C::TC>(x, lg, j, tw);
+      fft_e<R, N, C::E, +1, false, C::TC, false, SWP>(x, lg, j, tw);
       // bit s: some point of axis-0 index j + T*s uses node n (else the row is never read)
       const uint32_t m = act ? (uint32_t)smask[n * C::T + j] : 0u;
 #pragma unroll
@@ -394,9 +428,10 @@ __device__ __forceinline__ void rows_combine_body(
     for (int i = threadIdx.x; i < kLagTable; i += C::THREADS * NS) slag[i] = lag[i];
     __syncthreads();
   }
+  constexpr bool SWP = rows_lane_swap<R, N, C::G>() && NS == 1;
   const int sp = NS > 1 ? (int)threadIdx.x / C::THREADS : 0;
   const int tl = NS > 1 ? (int)threadIdx.x % C::THREADS : (int)threadIdx.x;
-  const int g = tl / C::T, j = tl % C::T;
+  const int g = tl / C::T, j = SWP ? rows_swap_thread(tl) : tl % C::T;
   const int row = bx * C::G + g;
   const bool act = row < rows;
   const size_t rbase = (size_t)row * N;
@@ -457,7 +492,7 @@ __device__ __forceinline__ void rows_combine_body(
 #pragma unroll
       for (int s = 0; s < C::E; ++s) nx[s] = ld ? fr[(size_t)n2 * fs + j + C::T * s] : cpx<R>{0, 0};
     }
-    fft<R, N, +1, true>(x, lg, j, tw);
+    fft_e<R, N, C::E, +1, true, 1, false, SWP>(x, lg, j, tw);
 #pragma unroll
     for (int s = 0; s < C::E; ++s) {
       const R w = interp_weight<R, IM>(ab[s], tt[s], uu[s], n, ord, slag);

@@ -185,7 +185,8 @@ def test_mixed_served_mix_with_3d_requests(orc, dev):
                                         ((16, 1024), "bilinear"), ((16, 16, 256), "lagrange")])
 def test_mixed_combine_modes_on_long_rows(orc, hp, dev, shape, mode):
     """Mixed-precision combines of 256- to 1024-point rows (one row per wavefront) in the
-    higher-degree and bilinear interpolation modes, against the oracle."""
+    higher-degree and bilinear interpolation modes, against the oracle; FP64 too for
+    1024-point rows."""
     _case("combine_modes_long_rows", shape=shape, mode=mode)
     nmin = min(shape)
     omega = 2 * np.pi * nmin / 4
@@ -200,8 +201,12 @@ def test_mixed_combine_modes_on_long_rows(orc, hp, dev, shape, mode):
         kw = dict(m_real=5, m_damp=3)
     v = _v32(shape, 53, nrhs=2)
     ue = orc.Problem(shape, omega, c, a, zeta, **kw).apply(v)
-    plan = hp.Plan(shape, omega, c, a, zeta, precision="mixed", max_nrhs=2, **kw)
-    u = plan.apply(torch.from_numpy(v).to(dev).to(torch.complex64)).cpu().numpy()
-    for r in range(2):
-        _check(u[r], ue[r], 1e-5, f"mixed {mode} {shape} rhs {r}")
-    plan.close()
+    precs = [("mixed", torch.complex64, 1e-5)]
+    if shape[-1] == 1024:   # FP64 1024-point rows take the lane exchange in every combine mode
+        precs.append(("fp64", torch.complex128, 1e-12))
+    for prec, dt, tol in precs:
+        plan = hp.Plan(shape, omega, c, a, zeta, precision=prec, max_nrhs=2, **kw)
+        u = plan.apply(torch.from_numpy(v).to(dev).to(dt)).cpu().numpy()
+        for r in range(2):
+            _check(u[r], ue[r], tol, f"{prec} {mode} {shape} rhs {r}")
+        plan.close()
