@@ -179,16 +179,66 @@ __device__ __forceinline__ void lane_swap32(double& a, double& b) {
   a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
   b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
 }
-__device__ __forceinline__ void lane_swap32(float& a, float& b) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
-                                                  false, false);
-  a = __builtin_bit_cast(float, r[0]);
-  b = __builtin_bit_cast(float, r[1]);
+// An FP32 complex value goes through as one 64-bit word (its re and im as the two
+// halves), the same instruction pattern as an FP64 value: with each float bit-cast
+// on its own, this compiler kept the first result for both outputs.
+__device__ __forceinline__ void lane_swap32(cpx<float>& a, cpx<float>& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(cpx<float>, ((unsigned long long)hi[0] << 32) | lo[0]);
+  b = __builtin_bit_cast(cpx<float>, ((unsigned long long)hi[1] << 32) | lo[1]);
 }
-template <typename R>
-__device__ __forceinline__ void lane_swap32(cpx<R>& a, cpx<R>& b) {
+__device__ __forceinline__ void lane_swap32(cpx<double>& a, cpx<double>& b) {
   lane_swap32(a.re, b.re);
   lane_swap32(a.im, b.im);
+}
+// The same between lanes l and l ^ 16 (v_permlane16_swap): lanes with bit 4 clear
+// keep a and receive into b the a of lane l + 16; the others keep b and receive
+// into a the b of lane l - 16.
+__device__ __forceinline__ void lane_swap16(double& a, double& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+  b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ void lane_swap16(cpx<float>& a, cpx<float>& b) {
+  const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+  const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(cpx<float>, ((unsigned long long)hi[0] << 32) | lo[0]);
+  b = __builtin_bit_cast(cpx<float>, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ void lane_swap16(cpx<double>& a, cpx<double>& b) {
+  lane_swap16(a.re, b.re);
+  lane_swap16(a.im, b.im);
+}
+template <int D, typename R>
+__device__ __forceinline__ void lane_swap(cpx<R>& a, cpx<R>& b) {
+  static_assert(D == 16 || D == 32, "lane distance");
+  if constexpr (D == 32) lane_swap32(a, b);
+  else lane_swap16(a, b);
+}
+
+// Which exchange before the last stage of a length-N transform with E elements
+// per thread can go through lanes: 2 when the last stage has radix 2 and the one
+// before it radix E (thread j trades half its elements with thread j ^ T/2), 4
+// when the last has radix 4 after one of radix E (threads j, j ^ T/4, j ^ T/2,
+// j ^ 3T/4 trade a quarter with each other), else 0.
+template <int N, int E>
+__host__ __device__ constexpr int lane_exchange_kind() {
+  int ns = 1, prev = 0, r = 0;
+  while (ns < N) {
+    prev = r;
+    r = (N / ns) < E ? (N / ns) : E;
+    ns *= r;
+  }
+  if (prev != E) return 0;
+  return (r == 2 || r == 4) ? r : 0;
 }
 
 template <int N, int NS, int E>
@@ -201,13 +251,20 @@ __host__ __device__ constexpr int stage_radix() {
 // ILV: several transforms share one LDS array with their elements interleaved
 // (element p of transform g at lidx(p) * ILV + g; the caller passes lds + g),
 // so that lanes of neighbouring transforms touch neighbouring banks.
-// SWP: when the last stage has radix 2 and this one radix E (one butterfly per
-// thread), the exchange between them goes through lanes instead of LDS.  Thread j
-// then holds positions (j / (T/2)) N/2 + j % (T/2) + (T/2) t, t < E, and needs
-// j % (T/2) + (T/2)(j / (T/2) + 2 s), s < E: it keeps the odd or even t (by
-// j / (T/2)) and trades the other half with thread j ^ (T/2), which the caller
-// must place at lane ^ 32 of the same wavefront, with j / (T/2) = 0 in lanes 0-31.
-template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV, bool RELOAD = false, bool SWP = false>
+// SWP (0, 16 or 32): the exchange before the last stage goes through lanes
+// instead of LDS when lane_exchange_kind says it can.  With thread j = h (T/K) + L,
+// K the last radix, L < T/K, after the stage before the last thread j holds the
+// positions h N/K + L + (T/K) t, t < E, and needs L + (T/K)(h + K s), s < E.
+//  * K = 2: it keeps the t of its own parity (h) and trades the rest with thread
+//    j ^ T/2, which the caller places at lane ^ SWP of the same wavefront, with
+//    h = 0 on the lanes whose bit log2(SWP) is clear.
+//  * K = 4 (SWP = 32): threads h = 0..3 of one L sit at lanes differing in bits 5
+//    (h bit 1) and 4 (h bit 0); a trade over lane bit 5 of the t with t mod 4 in
+//    {2, 3} (or {0, 1}) and then one over lane bit 4 of the odd (even) t leave each
+//    thread the E/4 elements t = h + 4c of every h', which belong at s = (E/4) h' + c.
+// In both cases the element a lane keeps sits in the register it keeps, so the
+// trades need no per-lane selects, and the final order is a fixed renaming.
+template <typename R, int N, int E, int DIR, int NS, bool WAVE, int ILV, bool RELOAD = false, int SWP = 0>
 struct Stage {
   __device__ __forceinline__ static void run(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
     if constexpr (RELOAD && NS > 1) tw = reload_each_time(tw);
@@ -215,7 +272,10 @@ struct Stage {
     constexpr int B = E / RS;
     constexpr int T = N / E;
     constexpr bool last = (NS * RS == N);
-    constexpr bool swap_next = SWP && !last && RS == E && 2 * NS * RS == N;
+    constexpr int lxk = lane_exchange_kind<N, E>();
+    constexpr bool swap2 = SWP != 0 && !last && lxk == 2 && 2 * NS * RS == N;
+    constexpr bool swap4 = SWP == 32 && !last && lxk == 4 && 4 * NS * RS == N;
+    constexpr bool swap_next = swap2 || swap4;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       const int b = j + T * i;
@@ -234,14 +294,22 @@ struct Stage {
       if constexpr (last) {
 #pragma unroll
         for (int t = 0; t < RS; ++t) x[i + B * t] = out[t];
-      } else if constexpr (swap_next) {
+      } else if constexpr (swap2) {
 #pragma unroll
         for (int u = 0; u < E / 2; ++u) {
           cpx<R> a = out[2 * u], c = out[2 * u + 1];
-          lane_swap32(a, c);
+          lane_swap<SWP>(a, c);
           x[u] = a;
           x[u + E / 2] = c;
         }
+      } else if constexpr (swap4) {
+#pragma unroll
+        for (int t = 0; t < E; ++t)
+          if (t % 4 < 2) lane_swap32(out[t], out[t + 2]);
+#pragma unroll
+        for (int t = 0; t < E; t += 2) lane_swap16(out[t], out[t + 1]);
+#pragma unroll
+        for (int t = 0; t < E; ++t) x[t] = out[(t % (E / 4)) * 4 + t / (E / 4)];
       } else {
         const int base = (b / NS) * NS * RS + k;
 #pragma unroll
@@ -270,8 +338,8 @@ __host__ __device__ constexpr int lds_elems(int n) { return lds_elems_e<elems_pe
 // fft_e takes the elements per thread E explicitly (LDS: lds_elems_e<E>(N) per transform).
 // RELOAD: each stage reads its twiddles through reload_each_time (wave-resident
 // lines of many elements per lane, whose registers cannot hold every stage's).
-// SWP: the exchange before a last radix-2 stage goes through lanes (see Stage).
-template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1, bool RELOAD = false, bool SWP = false>
+// SWP: the exchange before the last stage goes through lanes where it can (see Stage).
+template <typename R, int N, int E, int DIR, bool CONTIG = false, int ILV = 1, bool RELOAD = false, int SWP = 0>
 __device__ __forceinline__ void fft_e(cpx<R> (&x)[E], cpx<R>* lds, int j, const cpx<R>* __restrict__ tw) {
   constexpr int T = N / E;
   Stage<R, N, E, DIR, 1, CONTIG && (T <= 64), ILV, RELOAD, SWP>::run(x, lds, j, tw);

@@ -112,21 +112,33 @@ using ColsCfg = std::conditional_t<MODE == 1, SymCfg<R, N>, ColCfg<R, N, 1024>>;
 #define HP_WAVE_COMB 1
 #endif
 
-// 1024-point FP64 lines take the exchange before their last radix-2 stage through
-// lanes (v_permlane32_swap) instead of LDS and two barriers; threads j and j ^ 64
-// of a line must then sit at lanes l and l ^ 32 of one wavefront.
+// FP64 lines of 1024 points (stages 8, 8, 8, 2) and, in the row passes, of 2048
+// (8, 8, 8, 4) take the exchange before their last stage through lanes
+// (v_permlane32_swap / v_permlane16_swap) instead of LDS and two barriers
+// (lane_exchange_kind and Stage in the FFT engine).  The threads that trade must
+// share a wavefront at the lanes Stage expects, so these lines number their threads
+// differently.  Measured and left off: the 2048-point symbol pass (741 -> 831 us:
+// its column tiles' loads spread over four row groups per wavefront) and the FP32
+// lines of 1024 points (16, 16, 4), whose LDS exchanges need only wavefront
+// barriers (1024^2 mixed combine 55.7 -> 63.0 us).
 #ifndef HP_LANE_SWAP
 #define HP_LANE_SWAP 1
 #endif
-// rows: 128 threads per row (two wavefronts), wavefront w = (j >> 5) & 1 and
-// lane = (j >> 6) << 5 | (j & 31); tl is the thread's index within its row
-template <typename R, int N, int G>
-constexpr bool rows_lane_swap() {
-  return HP_LANE_SWAP && sizeof(R) == 8 && N == 1024 && elems_per_thread<R>(N) == 8;
+template <typename R, int N>
+constexpr int rows_swap() {
+  constexpr int E = elems_per_thread<R>(N), T = N / E, K = lane_exchange_kind<N, E>();
+  if (!HP_LANE_SWAP || sizeof(R) != 8) return 0;
+  return ((T == 128 && K == 2) || (T == 256 && K == 4)) ? 32 : 0;
 }
-__device__ __forceinline__ int rows_swap_thread(int tl) {
+// j of the thread with index tl within its line: 128 threads, j ^ 64 at lane ^ 32;
+// 256 threads, j >> 6 in lane bits 4-5
+template <typename R, int N>
+__device__ __forceinline__ int rows_thread(int tl) {
+  constexpr int T = N / elems_per_thread<R>(N);
   const int lane = tl & 63;
-  return (lane & 31) | (((tl >> 6) & 1) << 5) | ((lane >> 5) << 6);
+  if constexpr (rows_swap<R, N>() != 0 && T == 128) return (lane & 31) | (((tl >> 6) & 1) << 5) | ((lane >> 5) << 6);
+  else if constexpr (rows_swap<R, N>() != 0 && T == 256) return ((lane >> 4) << 6) | (((tl >> 6) & 3) << 4) | (lane & 15);
+  else return tl;
 }
 
 // ---------------------------------------------------------------- pass A
@@ -138,9 +150,8 @@ __device__ __forceinline__ void rows_fwd_body(const cpx<TI>* __restrict__ in, cp
                                               size_t in_rs, size_t out_rs, const cpx<R>* __restrict__ tw, int bx,
                                               int rhs, cpx<R>* lds) {
   using C = RowCfg<R, N>;
-  constexpr bool SWP = rows_lane_swap<R, N, C::G>();
-  const int tl = (int)threadIdx.x % C::T;
-  const int g = threadIdx.x / C::T, j = SWP ? rows_swap_thread(tl) : tl;
+  constexpr int SWP = rows_swap<R, N>();
+  const int g = threadIdx.x / C::T, j = rows_thread<R, N>((int)threadIdx.x % C::T);
   const int row = bx * C::G + g;
   const bool act = row < rows;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + (size_t)row * N;
@@ -213,13 +224,15 @@ constexpr int cols_smask_words() {
   return MODE == 1 ? kMaxNodes * ColsCfg<R, N, MODE>::T : 1;
 }
 
-// The symbol pass of 1024-point FP64 columns (two columns of 128 threads per
-// workgroup) takes the same lane exchange.
+// The symbol pass takes the same lane exchange for its 1024-point FP64 columns
+// (two columns of 128 threads per workgroup).
 template <typename R, int N, int MODE>
-constexpr bool cols_lane_swap() {
+constexpr int cols_swap() {
   using C = ColsCfg<R, N, MODE>;
-  return HP_LANE_SWAP && MODE == 1 && sizeof(R) == 8 && N == 1024 && C::E == 8 && C::T == 128 && C::TC == 2 &&
-         C::THREADS == 256;
+  return HP_LANE_SWAP && MODE == 1 && sizeof(R) == 8 && lane_exchange_kind<N, C::E>() == 2 && C::T == 128 &&
+                 C::TC == 2 && C::THREADS == 256
+             ? 32
+             : 0;
 }
 
 template <typename R, typename TI, int N, int DIR, int MODE>
@@ -230,15 +243,15 @@ __device__ __forceinline__ void cols_body(
     const NodeConst* __restrict__ nodes, int K, double scale, const uint16_t* __restrict__ store_mask,
     const uint8_t* __restrict__ slab_need, int bx, int by, int bz, int gx, int gy, cpx<R>* lds, uint16_t* smask) {
   using C = ColsCfg<R, N, MODE>;
-  constexpr bool SWP = cols_lane_swap<R, N, MODE>();
+  constexpr int SWP = cols_swap<R, N, MODE>();
   const int z = bz;
   const int rhs = (MODE == 0) ? z / nfields : z;
   const int fld = (MODE == 0) ? z % nfields : 0;
   if (skip != nullptr && skip[rhs] != 0) return;
   // plain passes over node fields: slabs whose points never use this node are skipped
   if (MODE == 0 && slab_need != nullptr && slab_need[(size_t)fld * gy + by] == 0) return;
-  // With the lane exchange (SWP) threads j and j ^ 64 of a column sit at lanes l and
-  // l ^ 32 of one wavefront: lane = (j >> 6) << 5 | (j & 15) << 1 | g, wavefront (j >> 4) & 3.
+  // With the lane exchange threads j and j ^ 64 of a column sit at lanes l and l ^ 32
+  // of one wavefront: lane = (j >> 6) << 5 | (j & 15) << 1 | g, wavefront (j >> 4) & 3.
   const int lane = threadIdx.x & 63;
   const int g = SWP ? (lane & 1) : (int)threadIdx.x % C::TC;
   const int j = SWP ? (((lane >> 1) & 15) | ((int)(threadIdx.x >> 6) << 4) | ((lane >> 5) << 6))
@@ -428,10 +441,10 @@ __device__ __forceinline__ void rows_combine_body(
     for (int i = threadIdx.x; i < kLagTable; i += C::THREADS * NS) slag[i] = lag[i];
     __syncthreads();
   }
-  constexpr bool SWP = rows_lane_swap<R, N, C::G>() && NS == 1;
+  constexpr int SWP = NS == 1 ? rows_swap<R, N>() : 0;
   const int sp = NS > 1 ? (int)threadIdx.x / C::THREADS : 0;
   const int tl = NS > 1 ? (int)threadIdx.x % C::THREADS : (int)threadIdx.x;
-  const int g = tl / C::T, j = SWP ? rows_swap_thread(tl) : tl % C::T;
+  const int g = tl / C::T, j = SWP ? rows_thread<R, N>(tl % C::T) : tl % C::T;
   const int row = bx * C::G + g;
   const bool act = row < rows;
   const size_t rbase = (size_t)row * N;
