@@ -82,6 +82,10 @@ struct hp_plan_s {
   double rows_used = 0;    // sum over pass-C rows of the nodes the row uses
   double slabs_used = 0;   // sum over nodes of the axis-0 indices that use the node
   DevBuf t, fields;                  // apply workspace
+  // Who last wrote t, in enqueue order: a solver session whose fused Arnoldi update
+  // left the row transform of its u_{t_step} there, or nobody (an apply overwrote it).
+  const void* t_owner = nullptr;
+  int t_step = -1;
   // solver workspace of hp_solve (sessions created with hp_solver_create own theirs)
   struct SolverWs* solver_ws_ptr = nullptr;
   int arnoldi_k = -1;   // basis vectors the last hp_arnoldi left in that workspace (-1: none)
@@ -703,6 +707,13 @@ constexpr size_t kGroupMaxPts = (size_t)1 << 21;
 #define HP_SOLO_GROUPED 1
 #endif
 constexpr bool kSoloGrouped = HP_SOLO_GROUPED != 0;
+// FP64 2-D grids with rows of 1024 or 2048 points: the update of Arnoldi step j
+// also transforms u_{j+1} along the rows (pass A of step j + 1), whose apply then
+// starts at pass B (HP_FUSE_PASS_A=0: separate passes).
+#ifndef HP_FUSE_PASS_A
+#define HP_FUSE_PASS_A 1
+#endif
+constexpr bool kFusePassA = HP_FUSE_PASS_A != 0;
 
 // Pass timer: launches recorded per read at most (later ones are not timed).
 constexpr size_t kMaxTimedLaunches = 1 << 16;
@@ -732,11 +743,14 @@ struct ApplyWs {
   void* fields;
 };
 
+// from_b: pass A's output is already in the plan's t (the fused update of the
+// previous Arnoldi step wrote it); the apply starts at pass B.
 hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, void* u, int out_kind,
                      size_t out_rs, bool acc, int nrhs, const int* skip, hipStream_t st,
-                     hipEvent_t* ev = nullptr, int reps = 1, const ApplyWs* ws = nullptr) {
+                     hipEvent_t* ev = nullptr, int reps = 1, const ApplyWs* ws = nullptr, bool from_b = false) {
   const int rk = P->real_kind();
   void* const wt = ws ? ws->t : P->t.p;
+  if (!ws && !from_b) P->t_owner = nullptr;
   void* const wf = ws ? ws->fields : P->fields.p;
   const size_t np = P->npts;
   hipError_t e;
@@ -756,7 +770,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
     return launch(tev);
   };
   if ((e = mark(0)) != hipSuccess) return e;
-  for (int r = 0; r < reps; ++r) {
+  for (int r = 0; r < (from_b ? 0 : reps); ++r) {
     e = timed(0, [&](const hipEvent_t* tev) {
       return hp::launch_rows_fwd(rk, in_kind, nl, v, wt, rows, in_rs, np, nrhs, P->tw(P->dim - 1), skip,
                                  P->tune[0], st, tev);
@@ -1151,18 +1165,36 @@ struct Session {
       // bitwise the result of the same step inside a grouped launch
       hp::GroupMember gm;
       if (kSoloGrouped && group_member(&gm)) return hp::launch_group_step(&gm, 1, s);
-      if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, s)) != hipSuccess)
+      // step 0 of a cycle transforms u_0 itself; a later step finds it in t when its
+      // own previous update was the last thing enqueued to write t
+      const bool from_b = fused_pass_a() && j > 0 && P->t_owner == this && P->t_step == j;
+      if ((e = run_apply(P, vj, 0, vrs, W->z.p, mixed ? 1 : 0, np, false, nrhs, K.skip_step, s, nullptr, 1, nullptr,
+                         from_b)) != hipSuccess)
         return e;
       if (kFuseStencil && np <= kFuseStencilMaxPts) {
         const hp::StencilArgs sa = stencil_args(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step);
         if ((e = hp::launch_arnoldi_dots_stencil(K, j, sa, s)) != hipSuccess) return e;
-        return hp::launch_arnoldi_update(K, j, s);
+        return update(s);
       }
       if ((e = run_stencil(P, mixed ? 2 : 0, W->z.p, np, vj1, vrs, nullptr, nrhs, K.skip_step, s)) != hipSuccess)
         return e;
     }
     if ((e = hp::launch_arnoldi_dots(K, j, s)) != hipSuccess) return e;
-    return hp::launch_arnoldi_update(K, j, s);
+    return update(s);
+  }
+
+  // The right-preconditioned steps of FP64 2-D grids whose rows the fused update
+  // transforms (not in captured step graphs: a replay cannot see who wrote t last).
+  bool fused_pass_a() const {
+    return kFusePassA && !use_graphs && o.side == HP_RIGHT &&
+           hp::update_rows_fits(P->real_kind(), P->dim, P->n[P->dim - 1]);
+  }
+  hipError_t update(hipStream_t s) {
+    if (!fused_pass_a()) return hp::launch_arnoldi_update(K, j, s);
+    hipError_t e = hp::launch_arnoldi_update_rows(K, j, P->t.p, P->n[P->dim - 1], P->tw(P->dim - 1), s);
+    P->t_owner = e == hipSuccess ? this : nullptr;
+    P->t_step = j + 1;
+    return e;
   }
 
   // Step j as a graph: captured once per workspace configuration on the private

@@ -2146,6 +2146,81 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(cpx<double>* __restrict_
 }
 
 
+// The update for FP64 2-D grids whose rows (1024 or 2048 points) run the register
+// transform: each workgroup updates whole rows of v_j and u_{j+1} (the same sums in
+// the same order as k_arnoldi_update, over pairs of basis vectors) and, with u_{j+1}
+// still in registers, transforms it along the rows into t: pass A of the next
+// step's apply, whose launch and whose read of u_{j+1} are saved.
+template <int N>
+__global__ __launch_bounds__((RowCfg<double, N>::THREADS)) void k_arnoldi_update_rows(
+    cpx<double>* __restrict__ V, size_t npts, size_t vrs, const KState* __restrict__ state,
+    const int* __restrict__ skip_step, int j, cpx<double>* __restrict__ t, int rows,
+    const cpx<double>* __restrict__ tw) {
+  using C = RowCfg<double, N>;
+  __shared__ cpx<double> ca[kMaxRestart + 8], cc[kMaxRestart + 8];
+  __shared__ cpx<double> lds[C::LDS];
+  const int rhs = blockIdx.y;
+  const KState& S = state[rhs];
+  if (skip_step[rhs] && S.stop_at != j) return;
+  for (int i = threadIdx.x; i < kMaxRestart + 8; i += blockDim.x) {
+    ca[i] = i < j ? S.av[i] : cpx<double>{0.0, 0.0};
+    cc[i] = i < j ? S.cv[i] : cpx<double>{0.0, 0.0};
+  }
+  __syncthreads();
+  const double isg = S.inv_sigma;
+  const cpx<double> cu = S.cu;
+  const int g = threadIdx.x / C::T;
+  const int jj = rows_thread<double, N>((int)threadIdx.x % C::T);
+  const int row = blockIdx.x * C::G + g;
+  const bool act = row < rows;
+  const size_t base = (size_t)(act ? row : 0) * N + jj;   // inactive rows load row 0 and store nothing
+  cpx<double>* Vr = V + (size_t)rhs * vrs;
+  cpx<double> sa[C::E], sc[C::E];
+#pragma unroll
+  for (int q = 0; q < C::E; ++q) { sa[q] = {0.0, 0.0}; sc[q] = {0.0, 0.0}; }
+  constexpr int kPair = 2;
+  for (int v0 = 0; v0 < j; v0 += kPair) {
+    cpx<double> xv[kPair][C::E];
+#pragma unroll
+    for (int u = 0; u < kPair; ++u) {
+      const int k = v0 + u < j ? v0 + u : j - 1;   // past v_{j-1} the coefficient is zero
+#pragma unroll
+      for (int q = 0; q < C::E; ++q) xv[u][q] = Vr[(size_t)k * npts + base + C::T * q];
+    }
+#pragma unroll
+    for (int u = 0; u < kPair; ++u) {
+      const cpx<double> a = ca[v0 + u], c = cc[v0 + u];
+#pragma unroll
+      for (int q = 0; q < C::E; ++q) {
+        sa[q].re += a.re * xv[u][q].re - a.im * xv[u][q].im;
+        sa[q].im += a.re * xv[u][q].im + a.im * xv[u][q].re;
+        sc[q].re += c.re * xv[u][q].re - c.im * xv[u][q].im;
+        sc[q].im += c.re * xv[u][q].im + c.im * xv[u][q].re;
+      }
+    }
+  }
+  cpx<double>* U = Vr + (size_t)j * npts;
+  cpx<double>* W = Vr + (size_t)(j + 1) * npts;
+  cpx<double> x[C::E];
+#pragma unroll
+  for (int q = 0; q < C::E; ++q) {
+    const size_t i = base + C::T * q;
+    const cpx<double> u = U[i], w = W[i];
+    const cpx<double> cuu = cmul(cu, u);
+    x[q] = {w.re * isg - sc[q].re - cuu.re, w.im * isg - sc[q].im - cuu.im};
+    if (act) {
+      U[i] = cscale(csub(u, sa[q]), isg);
+      W[i] = x[q];
+    }
+  }
+  fft_e<double, N, C::E, -1, true, 1, false, rows_swap<double, N>()>(x, lds + g * lds_elems<double>(N), jj, tw);
+  if (act) {
+    cpx<double>* dst = t + (size_t)rhs * npts + (size_t)row * N;
+#pragma unroll
+    for (int q = 0; q < C::E; ++q) dst[jj + C::T * q] = x[q];
+  }
+}
+
 // The update of k_arnoldi_update for the grouped launches (bx, gx: this workgroup's
 // index among the gx of one right-hand side).  The single-plan kernel keeps its own
 // copy: its code, and so its rounding, stays exactly as it was.
@@ -2535,6 +2610,24 @@ hipError_t launch_arnoldi_dots_stencil(const KrylovArgs& a, int j, const Stencil
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_arnoldi_fin, dim3(a.nrhs), dim3(kFinThreads), 0, st, (const cpx<double>*)a.part, a.skip_step,
                      a.state, j, a.restart, a.host_stop);
+  return hipGetLastError();
+}
+
+bool update_rows_fits(int real_kind, int dim, int n_last) {
+  return real_kind == 0 && dim == 2 && (n_last == 1024 || n_last == 2048);
+}
+
+hipError_t launch_arnoldi_update_rows(const KrylovArgs& a, int j, void* t, int n_last, const void* tw,
+                                      hipStream_t st) {
+  const int rows = (int)(a.npts / (size_t)n_last);
+  auto go = [&](auto kern, int G, int threads) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + G - 1) / G), a.nrhs), dim3(threads), 0, st, a.V, a.npts, a.vrs,
+                       (const KState*)a.state, (const int*)a.skip_step, j, (cpx<double>*)t, rows,
+                       (const cpx<double>*)tw);
+  };
+  if (n_last == 1024) go(k_arnoldi_update_rows<1024>, RowCfg<double, 1024>::G, RowCfg<double, 1024>::THREADS);
+  else if (n_last == 2048) go(k_arnoldi_update_rows<2048>, RowCfg<double, 2048>::G, RowCfg<double, 2048>::THREADS);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
