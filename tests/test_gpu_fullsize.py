@@ -182,11 +182,12 @@ def test_mixed_served_mix_with_3d_requests(orc, dev):
 
 
 @pytest.mark.parametrize("shape,mode", [((32, 256), "lagrange"), ((16, 1024), "lagrange"), ((24, 512), "bilinear"),
-                                        ((16, 1024), "bilinear"), ((16, 16, 256), "lagrange")])
+                                        ((16, 1024), "bilinear"), ((16, 16, 256), "lagrange"),
+                                        ((16, 2048), "lagrange"), ((16, 2048), "bilinear")])
 def test_mixed_combine_modes_on_long_rows(orc, hp, dev, shape, mode):
     """Mixed-precision combines of 256- to 1024-point rows (one row per wavefront) in the
     higher-degree and bilinear interpolation modes, against the oracle; FP64 too for
-    1024-point rows."""
+    1024- and 2048-point rows."""
     _case("combine_modes_long_rows", shape=shape, mode=mode)
     nmin = min(shape)
     omega = 2 * np.pi * nmin / 4
@@ -202,7 +203,7 @@ def test_mixed_combine_modes_on_long_rows(orc, hp, dev, shape, mode):
     v = _v32(shape, 53, nrhs=2)
     ue = orc.Problem(shape, omega, c, a, zeta, **kw).apply(v)
     precs = [("mixed", torch.complex64, 1e-5)]
-    if shape[-1] == 1024:   # FP64 1024-point rows take the lane exchange in every combine mode
+    if shape[-1] >= 1024:   # FP64 1024- and 2048-point rows take the lane exchange in every combine mode
         precs.append(("fp64", torch.complex128, 1e-12))
     for prec, dt, tol in precs:
         plan = hp.Plan(shape, omega, c, a, zeta, precision=prec, max_nrhs=2, **kw)
