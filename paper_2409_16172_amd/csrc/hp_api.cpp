@@ -707,7 +707,7 @@ constexpr size_t kGroupMaxPts = (size_t)1 << 21;
 #define HP_SOLO_GROUPED 1
 #endif
 constexpr bool kSoloGrouped = HP_SOLO_GROUPED != 0;
-// FP64 2-D grids with rows of 1024 or 2048 points: the update of Arnoldi step j
+// FP64 2-D grids with rows of 512, 1024 or 2048 points: the update of Arnoldi step j
 // also transforms u_{j+1} along the rows (pass A of step j + 1), whose apply then
 // starts at pass B (HP_FUSE_PASS_A=0: separate passes).
 #ifndef HP_FUSE_PASS_A

@@ -202,7 +202,7 @@ hipError_t launch_arnoldi_dots(const KrylovArgs& a, int j, hipStream_t st);
 hipError_t launch_arnoldi_dots_stencil(const KrylovArgs& a, int j, const StencilArgs& s, hipStream_t st);
 // Arnoldi step j: slot j <- v_j, slot j+1 <- u_{j+1}.
 hipError_t launch_arnoldi_update(const KrylovArgs& a, int j, hipStream_t st);
-// The same for FP64 2-D grids with rows of 1024 or 2048 points (update_rows_fits),
+// The same for FP64 2-D grids with rows of 512, 1024 or 2048 points (update_rows_fits),
 // which also writes the row transform of u_{j+1} into t ([nrhs][npts]), pass A of
 // the next step's apply.
 bool update_rows_fits(int real_kind, int dim, int n_last);

@@ -2146,7 +2146,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(cpx<double>* __restrict_
 }
 
 
-// The update for FP64 2-D grids whose rows (1024 or 2048 points) run the register
+// The update for FP64 2-D grids whose rows (512 to 2048 points) run the register
 // transform: each workgroup updates whole rows of v_j and u_{j+1} (the same sums in
 // the same order as k_arnoldi_update, over pairs of basis vectors) and, with u_{j+1}
 // still in registers, transforms it along the rows into t: pass A of the next
@@ -2613,8 +2613,11 @@ hipError_t launch_arnoldi_dots_stencil(const KrylovArgs& a, int j, const Stencil
   return hipGetLastError();
 }
 
+// Rows of 512, 1024 and 2048 points.  Rows of 256 points (one workgroup per eight
+// rows: a quarter of the plain update's workgroups on a 256^2 grid) measured no
+// faster: 256^2 FP64 solve 4.82 -> 4.85 ms, 512^2 4.44 -> 4.38 ms.
 bool update_rows_fits(int real_kind, int dim, int n_last) {
-  return real_kind == 0 && dim == 2 && (n_last == 1024 || n_last == 2048);
+  return real_kind == 0 && dim == 2 && (n_last == 512 || n_last == 1024 || n_last == 2048);
 }
 
 hipError_t launch_arnoldi_update_rows(const KrylovArgs& a, int j, void* t, int n_last, const void* tw,
@@ -2625,7 +2628,8 @@ hipError_t launch_arnoldi_update_rows(const KrylovArgs& a, int j, void* t, int n
                        (const KState*)a.state, (const int*)a.skip_step, j, (cpx<double>*)t, rows,
                        (const cpx<double>*)tw);
   };
-  if (n_last == 1024) go(k_arnoldi_update_rows<1024>, RowCfg<double, 1024>::G, RowCfg<double, 1024>::THREADS);
+  if (n_last == 512) go(k_arnoldi_update_rows<512>, RowCfg<double, 512>::G, RowCfg<double, 512>::THREADS);
+  else if (n_last == 1024) go(k_arnoldi_update_rows<1024>, RowCfg<double, 1024>::G, RowCfg<double, 1024>::THREADS);
   else if (n_last == 2048) go(k_arnoldi_update_rows<2048>, RowCfg<double, 2048>::G, RowCfg<double, 2048>::THREADS);
   else return hipErrorInvalidValue;
   return hipGetLastError();

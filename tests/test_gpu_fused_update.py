@@ -1,5 +1,5 @@
 """The Arnoldi update fused with the next step's row transform (FP64 2-D grids whose
-rows have 1024 or 2048 points): solves reach the oracle's true residual, a batch
+rows have 512, 1024 or 2048 points): solves reach the oracle's true residual, a batch
 equals its right-hand sides solved one by one (bitwise), and two solver sessions of
 one plan advanced in turns on one stream equal the same solves run alone (each step
 finds its own row transform in the plan's workspace, or transforms again)."""
@@ -49,12 +49,15 @@ def _problem(name):
         c, a, zeta, omega, f = _thin(shape, 75, 2)
         kw = dict(m_real=6, m_layer=2, a_floor=0.05 * omega)
         return shape, omega, c, a, zeta, f, kw
-    w = inputs.workload("2d_2048_grf", nrhs=2, precision="fp64")   # rows of 2048 points
+    if name == "2d_512_grf":    # rows of 512 points
+        w = inputs.workload("2d_1024_grf", n=512, nrhs=2, precision="fp64")
+    else:                       # rows of 2048 points
+        w = inputs.workload("2d_2048_grf", nrhs=2, precision="fp64")
     kw = dict(m_real=w.m_real, m_layer=w.m_layer, a_floor=w.a_floor)
     return w.shape, w.omega, w.c, w.a, w.zeta, w.f, kw
 
 
-@pytest.mark.parametrize("name", ["thin_64x1024", "2d_2048_grf"])
+@pytest.mark.parametrize("name", ["thin_64x1024", "2d_512_grf", "2d_2048_grf"])
 def test_fused_update_batch_and_oracle(orc, hp, dev, name):
     print(f"[case] fused update {name}", flush=True)
     shape, omega, c, a, zeta, f, kw = _problem(name)
