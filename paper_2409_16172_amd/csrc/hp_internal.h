@@ -58,11 +58,24 @@ constexpr int kPartSlots = 2 * kMaxRestart + 4;
 // holds at most E elements of a line: kGenRowE in pass A, gen_e<R>() in the
 // column passes and in pass C.
 constexpr int kGenRowE = 16;
-// column passes and pass C: FP64 lines with 12 elements per thread and at most 512
+// column passes and pass C: FP64 lines with 10 elements per thread and at most 512
 // threads (up to 256 VGPRs), FP32 lines with 8 and at most 1024
-template <typename R> constexpr int gen_e() { return sizeof(R) == 8 ? 12 : 8; }
+template <typename R> constexpr int gen_e() { return sizeof(R) == 8 ? 10 : 8; }
 template <typename R> constexpr int gen_maxthr() { return sizeof(R) == 8 ? 512 : 1024; }
 constexpr int kGenMaxStages = 24;
+constexpr int kGenStageMax = 16;   // largest stage radix (any product of 2, 3 and 5 up to it)
+// Largest stage radix of each mixed-radix kernel (a thread holds up to that many
+// elements in a stage, beside what the kernel keeps across transforms: the spectrum in
+// the symbol pass, sums and interpolation records in pass C), chosen so that none
+// spills and a line of kGenMaxN points still fits the thread limit.
+enum GenKernel { kGenRows = 0, kGenCols = 1, kGenSym = 2, kGenComb = 3 };
+#ifndef HP_GEN_SMAX64
+#define HP_GEN_SMAX64 12
+#endif
+template <typename R>
+constexpr int gen_smax(int k) {
+  return sizeof(R) == 8 ? (k == kGenRows || k == kGenCols ? kGenStageMax : HP_GEN_SMAX64) : (k == kGenRows ? 12 : 8);
+}
 constexpr int kGenMaxN = 4800;
 struct GenPlan {
   int n, nst, nthr, tc;
@@ -70,10 +83,13 @@ struct GenPlan {
 };
 // Fills *gp for length n, E elements per thread and at most maxthr threads per
 // line; false if n is not a product of 2, 3 and 5 within kGenMaxN or does not fit.
-// order: radix schedule (0: 4,2,3,5; 1: 5,3,4,2; 2: 3,5,4,2; 3: 2,4,3,5 — each radix
-// taken as often as it divides what is left); nthr_req > 0 asks for that many threads
-// per line (false if it does not fit E and maxthr).
-bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order = 0, int nthr_req = 0);
+// order: radix schedule (0: the largest stage radix up to kGenStageMax that divides what
+// is left, first — 2400 = 16 15 10; 1: the same stages ascending; 2: the same with the
+// first moved last; 3: radices 4, 2, 3, 5 only, each as often as it divides what is
+// left); nthr_req > 0 asks for that many threads per line (false if it does not fit E
+// and maxthr).
+bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order = 0, int nthr_req = 0,
+                   int smax = kGenStageMax);
 constexpr int kGenOrders = 4;
 // Every mixed-radix kernel can take lines of length n.
 bool gen_length_ok(int n);

@@ -45,9 +45,9 @@ __device__ __forceinline__ cpx<R> cvt(cpx<S> a) {
 #ifndef HP_PREFETCH_C
 #define HP_PREFETCH_C 0
 #endif
-// mixed-radix column and combine passes read their twiddles from a copy in LDS
-// (8-12 % faster at 2400^2-4800^2; pass A keeps them in global memory: the copy would
-// halve its occupancy and costs 2-40 %)
+// mixed-radix column and combine passes gather each stage's twiddles into LDS at the
+// start of a workgroup (consecutive butterflies then read consecutive entries); pass A
+// reads the line's table from global memory (one transform per workgroup)
 #ifndef HP_GEN_LDS_TW
 #define HP_GEN_LDS_TW 1
 #endif
@@ -653,66 +653,200 @@ __global__ __launch_bounds__(64 * kWaveRows, 2) void k_comb_wave(
 
 // ---------------------------------------------------------------- mixed-radix lines
 // Line lengths N = 2^a 3^b 5^c that are not powers of two (the grids of Example 1,
-// Section 5.1).  One line per workgroup, held in LDS (dynamic shared memory, N
-// elements) and transformed by Stockham stages of radix 2, 3, 4 or 5 with a
-// barrier between the reads and the writes of a stage.  In a stage of radix R
-// thread t handles butterflies t, t + T, ... of the N/R (at most E/R of them,
-// which the host's choice of T guarantees) and keeps their outputs in registers
-// until every thread has read its inputs.
+// Section 5.1).  One line per workgroup (or tc interleaved lines), held in LDS
+// (dynamic shared memory) and transformed by Stockham stages whose radix is any
+// product of 2, 3 and 5 up to 16 (a 2400-point line takes three stages, 16, 15
+// and 10), each stage's DFT done in registers as two passes of radix 2, 3, 4 or 5
+// with fixed roots between them.  In a stage of radix R thread t handles
+// butterflies t, t + T, ... of the N/R (at most 16/R of them, which the host's
+// choice of T guarantees) and keeps their outputs in registers until every thread
+// has read its inputs.  Element p of a line sits at LDS slot p + p/16 (one pad per
+// 16 elements), which spreads the strided writes of the early stages over the banks.
 
-// exp(DIR 2 pi i m / RAD) for the small radices.
-template <typename R, int RAD, int DIR>
-__device__ __forceinline__ cpx<R> unit_root(int m) {
-  constexpr double c3 = -0.5, s3 = 0.86602540378443864676;                       // 2 pi / 3
-  constexpr double c5a = 0.30901699437494742410, s5a = 0.95105651629515357212;  // 2 pi / 5
-  constexpr double c5b = -0.80901699437494742410, s5b = 0.58778525229247312917; // 4 pi / 5
-  double c = 1.0, sn = 0.0;
-  if constexpr (RAD == 2) { c = m ? -1.0 : 1.0; }
-  else if constexpr (RAD == 3) { if (m) { c = c3; sn = m == 1 ? s3 : -s3; } }
-  else if constexpr (RAD == 4) { const double cc[4] = {1, 0, -1, 0}, ss[4] = {0, 1, 0, -1}; c = cc[m]; sn = ss[m]; }
-  else {
-    const double cc[5] = {1, c5a, c5b, c5b, c5a}, ss[5] = {0, s5a, s5b, -s5b, -s5a};
-    c = cc[m]; sn = ss[m];
+#ifndef HP_GEN_PAD
+#define HP_GEN_PAD 1
+#endif
+__host__ __device__ __forceinline__ int gpos(int p) { return HP_GEN_PAD ? p + (p >> 4) : p; }
+// LDS slots a line of n elements takes
+__host__ __device__ __forceinline__ size_t gen_line_slots(int n) { return (size_t)gpos(n - 1) + 1; }
+
+// cos and sin of 2 pi m / r, evaluated at compile time for the butterflies' fixed
+// roots: the angle is reduced to [0, pi/4] by the octant symmetries (exactly, in
+// integers), then summed as a Taylor series.
+constexpr double kPiD = 3.14159265358979323846;
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 14; ++k) { t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0)); s += t; }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 14; ++k) { t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k)); s += t; }
+  return s;
+}
+// angle 2 pi m / r with 0 <= m <= r/8 (at most pi/4)
+constexpr void small_cs(long m, long r, double& c, double& s) {
+  const double x = 2.0 * kPiD * (double)m / (double)r;
+  c = taylor_cos(x);
+  s = taylor_sin(x);
+}
+constexpr void root_cs(long m, long r, double& c, double& s) {
+  m %= r;
+  double sg = 1.0;
+  if (2 * m > r) { m = r - m; sg = -1.0; }           // sin(2 pi - x) = -sin x
+  double cg = 1.0;                                   // now x in [0, pi]
+  if (4 * m > r) { m = r - 2 * m; cg = -1.0; r *= 2; }  // x -> pi - x: cos flips; m/r -> (r/2 - m)/r
+  // now x = 2 pi m / r in [0, pi/2]
+  double cc = 0.0, ss = 0.0;
+  if (8 * m > r) {                                   // x -> pi/2 - x swaps cos and sin
+    small_cs(r - 4 * m, 4 * r, ss, cc);
+  } else {
+    small_cs(m, r, cc, ss);
   }
-  return {(R)c, (R)(DIR * sn)};
+  c = cg * cc;
+  s = sg * ss;
+}
+template <int RAD>
+struct RootTab {
+  double c[RAD], s[RAD];
+};
+template <int RAD>
+constexpr RootTab<RAD> make_roots() {
+  RootTab<RAD> t{};
+  for (int m = 0; m < RAD; ++m) root_cs(m, RAD, t.c[m], t.s[m]);
+  return t;
+}
+template <int RAD>
+constexpr RootTab<RAD> kRoots = make_roots<RAD>();
+
+// x exp(DIR 2 pi i m / RAD) for a fixed m (the quarter turns without multiplies)
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ cpx<R> mul_root(cpx<R> x, int m) {
+  m %= RAD;
+  if (m == 0) return x;
+  if (2 * m == RAD) return {-x.re, -x.im};
+  if (4 * m == RAD) return DIR > 0 ? cpx<R>{-x.im, x.re} : cpx<R>{x.im, -x.re};
+  if (4 * m == 3 * RAD) return DIR > 0 ? cpx<R>{x.im, -x.re} : cpx<R>{-x.im, x.re};
+  const R c = (R)kRoots<RAD>.c[m], sn = (R)(DIR * kRoots<RAD>.s[m]);
+  return {x.re * c - x.im * sn, x.re * sn + x.im * c};
 }
 
-// out[k] = sum_t v[t] exp(DIR 2 pi i t k / RAD), written out term by term.
+// DFTs of length 2, 3, 4 and 5 in place: out[k] = sum_t v[t] exp(DIR 2 pi i t k / RAD),
+// with the symmetric pairs of terms combined.
+template <typename R, int DIR>
+__device__ __forceinline__ void dft2(cpx<R>& a, cpx<R>& b) {
+  const cpx<R> s = cadd(a, b), d = csub(a, b);
+  a = s;
+  b = d;
+}
+template <typename R, int DIR>
+__device__ __forceinline__ cpx<R> times_dir_i(cpx<R> x) {   // DIR i x
+  return DIR > 0 ? cpx<R>{-x.im, x.re} : cpx<R>{x.im, -x.re};
+}
 template <typename R, int RAD, int DIR>
-__device__ __forceinline__ void dft_small(cpx<R> (&v)[RAD]) {
-  cpx<R> o[RAD];
-#pragma unroll
-  for (int k = 0; k < RAD; ++k) {
-    cpx<R> acc = v[0];
-#pragma unroll
-    for (int t = 1; t < RAD; ++t) acc = cadd(acc, cmul(v[t], unit_root<R, RAD, DIR>((t * k) % RAD)));
-    o[k] = acc;
+__device__ __forceinline__ void dft_prime(cpx<R> (&v)[RAD]) {
+  if constexpr (RAD == 2) {
+    dft2<R, DIR>(v[0], v[1]);
+  } else if constexpr (RAD == 3) {
+    constexpr double s3 = 0.86602540378443864676;   // sin(2 pi / 3)
+    const cpx<R> a = cadd(v[1], v[2]);
+    const cpx<R> d = csub(v[1], v[2]);
+    const cpx<R> m = {v[0].re - (R)0.5 * a.re, v[0].im - (R)0.5 * a.im};
+    const cpx<R> j = times_dir_i<R, DIR>(cpx<R>{(R)s3 * d.re, (R)s3 * d.im});
+    v[0] = cadd(v[0], a);
+    v[1] = cadd(m, j);
+    v[2] = csub(m, j);
+  } else if constexpr (RAD == 4) {
+    const cpx<R> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const cpx<R> s13 = cadd(v[1], v[3]), d13 = times_dir_i<R, DIR>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  } else {
+    static_assert(RAD == 5, "radix 2, 3, 4 or 5");
+    constexpr double c1 = 0.30901699437494742410, s1 = 0.95105651629515357212;   // 2 pi / 5
+    constexpr double c2 = -0.80901699437494742410, s2 = 0.58778525229247312917;  // 4 pi / 5
+    const cpx<R> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const cpx<R> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const cpx<R> m1 = {v[0].re + (R)c1 * a1.re + (R)c2 * a2.re, v[0].im + (R)c1 * a1.im + (R)c2 * a2.im};
+    const cpx<R> m2 = {v[0].re + (R)c2 * a1.re + (R)c1 * a2.re, v[0].im + (R)c2 * a1.im + (R)c1 * a2.im};
+    const cpx<R> j1 = times_dir_i<R, DIR>(cpx<R>{(R)s1 * b1.re + (R)s2 * b2.re, (R)s1 * b1.im + (R)s2 * b2.im});
+    const cpx<R> j2 = times_dir_i<R, DIR>(cpx<R>{(R)s2 * b1.re - (R)s1 * b2.re, (R)s2 * b1.im - (R)s1 * b2.im});
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(m1, j1);
+    v[4] = csub(m1, j1);
+    v[2] = cadd(m2, j2);
+    v[3] = csub(m2, j2);
   }
-#pragma unroll
-  for (int k = 0; k < RAD; ++k) v[k] = o[k];
 }
 
-template <typename R, int RAD, int DIR, int E>
-__device__ void gen_stage(cpx<R>* buf, int ilv, int n, int ns, const cpx<R>* __restrict__ tw, int tid, int nthr) {
-  constexpr int MB = E / RAD;
+// first factor of a stage radix: the DFT of length RAD = F·(RAD/F) runs as RAD/F
+// DFTs of length F, fixed roots, then F DFTs of length RAD/F
+constexpr int radix_first(int r) { return r % 5 == 0 ? 5 : r % 4 == 0 ? 4 : r % 3 == 0 ? 3 : 2; }
+
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ void dft_radix(cpx<R> (&v)[RAD]) {
+  constexpr int F = radix_first(RAD), G = RAD / F;
+  if constexpr (G == 1) {
+    dft_prime<R, RAD, DIR>(v);
+  } else {
+    // input index t = tf G + tg, output index kf + F kg
+    cpx<R> a[G][F];
+#pragma unroll
+    for (int tg = 0; tg < G; ++tg) {
+      cpx<R> u[F];
+#pragma unroll
+      for (int tf = 0; tf < F; ++tf) u[tf] = v[tf * G + tg];
+      dft_prime<R, F, DIR>(u);
+#pragma unroll
+      for (int kf = 0; kf < F; ++kf) a[tg][kf] = mul_root<R, RAD, DIR>(u[kf], tg * kf);
+    }
+#pragma unroll
+    for (int kf = 0; kf < F; ++kf) {
+      cpx<R> u[G];
+#pragma unroll
+      for (int tg = 0; tg < G; ++tg) u[tg] = a[tg][kf];
+      dft_radix<R, G, DIR>(u);
+#pragma unroll
+      for (int kg = 0; kg < G; ++kg) v[kf + F * kg] = u[kg];
+    }
+  }
+}
+
+// One Stockham stage of radix RAD over the line in buf (element p at
+// buf[gpos(p) << lg]) after ns = the product of the earlier radices.  Twiddles:
+// with ST, tw holds this stage's table, entry (t - 1) ns + k = exp(-2 pi i k t /
+// (ns RAD)) (consecutive k for consecutive butterflies); else tw is the line's
+// table exp(-2 pi i j / n).  Indices advance by additions (no integer multiplies
+// per element).
+template <typename R, int RAD, int DIR, bool ST, int SMAX>
+__device__ void gen_stage(cpx<R>* buf, int lg, int n, int ns, const cpx<R>* __restrict__ tw, int tid, int nthr) {
+  constexpr int MB = SMAX / RAD;
   const int nb = n / RAD;
+  const int step = n / (ns * RAD);
   cpx<R> o[MB][RAD];
+  int kk[MB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     const int b = tid + i * nthr;
+    kk[i] = 0;
     if (b < nb) {
-      const int k = b % ns;
+      const int k = ns > 1 ? b % ns : 0;
+      kk[i] = k;
+      int p = b;
 #pragma unroll
-      for (int t = 0; t < RAD; ++t) o[i][t] = buf[(size_t)(b + t * nb) * ilv];
+      for (int t = 0; t < RAD; ++t, p += nb) o[i][t] = buf[gpos(p) << lg];
       if (ns > 1) {
-        const int step = n / (ns * RAD);
+        const int dq = ST ? ns : k * step;
+        int q = ST ? k : dq;
 #pragma unroll
-        for (int t = 1; t < RAD; ++t) {
-          const cpx<R> w = tw[k * t * step];
+        for (int t = 1; t < RAD; ++t, q += dq) {
+          const cpx<R> w = tw[q];
           o[i][t] = DIR < 0 ? cmul(o[i][t], w) : cmulc(o[i][t], w);
         }
       }
-      dft_small<R, RAD, DIR>(o[i]);
+      dft_radix<R, RAD, DIR>(o[i]);
     }
   }
   __syncthreads();
@@ -720,28 +854,58 @@ __device__ void gen_stage(cpx<R>* buf, int ilv, int n, int ns, const cpx<R>* __r
   for (int i = 0; i < MB; ++i) {
     const int b = tid + i * nthr;
     if (b < nb) {
-      const int k = b % ns;
-      const int base = (b / ns) * ns * RAD + k;
+      const int k = kk[i];
+      int p = (b - k) * RAD + k;
 #pragma unroll
-      for (int t = 0; t < RAD; ++t) buf[(size_t)(base + t * ns) * ilv] = o[i][t];
+      for (int t = 0; t < RAD; ++t, p += ns) buf[gpos(p) << lg] = o[i][t];
     }
   }
   __syncthreads();
 }
 
-// In-place transform of the line in buf (element p at buf[p * ilv]); every thread
-// of the workgroup calls it after a barrier that follows the writes of the line.
-template <typename R, int DIR, int E>
-__device__ void fft_gen(cpx<R>* buf, int ilv, const GenPlan& gp, const cpx<R>* __restrict__ tw, int tid) {
+// In-place transform of the line in buf (element p at buf[gpos(p) << lg]); every
+// thread of the workgroup calls it after a barrier that follows the writes of the
+// line.  ST: tw is the stage-layout table gen_stage_twiddles built.  The plan's
+// radices are at most SMAX (a thread holds up to SMAX elements in a stage).
+template <typename R, int DIR, bool ST, int SMAX>
+__device__ void fft_gen(cpx<R>* buf, int lg, const GenPlan& gp, const cpx<R>* __restrict__ tw, int tid) {
   int ns = 1;
+  const cpx<R>* t = tw;
   for (int s = 0; s < gp.nst; ++s) {
-    switch (gp.radix[s]) {
-      case 2: gen_stage<R, 2, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
-      case 3: gen_stage<R, 3, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
-      case 4: gen_stage<R, 4, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
-      default: gen_stage<R, 5, DIR, E>(buf, ilv, gp.n, ns, tw, tid, gp.nthr); break;
+    const int r = gp.radix[s];
+    switch (r) {
+      case 2: gen_stage<R, 2, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 3: gen_stage<R, 3, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 4: gen_stage<R, 4, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 5: gen_stage<R, 5, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 6: if constexpr (SMAX >= 6) gen_stage<R, 6, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 8: if constexpr (SMAX >= 8) gen_stage<R, 8, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 9: if constexpr (SMAX >= 9) gen_stage<R, 9, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 10: if constexpr (SMAX >= 10) gen_stage<R, 10, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 12: if constexpr (SMAX >= 12) gen_stage<R, 12, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      case 15: if constexpr (SMAX >= 15) gen_stage<R, 15, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
+      default: if constexpr (SMAX >= 16) gen_stage<R, 16, DIR, ST, SMAX>(buf, lg, gp.n, ns, t, tid, gp.nthr); break;
     }
-    ns *= gp.radix[s];
+    if (ST && ns > 1) t += (size_t)ns * (r - 1);
+    ns *= r;
+  }
+}
+
+// The stage-layout twiddle table of plan gp (n - radix[0] entries) gathered into
+// stw from the line's table tw by all nthr threads of the workgroup; the caller
+// puts a barrier between this and the first use.
+template <typename R>
+__device__ void gen_stage_twiddles(cpx<R>* stw, const GenPlan& gp, const cpx<R>* __restrict__ tw, int tid,
+                                   int nthr) {
+  int ns = gp.radix[0], off = 0;
+  for (int s = 1; s < gp.nst; ++s) {
+    const int r = gp.radix[s], cnt = ns * (r - 1), step = gp.n / (ns * r);
+    for (int q = tid; q < cnt; q += nthr) {
+      const int t = q / ns + 1, k = q - (t - 1) * ns;
+      stw[off + q] = tw[k * t * step];
+    }
+    off += cnt;
+    ns *= r;
   }
 }
 
@@ -757,15 +921,15 @@ __global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict_
   const int n = gp.n, tid = threadIdx.x;
   const size_t row = blockIdx.x;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + row * n;
-  for (int i = tid; i < n; i += gp.nthr) buf[i] = cvt<R>(src[i]);
+  for (int i = tid; i < n; i += gp.nthr) buf[gpos(i)] = cvt<R>(src[i]);
   __syncthreads();
-  fft_gen<R, -1, kGenRowE>(buf, 1, gp, tw, tid);
+  fft_gen<R, -1, false, gen_smax<R>(kGenRows)>(buf, 0, gp, tw, tid);
   cpx<R>* dst = out + (size_t)rhs * out_rs + row * n;
-  for (int i = tid; i < n; i += gp.nthr) dst[i] = buf[i];
+  for (int i = tid; i < n; i += gp.nthr) dst[i] = buf[gpos(i)];
 }
 
 // Strided axis, gp.tc adjacent columns per workgroup (their lines interleaved
-// in LDS: element p of column g at p*tc + g, so that loads and stores of a
+// in LDS: element p of column g at gpos(p)*tc + g, so that loads and stores of a
 // wavefront touch tc consecutive columns): element (o, p, c) at o*n*S + p*S + c.
 // MODE 0: plain transform (slabs that no point of node field `fld` uses are skipped);
 // MODE 1: forward transform, then for every node symbol multiply and inverse
@@ -779,6 +943,7 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
                                                    const NodeConst* __restrict__ nodes, int K, double scale,
                                                    const uint8_t* __restrict__ need) {
   constexpr int E = gen_e<R>();
+  constexpr bool ST = HP_GEN_LDS_TW != 0;
   extern __shared__ char dyn_lds[];
   const int z = blockIdx.z;
   const int rhs = (MODE == 0) ? z / nfields : z;
@@ -786,7 +951,8 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
   if (skip != nullptr && skip[rhs] != 0) return;
   if (MODE == 0 && need != nullptr && need[(size_t)fld * gridDim.y + blockIdx.y] == 0) return;
   const int n = gp.n, tc = gp.tc, nthr = gp.nthr;
-  const int g = threadIdx.x % tc, tl = threadIdx.x / tc;
+  const int lg = __builtin_ctz(tc);   // tc is a power of two
+  const int g = threadIdx.x & (tc - 1), tl = threadIdx.x >> lg;
   int tile = blockIdx.x;
   if ((gridDim.x & 7) == 0) tile = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);   // XCD-aware
   const int c = tile * tc + g;
@@ -794,21 +960,21 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds) + g;
   const size_t obase = (size_t)blockIdx.y * n * S + (act ? c : 0);
   const cpx<R>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
-  for (int p = tl; p < n; p += nthr) buf[(size_t)p * tc] = act ? src[(size_t)p * S] : cpx<R>{0, 0};
-  if (HP_GEN_LDS_TW) {   // the line's twiddles after the tc lines
-    cpx<R>* stw = reinterpret_cast<cpx<R>*>(dyn_lds) + (size_t)n * tc;
-    for (int p = threadIdx.x; p < n; p += nthr * tc) stw[p] = tw[p];
+  for (int p = tl; p < n; p += nthr) buf[gpos(p) << lg] = act ? src[(size_t)p * S] : cpx<R>{0, 0};
+  if constexpr (ST) {   // the stage twiddle tables after the tc lines
+    cpx<R>* stw = reinterpret_cast<cpx<R>*>(dyn_lds) + gen_line_slots(n) * tc;
+    gen_stage_twiddles<R>(stw, gp, tw, threadIdx.x, nthr * tc);
     tw = stw;
   }
   __syncthreads();
   if constexpr (MODE == 0) {
-    fft_gen<R, DIR, E>(buf, tc, gp, tw, tl);
+    fft_gen<R, DIR, ST, gen_smax<R>(kGenCols)>(buf, lg, gp, tw, tl);
     if (act) {
       cpx<R>* dst = out + (size_t)rhs * out_rs + (size_t)fld * out_fs + obase;
-      for (int p = tl; p < n; p += nthr) dst[(size_t)p * S] = buf[(size_t)p * tc];
+      for (int p = tl; p < n; p += nthr) dst[(size_t)p * S] = buf[gpos(p) << lg];
     }
   } else {
-    fft_gen<R, -1, E>(buf, tc, gp, tw, tl);
+    fft_gen<R, -1, ST, gen_smax<R>(kGenSym)>(buf, lg, gp, tw, tl);
     // the spectrum and lambda of this thread's elements p = tl + nthr * i
     cpx<R> vh[E];
     double lam[E];
@@ -816,7 +982,7 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int p = tl + i * nthr;
-      vh[i] = p < n ? buf[(size_t)p * tc] : cpx<R>{0, 0};
+      vh[i] = p < n ? buf[gpos(p) << lg] : cpx<R>{0, 0};
       lam[i] = p < n ? lam_ax[p] + lc : 0.0;
     }
     cpx<R>* dst = out + (size_t)rhs * out_rs + obase;
@@ -837,15 +1003,15 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
             const float inv = (float)scale * recip(fr * fr + fi * fi);
             q = {fr * inv, -fi * inv};
           }
-          buf[(size_t)p * tc] = cmul(vh[i], q);
+          buf[gpos(p) << lg] = cmul(vh[i], q);
         }
       }
       __syncthreads();
-      fft_gen<R, +1, E>(buf, tc, gp, tw, tl);
+      fft_gen<R, +1, ST, gen_smax<R>(kGenSym)>(buf, lg, gp, tw, tl);
       if (act) {
         const uint8_t* nn = need + (size_t)nd * n;
         for (int p = tl; p < n; p += nthr)
-          if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[(size_t)p * tc];
+          if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[gpos(p) << lg];
       }
     }
   }
@@ -891,22 +1057,23 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
   }
   const uint64_t rm = rowmask[row];
   const cpx<R>* fr = fields + (size_t)rhs * frs + rbase;
-  if (HP_GEN_LDS_TW) {   // the row's twiddles after the line
-    cpx<R>* stw = buf + n;
-    for (int p = tid; p < n; p += nthr) stw[p] = tw[p];
+  constexpr bool ST = HP_GEN_LDS_TW != 0;
+  if constexpr (ST) {   // the stage twiddle tables after the line
+    cpx<R>* stw = buf + gen_line_slots(n);
+    gen_stage_twiddles<R>(stw, gp, tw, tid, nthr);
     tw = stw;
   }
   for (int nd = 0; nd < K; ++nd) {
     if (((rm >> nd) & 1ull) == 0) continue;
-    for (int p = tid; p < n; p += nthr) buf[p] = fr[(size_t)nd * fs + p];
+    for (int p = tid; p < n; p += nthr) buf[gpos(p)] = fr[(size_t)nd * fs + p];
     __syncthreads();
-    fft_gen<R, +1, gen_e<R>()>(buf, 1, gp, tw, tid);
+    fft_gen<R, +1, ST, gen_smax<R>(kGenComb)>(buf, 0, gp, tw, tid);
 #pragma unroll
     for (int i = 0; i < gen_e<R>(); ++i) {
       const int p = tid + i * nthr;
       if (p < n) {
         const R w = interp_weight<R, IM>(ab[i], tt[i], uu[i], nd, ord, slag);
-        const cpx<R> x = buf[p];
+        const cpx<R> x = buf[gpos(p)];
         acc[i].re += w * x.re;
         acc[i].im += w * x.im;
       }
@@ -961,23 +1128,40 @@ struct RowsFwdL {
 };
 
 // ---- mixed-radix launch helpers
-bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order, int nthr_req) {
-  static const int kOrder[kGenOrders][4] = {{4, 2, 3, 5}, {5, 3, 4, 2}, {3, 5, 4, 2}, {2, 4, 3, 5}};
+bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order, int nthr_req, int smax) {
+  static const int kRadices[] = {16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+  static const int kPrimeOrder[4] = {4, 2, 3, 5};
   if (n < 2 || n > kGenMaxN || order < 0 || order >= kGenOrders) return false;
   GenPlan g{};
   g.n = n;
   g.tc = 1;
   int m = n;
-  auto take = [&](int r) {
-    while (m % r == 0 && g.nst < kGenMaxStages) { g.radix[g.nst++] = r; m /= r; }
-  };
-  for (int i = 0; i < 4; ++i) take(kOrder[order][i]);
+  if (order == 3) {   // radices 4, 2, 3, 5 only, each as often as it divides what is left
+    for (int r : kPrimeOrder)
+      while (m % r == 0 && g.nst < kGenMaxStages) { g.radix[g.nst++] = r; m /= r; }
+  } else {            // the largest radix that divides what is left, first
+    while (m > 1 && g.nst < kGenMaxStages) {
+      int pick = 0;
+      for (int r : kRadices)
+        if (r <= smax && m % r == 0) { pick = r; break; }
+      if (pick == 0) break;
+      g.radix[g.nst++] = pick;
+      m /= pick;
+    }
+    if (order == 1) {                       // ascending
+      for (int i = 0, j = g.nst - 1; i < j; ++i, --j) { const int x = g.radix[i]; g.radix[i] = g.radix[j]; g.radix[j] = x; }
+    } else if (order == 2 && g.nst > 1) {   // the largest stage last
+      const int x = g.radix[0];
+      for (int i = 0; i + 1 < g.nst; ++i) g.radix[i] = g.radix[i + 1];
+      g.radix[g.nst - 1] = x;
+    }
+  }
   if (m != 1) return false;
   auto fits = [&](int t) {
     bool ok = (size_t)t * E >= (size_t)n;
     for (int s = 0; s < g.nst && ok; ++s) {
       const int r = g.radix[s];
-      ok = (n / r + t - 1) / t <= E / r;
+      ok = (n / r + t - 1) / t <= smax / r;
     }
     return ok;
   };
@@ -993,34 +1177,41 @@ bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order, int nthr_re
 }
 
 // A pass's plan with its run-time choices, or the built-in one when they do not fit.
-static bool tuned_gen_plan(int n, int E, int maxthr, const PassTune& t, GenPlan* gp) {
-  if ((t.nthr > 0 || t.order > 0) && make_gen_plan(n, E, maxthr, gp, t.order, t.nthr)) return true;
-  return make_gen_plan(n, E, maxthr, gp);
+static bool tuned_gen_plan(int n, int E, int maxthr, const PassTune& t, GenPlan* gp, int smax) {
+  if ((t.nthr > 0 || t.order > 0) && make_gen_plan(n, E, maxthr, gp, t.order, t.nthr, smax)) return true;
+  return make_gen_plan(n, E, maxthr, gp, 0, 0, smax);
 }
 
 bool gen_length_ok(int n) {
-  GenPlan a, b, c;
-  return make_gen_plan(n, kGenRowE, 512, &a) && make_gen_plan(n, gen_e<double>(), gen_maxthr<double>(), &b) &&
-         make_gen_plan(n, gen_e<float>(), gen_maxthr<float>(), &c);
+  bool ok = true;
+  for (int k = kGenRows; k <= kGenComb && ok; ++k) {
+    GenPlan a;
+    const int e64 = k == kGenRows ? kGenRowE : gen_e<double>(), e32 = k == kGenRows ? kGenRowE : gen_e<float>();
+    const int t64 = k == kGenRows ? 512 : gen_maxthr<double>(), t32 = k == kGenRows ? 512 : gen_maxthr<float>();
+    ok = make_gen_plan(n, e64, t64, &a, 0, 0, gen_smax<double>(k)) && make_gen_plan(n, e32, t32, &a, 0, 0, gen_smax<float>(k));
+  }
+  return ok;
 }
 
-// Column passes: as many adjacent columns per workgroup as the thread limit and
-// the LDS (here up to 144 KiB, one workgroup per CU at most) allow, at most 8.
+// Column passes: a power of two of adjacent columns per workgroup (at most 8) within
+// the thread limit and up to 144 KiB of LDS.
 template <typename R>
 static bool col_tc_fits(int n, int S, int nthr, int tc) {
-  return tc >= 1 && tc <= 8 && tc * nthr <= gen_maxthr<R>() &&
-         (size_t)(tc + (HP_GEN_LDS_TW ? 1 : 0)) * n * sizeof(cpx<R>) <= (size_t)144 * 1024 && tc <= S;
+  return tc >= 1 && tc <= 8 && (tc & (tc - 1)) == 0 && tc * nthr <= gen_maxthr<R>() &&
+         (gen_line_slots(n) * tc + (HP_GEN_LDS_TW ? n : 0)) * sizeof(cpx<R>) <= (size_t)144 * 1024 && tc <= S;
 }
 
 template <typename R>
-static bool make_col_plan(int n, int S, GenPlan* gp, const PassTune& t = PassTune{}) {
-  if (!tuned_gen_plan(n, gen_e<R>(), gen_maxthr<R>(), t, gp)) return false;
+static bool make_col_plan(int n, int S, int mode, GenPlan* gp, const PassTune& t = PassTune{}) {
+  if (!tuned_gen_plan(n, gen_e<R>(), gen_maxthr<R>(), t, gp, gen_smax<R>(mode == 1 ? kGenSym : kGenCols))) return false;
   if (t.tc > 0 && col_tc_fits<R>(n, S, gp->nthr, t.tc)) {
     gp->tc = t.tc;
     return true;
   }
+  // up to 256 threads per workgroup, so that two or more workgroups share a CU and
+  // one's barriers overlap another's work
   int tc = 1;
-  while (tc < 8 && col_tc_fits<R>(n, S, gp->nthr, tc * 2)) tc *= 2;
+  while (tc < 8 && tc * 2 * gp->nthr <= 256 && col_tc_fits<R>(n, S, gp->nthr, tc * 2)) tc *= 2;
   gp->tc = tc;
   return true;
 }
@@ -1048,13 +1239,15 @@ int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, Pass
   }
   const int E = kind == kTuneRows ? kGenRowE : (real_kind == 0 ? gen_e<double>() : gen_e<float>());
   const int maxthr = kind == kTuneRows ? 512 : (real_kind == 0 ? gen_maxthr<double>() : gen_maxthr<float>());
+  const int gk = kind == kTuneRows ? kGenRows : kind == kTuneCols ? (mode == 1 ? kGenSym : kGenCols) : kGenComb;
+  const int smax = real_kind == 0 ? gen_smax<double>(gk) : gen_smax<float>(gk);
   for (int order = 0; order < kGenOrders; ++order) {
     GenPlan g;
-    if (!make_gen_plan(n, E, maxthr, &g, order)) continue;
+    if (!make_gen_plan(n, E, maxthr, &g, order, 0, smax)) continue;
     // the smallest thread count that fits, and up to three larger ones
     for (int t = g.nthr, k = 0; t <= maxthr && k < 4; t += 64, ++k) {
       GenPlan h;
-      if (!make_gen_plan(n, E, maxthr, &h, order, t)) continue;
+      if (!make_gen_plan(n, E, maxthr, &h, order, t, smax)) continue;
       if (kind != kTuneCols) {
         push(PassTune{t, 0, order, 0});
         continue;
@@ -1077,7 +1270,7 @@ static void allow_dynamic_lds(K kernel, size_t bytes) {
 template <typename R, typename TI>
 static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int rows, size_t in_rs, size_t out_rs,
                                int nrhs, const void* tw, const int* skip, hipStream_t st, const hipEvent_t* tev) {
-  const size_t lds = (size_t)gp.n * sizeof(cpx<R>);
+  const size_t lds = gen_line_slots(gp.n) * sizeof(cpx<R>);
   allow_dynamic_lds(k_rows_fwd_gen<R, TI>, lds);
   HP_PASS_LAUNCH(tev, (k_rows_fwd_gen<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
                  (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
@@ -1086,7 +1279,7 @@ static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int
 
 template <typename R>
 static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)gp.n * (gp.tc + (HP_GEN_LDS_TW ? 1 : 0)) * sizeof(cpx<R>);
+  const size_t lds = (gen_line_slots(gp.n) * gp.tc + (HP_GEN_LDS_TW ? gp.n : 0)) * sizeof(cpx<R>);
   dim3 grid((a.S + gp.tc - 1) / gp.tc, a.outer, a.mode == 0 ? a.nrhs * a.nfields : a.nrhs);
   const cpx<R>* in = (const cpx<R>*)a.in;
   cpx<R>* out = (cpx<R>*)a.out;
@@ -1112,7 +1305,7 @@ static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st)
 
 template <typename R, typename TO, bool ACC, int IM>
 static hipError_t combine_gen_l(const GenPlan& gp, const CombineArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)gp.n * (HP_GEN_LDS_TW ? 2 : 1) * sizeof(cpx<R>);
+  const size_t lds = (gen_line_slots(gp.n) + (HP_GEN_LDS_TW ? gp.n : 0)) * sizeof(cpx<R>);
   allow_dynamic_lds(k_rows_combine_gen<R, TO, ACC, IM>, lds);
   HP_PASS_LAUNCH(a.tev, (k_rows_combine_gen<R, TO, ACC, IM>), dim3(a.rows, a.nrhs), dim3(gp.nthr), lds, st,
                      (const cpx<R>*)a.fields, a.fs, a.frs, a.pos, a.rowmask, (cpx<TO>*)a.out, a.out_rs, a.K, a.M,
@@ -1136,7 +1329,8 @@ hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, vo
                            const PassTune& tune, hipStream_t st, const hipEvent_t* tev) {
   if (!is_pow2_len(n)) {
     GenPlan gp;
-    if (!tuned_gen_plan(n, kGenRowE, 512, tune, &gp)) return hipErrorInvalidValue;
+    if (!tuned_gen_plan(n, kGenRowE, 512, tune, &gp, real_kind == 0 ? gen_smax<double>(kGenRows) : gen_smax<float>(kGenRows)))
+      return hipErrorInvalidValue;
     if (real_kind == 0) {
       if (in_kind != 0) return hipErrorInvalidValue;
       return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
@@ -1196,8 +1390,8 @@ hipError_t launch_cols(const ColsArgs& a, hipStream_t st) {
   if (cols_use_gen(a.real_kind, a.n)) {
     GenPlan gp;
     if (a.real_kind == 0)
-      return make_col_plan<double>(a.n, a.S, &gp, a.tune) ? cols_gen<double>(gp, a, st) : hipErrorInvalidValue;
-    return make_col_plan<float>(a.n, a.S, &gp, a.tune) ? cols_gen<float>(gp, a, st) : hipErrorInvalidValue;
+      return make_col_plan<double>(a.n, a.S, a.mode, &gp, a.tune) ? cols_gen<double>(gp, a, st) : hipErrorInvalidValue;
+    return make_col_plan<float>(a.n, a.S, a.mode, &gp, a.tune) ? cols_gen<float>(gp, a, st) : hipErrorInvalidValue;
   }
   if (a.real_kind == 0) return dispatch_n<ColsL<double>::F>(a.n, a, st);
   return dispatch_n<ColsL<float>::F>(a.n, a, st);
@@ -1285,8 +1479,9 @@ bool combine_splits_ok(int real_kind, int n) {
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
   if (!is_pow2_len(a.n)) {
     GenPlan gp;
-    if (a.real_kind == 0 ? !tuned_gen_plan(a.n, gen_e<double>(), gen_maxthr<double>(), a.tune, &gp)
-                         : !tuned_gen_plan(a.n, gen_e<float>(), gen_maxthr<float>(), a.tune, &gp))
+    if (a.real_kind == 0
+            ? !tuned_gen_plan(a.n, gen_e<double>(), gen_maxthr<double>(), a.tune, &gp, gen_smax<double>(kGenComb))
+            : !tuned_gen_plan(a.n, gen_e<float>(), gen_maxthr<float>(), a.tune, &gp, gen_smax<float>(kGenComb)))
       return hipErrorInvalidValue;
     if (a.real_kind == 0) {
       if (a.out_kind != 0) return hipErrorInvalidValue;
