@@ -1065,7 +1065,19 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_rows_combine_gen(const cpx<
   }
   for (int nd = 0; nd < K; ++nd) {
     if (((rm >> nd) & 1ull) == 0) continue;
-    for (int p = tid; p < n; p += nthr) buf[gpos(p)] = fr[(size_t)nd * fs + p];
+    {   // the node row's loads issued together, then written to LDS
+      cpx<R> x[gen_e<R>()];
+#pragma unroll
+      for (int i = 0; i < gen_e<R>(); ++i) {
+        const int p = tid + i * nthr;
+        x[i] = p < n ? fr[(size_t)nd * fs + p] : cpx<R>{0, 0};
+      }
+#pragma unroll
+      for (int i = 0; i < gen_e<R>(); ++i) {
+        const int p = tid + i * nthr;
+        if (p < n) buf[gpos(p)] = x[i];
+      }
+    }
     __syncthreads();
     fft_gen<R, +1, ST, gen_smax<R>(kGenComb)>(buf, 0, gp, tw, tid);
 #pragma unroll
