@@ -921,7 +921,19 @@ __global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict_
   const int n = gp.n, tid = threadIdx.x;
   const size_t row = blockIdx.x;
   const cpx<TI>* src = in + (size_t)rhs * in_rs + row * n;
-  for (int i = tid; i < n; i += gp.nthr) buf[gpos(i)] = cvt<R>(src[i]);
+  {   // the row's loads issued together, then written to LDS
+    cpx<R> x[kGenRowE];
+#pragma unroll
+    for (int i = 0; i < kGenRowE; ++i) {
+      const int p = tid + i * gp.nthr;
+      x[i] = p < n ? cvt<R>(src[p]) : cpx<R>{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < kGenRowE; ++i) {
+      const int p = tid + i * gp.nthr;
+      if (p < n) buf[gpos(p)] = x[i];
+    }
+  }
   __syncthreads();
   fft_gen<R, -1, false, gen_smax<R>(kGenRows)>(buf, 0, gp, tw, tid);
   cpx<R>* dst = out + (size_t)rhs * out_rs + row * n;
@@ -960,7 +972,19 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds) + g;
   const size_t obase = (size_t)blockIdx.y * n * S + (act ? c : 0);
   const cpx<R>* src = in + (size_t)rhs * in_rs + (size_t)fld * in_fs + obase;
-  for (int p = tl; p < n; p += nthr) buf[gpos(p) << lg] = act ? src[(size_t)p * S] : cpx<R>{0, 0};
+  {   // the column's loads issued together, then written to LDS
+    cpx<R> x[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int p = tl + i * nthr;
+      x[i] = (act && p < n) ? src[(size_t)p * S] : cpx<R>{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int p = tl + i * nthr;
+      if (p < n) buf[gpos(p) << lg] = x[i];
+    }
+  }
   if constexpr (ST) {   // the stage twiddle tables after the tc lines
     cpx<R>* stw = reinterpret_cast<cpx<R>*>(dyn_lds) + gen_line_slots(n) * tc;
     gen_stage_twiddles<R>(stw, gp, tw, threadIdx.x, nthr * tc);
