@@ -81,6 +81,7 @@ struct hp_plan_s {
   // node usage counts for the byte model of the passes
   double rows_used = 0;    // sum over pass-C rows of the nodes the row uses
   double slabs_used = 0;   // sum over nodes of the axis-0 indices that use the node
+  int smask_thr = 0;       // mixed-radix lengths: threads per line storemask was built for
   DevBuf t, fields;                  // apply workspace
   // Who last wrote t, in enqueue order: a solver session whose fused Arnoldi update
   // left the row transform of its u_{t_step} there, or nobody (an apply overwrote it).
@@ -587,17 +588,26 @@ hp_status hp_plan_create(hp_plan* out, const hp_grid* grid, double omega, const 
     for (int k = 0; k < P->K; ++k)
       if ((m >> k) & 1ull) { need[(size_t)k * n0 + i0] = 1; P->slabs_used += 1.0; }
   }
-  // store masks of the power-of-two symbol pass: bit e of thread j = axis-0 index
-  // j + Tb*e (the LDS-resident column kernels read `need` directly)
+  // store masks of the symbol pass: bit e of thread j = axis-0 index j + Tb*e (for
+  // mixed-radix lengths, with the built-in plan's Tb; a tuned plan with another
+  // thread count reads `need` directly)
   std::vector<uint16_t> smask(1, 0);
-  if (!hp::cols_use_gen(P->real_kind(), n0)) {
-    const int Tb = hp::symbol_pass_line_threads(P->real_kind(), n0);
-    const int Eb = n0 / Tb;
-    smask.assign((size_t)P->K * Tb, 0);
-    for (int k = 0; k < P->K; ++k)
-      for (int j = 0; j < Tb; ++j)
-        for (int e2 = 0; e2 < Eb; ++e2)
-          if (need[(size_t)k * n0 + j + (size_t)Tb * e2]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e2);
+  P->smask_thr = 0;
+  {
+    const bool gen = hp::cols_use_gen(P->real_kind(), n0);
+    const int Tb = gen ? hp::gen_symbol_line_threads(P->real_kind(), n0)
+                       : hp::symbol_pass_line_threads(P->real_kind(), n0);
+    const int Eb = gen ? hp::gen_symbol_elems(P->real_kind()) : n0 / Tb;
+    if (Tb > 0 && Eb <= 16) {
+      if (gen) P->smask_thr = Tb;
+      smask.assign((size_t)P->K * Tb, 0);
+      for (int k = 0; k < P->K; ++k)
+        for (int j = 0; j < Tb; ++j)
+          for (int e2 = 0; e2 < Eb; ++e2) {
+            const size_t p = (size_t)j + (size_t)Tb * e2;
+            if (p < (size_t)n0 && need[(size_t)k * n0 + p]) smask[(size_t)k * Tb + j] |= (uint16_t)(1u << e2);
+          }
+    }
   }
 
   if ((e = upload(P->nodes, nc)) != hipSuccess) return failc(from_hip(e));
@@ -795,6 +805,7 @@ hipError_t run_apply(hp_plan_s* P, const void* v, int in_kind, size_t in_rs, voi
   b.lam_ax = (const double*)P->lam_ax.p; b.lam_in = (const double*)P->lam_in.p;
   b.nodes = (const hp::NodeConst*)P->nodes.p; b.K = P->K; b.scale = 1.0 / (double)np;
   b.store_mask = (const uint16_t*)P->storemask.p;
+  b.store_mask_thr = P->smask_thr;
   b.store_need = (const uint8_t*)P->slabneed.p;
   b.tune = P->tune[2];
   for (int r = 0; r < reps; ++r)

@@ -142,6 +142,7 @@ struct ColsArgs {
   int K;
   double scale;
   const uint16_t* store_mask;   // mode 1: [K][T] bit s = axis-0 index j + T*s uses node n
+  int store_mask_thr;           // mixed-radix lengths: the T store_mask was built for (0: none)
   const uint8_t* slab_need;     // mode 0 over node fields: [K][outer] != 0 if the slab uses node n
   const uint8_t* store_need;    // mode 1, mixed-radix lengths: [K][n] != 0 if axis-0 index p uses node n
   PassTune tune;
@@ -175,6 +176,10 @@ constexpr int kLagTable = kMaxNodes * 5;
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
 int combine_group_rows(int real_kind, int n);        // rows per workgroup of pass C
 int symbol_pass_line_threads(int real_kind, int n);  // threads per line T of pass B
+// threads per line of the built-in mixed-radix symbol-pass plan (0 if n has none) and
+// the elements each thread holds
+int gen_symbol_line_threads(int real_kind, int n);
+int gen_symbol_elems(int real_kind);
 
 // Stencil.  kind: 0 = FP64 (c128 -> c128), 1 = FP32 arithmetic c64 -> c64,
 // 2 = FP32 arithmetic c64 -> c128, 3 = FP64 residual y = f - P u (c128).

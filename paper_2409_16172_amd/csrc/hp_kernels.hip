@@ -953,7 +953,8 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
                                                    const int* __restrict__ skip, const double* __restrict__ lam_ax,
                                                    const double* __restrict__ lam_in,
                                                    const NodeConst* __restrict__ nodes, int K, double scale,
-                                                   const uint8_t* __restrict__ need) {
+                                                   const uint8_t* __restrict__ need,
+                                                   const uint16_t* __restrict__ smask) {
   constexpr int E = gen_e<R>();
   constexpr bool ST = HP_GEN_LDS_TW != 0;
   extern __shared__ char dyn_lds[];
@@ -1033,9 +1034,18 @@ __global__ __launch_bounds__(gen_maxthr<R>()) void k_cols_gen(const cpx<R>* __re
       __syncthreads();
       fft_gen<R, +1, ST, gen_smax<R>(kGenSym)>(buf, lg, gp, tw, tl);
       if (act) {
-        const uint8_t* nn = need + (size_t)nd * n;
-        for (int p = tl; p < n; p += nthr)
-          if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[gpos(p) << lg];
+        if (smask != nullptr) {   // one packed word per thread and node: bit i = element tl + i nthr
+          const unsigned m = smask[(size_t)nd * nthr + tl];
+          for (int i = 0; i < E; ++i)
+            if ((m >> i) & 1u) {
+              const int p = tl + i * nthr;
+              dst[(size_t)nd * out_fs + (size_t)p * S] = buf[gpos(p) << lg];
+            }
+        } else {
+          const uint8_t* nn = need + (size_t)nd * n;
+          for (int p = tl; p < n; p += nthr)
+            if (nn[p]) dst[(size_t)nd * out_fs + (size_t)p * S] = buf[gpos(p) << lg];
+        }
       }
     }
   }
@@ -1322,19 +1332,20 @@ static hipError_t cols_gen(const GenPlan& gp, const ColsArgs& a, hipStream_t st)
   const cpx<R>* tw = (const cpx<R>*)a.tw;
   if (a.mode == 1) {
     allow_dynamic_lds(k_cols_gen<R, -1, 1>, lds);
+    const uint16_t* sm = (a.store_mask_thr == gp.nthr && a.store_mask_thr > 0) ? a.store_mask : nullptr;
     HP_PASS_LAUNCH(a.tev, (k_cols_gen<R, -1, 1>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
-                       a.store_need);
+                       a.store_need, sm);
   } else if (a.dir < 0) {
     allow_dynamic_lds(k_cols_gen<R, -1, 0>, lds);
     HP_PASS_LAUNCH(a.tev, (k_cols_gen<R, -1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
-                       a.slab_need);
+                       a.slab_need, nullptr);
   } else {
     allow_dynamic_lds(k_cols_gen<R, +1, 0>, lds);
     HP_PASS_LAUNCH(a.tev, (k_cols_gen<R, +1, 0>), grid, dim3(gp.nthr * gp.tc), lds, st, in, out, a.S, a.nfields, a.in_rs,
                        a.out_rs, a.in_fs, a.out_fs, gp, tw, a.skip, a.lam_ax, a.lam_in, a.nodes, a.K, a.scale,
-                       a.slab_need);
+                       a.slab_need, nullptr);
   }
   return hipGetLastError();
 }
@@ -1578,6 +1589,15 @@ int sym_line_threads(int n) {
 int symbol_pass_line_threads(int real_kind, int n) {
   return real_kind == 0 ? sym_line_threads<double>(n) : sym_line_threads<float>(n);
 }
+
+int gen_symbol_line_threads(int real_kind, int n) {
+  GenPlan g;
+  const bool ok = real_kind == 0
+                      ? make_gen_plan(n, gen_e<double>(), gen_maxthr<double>(), &g, 0, 0, gen_smax<double>(kGenSym))
+                      : make_gen_plan(n, gen_e<float>(), gen_maxthr<float>(), &g, 0, 0, gen_smax<float>(kGenSym));
+  return ok ? g.nthr : 0;
+}
+int gen_symbol_elems(int real_kind) { return real_kind == 0 ? gen_e<double>() : gen_e<float>(); }
 
 int combine_group_rows(int real_kind, int n) {
   return real_kind == 0 ? group_rows<double>(n) : group_rows<float>(n);
