@@ -1,7 +1,7 @@
 """Mixed-radix lines under every radix schedule the plans offer (largest radix first,
 ascending, largest last, radices 2-5 only), forced through the tuning cache: each
 schedule's applies agree with the oracle on 2-D and 3-D grids whose lines take
-composite stage radices 6, 8, 9, 10, 12, 15 and 16 (and a 4800-point line)."""
+composite stage radices 6, 8, 9, 10, 12, 15 and 16 (and 2880-, 3600- and 4800-point lines)."""
 import numpy as np
 import pytest
 import torch
@@ -36,7 +36,7 @@ def _problem(shape, seed):
 
 
 CASES = [((240, 360), "fp64"), ((150, 96), "mixed"), ((18, 4800), "fp64"), ((36, 90, 80), "fp64"),
-         ((30, 12, 18), "mixed")]
+         ((30, 12, 18), "mixed"), ((4800, 10), "mixed"), ((10, 3600), "mixed"), ((2880, 12), "fp64")]
 
 
 @pytest.mark.parametrize("order", [0, 1, 2, 3])
