@@ -1217,6 +1217,11 @@ bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order, int nthr_re
     *gp = g;
     return true;
   }
+  // the smallest power of two of wavefronts that fits: workgroups of 1, 2, 4 or 8
+  // wavefronts fill a CU's wave slots evenly at two waves per SIMD (5-7 would leave
+  // slots empty beside a second workgroup that does not fit)
+  for (int t = 64; t <= maxthr; t *= 2)
+    if (fits(t)) { g.nthr = t; *gp = g; return true; }
   for (int t = 64; t <= maxthr; t += 64)
     if (fits(t)) { g.nthr = t; *gp = g; return true; }
   return false;
@@ -1290,8 +1295,18 @@ int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, Pass
   for (int order = 0; order < kGenOrders; ++order) {
     GenPlan g;
     if (!make_gen_plan(n, E, maxthr, &g, order, 0, smax)) continue;
-    // the smallest thread count that fits, and up to three larger ones
-    for (int t = g.nthr, k = 0; t <= maxthr && k < 4; t += 64, ++k) {
+    // the smallest thread count that fits and up to three larger ones, and the
+    // built-in (power-of-two) one
+    int tmin = 0;
+    for (int t = 64; t <= maxthr && tmin == 0; t += 64) {
+      GenPlan h;
+      if (make_gen_plan(n, E, maxthr, &h, order, t, smax)) tmin = t;
+    }
+    int cand[5], nc = 0;
+    for (int t = tmin, k = 0; tmin > 0 && t <= maxthr && k < 4; t += 64, ++k) cand[nc++] = t;
+    if (g.nthr >= tmin + 4 * 64) cand[nc++] = g.nthr;
+    for (int ci = 0; ci < nc; ++ci) {
+      const int t = cand[ci];
       GenPlan h;
       if (!make_gen_plan(n, E, maxthr, &h, order, t, smax)) continue;
       if (kind != kTuneCols) {
