@@ -99,7 +99,7 @@ def cpu_baseline(w, gpu_iters, gpu_cycles, restart=30, rtol=1e-8):
                           f"{nthreads} threads: {t_omp:.1f} s"})
     from paper_2409_16172_amd import inputs
     w0 = inputs.workload("2d_64_bump")
-    cfg0 = {}
+    bump = {}
     for omp in (False, True):
         nt = oracle.use_openmp(omp)
         p0 = oracle.from_workload(w0)
@@ -108,8 +108,8 @@ def cpu_baseline(w, gpu_iters, gpu_cycles, restart=30, rtol=1e-8):
         while reps < 3 or time.perf_counter() - t0 < 1.0:
             _, r0 = p0.gmres(w0.f[0], rtol=rtol, restart=restart)
             reps += 1
-        cfg0[f"{nt}_threads"] = {"solves_per_s": reps / (time.perf_counter() - t0), "iters": r0["iters"]}
-    out["bump_64"] = cfg0
+        bump[f"{nt}_threads"] = {"solves_per_s": reps / (time.perf_counter() - t0), "iters": r0["iters"]}
+    out["bump_64"] = bump
     oracle.use_openmp(False)
     p1 = oracle.from_workload(w)
     t = {}
