@@ -76,11 +76,15 @@ template <typename R>
 constexpr int gen_smax(int k) {
   return sizeof(R) == 8 ? (k == kGenRows || k == kGenCols ? kGenStageMax : HP_GEN_SMAX64) : (k == kGenRows ? 12 : 8);
 }
+// (pass A picks between kGenStageMax and kGenRowSmaxLo per length: gen_rows_smax)
 constexpr int kGenMaxN = 4800;
 struct GenPlan {
   int n, nst, nthr, tc;
+  int smax;   // the stage-radix cap the plan was made for (selects the kernel)
   int radix[kGenMaxStages];
 };
+constexpr int kGenRowSmaxLo = 12;   // pass A's cap at three waves per SIMD
+int gen_rows_smax(int real_kind, int n);
 // Fills *gp for length n, E elements per thread and at most maxthr threads per
 // line; false if n is not a product of 2, 3 and 5 within kGenMaxN or does not fit.
 // order: radix schedule (0: the largest stage radix up to kGenStageMax that divides what

@@ -909,11 +909,11 @@ __device__ void gen_stage_twiddles(cpx<R>* stw, const GenPlan& gp, const cpx<R>*
   }
 }
 
-// Pass A: forward transform of rows of length gp.n.
-template <typename R, typename TI>
-__global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out,
-                                                       size_t in_rs, size_t out_rs, GenPlan gp,
-                                                       const cpx<R>* __restrict__ tw, const int* __restrict__ skip) {
+// Pass A: forward transform of rows of length gp.n (stage radices up to SM).
+template <typename R, typename TI, int SM>
+__device__ __forceinline__ void rows_fwd_gen_body(const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out,
+                                                  size_t in_rs, size_t out_rs, const GenPlan& gp,
+                                                  const cpx<R>* __restrict__ tw, const int* __restrict__ skip) {
   extern __shared__ char dyn_lds[];
   cpx<R>* buf = reinterpret_cast<cpx<R>*>(dyn_lds);
   const int rhs = blockIdx.y;
@@ -935,9 +935,24 @@ __global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict_
     }
   }
   __syncthreads();
-  fft_gen<R, -1, false, gen_smax<R>(kGenRows)>(buf, 0, gp, tw, tid);
+  fft_gen<R, -1, false, SM>(buf, 0, gp, tw, tid);
   cpx<R>* dst = out + (size_t)rhs * out_rs + row * n;
   for (int i = tid; i < n; i += gp.nthr) dst[i] = buf[gpos(i)];
+}
+// stage radices up to 16, two waves per SIMD (up to 256 VGPRs)
+template <typename R, typename TI>
+__global__ __launch_bounds__(512) void k_rows_fwd_gen(const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out,
+                                                       size_t in_rs, size_t out_rs, GenPlan gp,
+                                                       const cpx<R>* __restrict__ tw, const int* __restrict__ skip) {
+  rows_fwd_gen_body<R, TI, kGenStageMax>(in, out, in_rs, out_rs, gp, tw, skip);
+}
+// stage radices up to 12 at three waves per SIMD (168 VGPRs): three workgroups of
+// four wavefronts share a CU
+template <typename R, typename TI>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_rows_fwd_gen3(
+    const cpx<TI>* __restrict__ in, cpx<R>* __restrict__ out, size_t in_rs, size_t out_rs, GenPlan gp,
+    const cpx<R>* __restrict__ tw, const int* __restrict__ skip) {
+  rows_fwd_gen_body<R, TI, kGenRowSmaxLo>(in, out, in_rs, out_rs, gp, tw, skip);
 }
 
 // Strided axis, gp.tc adjacent columns per workgroup (their lines interleaved
@@ -1181,6 +1196,7 @@ bool make_gen_plan(int n, int E, int maxthr, GenPlan* gp, int order, int nthr_re
   GenPlan g{};
   g.n = n;
   g.tc = 1;
+  g.smax = smax;
   int m = n;
   if (order == 3) {   // radices 4, 2, 3, 5 only, each as often as it divides what is left
     for (int r : kPrimeOrder)
@@ -1233,13 +1249,27 @@ static bool tuned_gen_plan(int n, int E, int maxthr, const PassTune& t, GenPlan*
   return make_gen_plan(n, E, maxthr, gp, 0, 0, smax);
 }
 
+// Pass A's stage-radix cap for a mixed-radix row length: 12 (the kernel at three waves
+// per SIMD) unless that plan needs more threads than 256 and than the plan at 16 does
+// (the 5 of 2880 = 2^6 3^2 5 needs radix 10 and 288 threads under 12).
+int gen_rows_smax(int real_kind, int n) {
+  GenPlan lo, hi;
+  const bool okl = make_gen_plan(n, kGenRowE, 512, &lo, 0, 0, kGenRowSmaxLo);
+  const bool okh = make_gen_plan(n, kGenRowE, 512, &hi, 0, 0, kGenStageMax);
+  if (real_kind != 0) return kGenRowSmaxLo;
+  if (okl && (!okh || lo.nthr <= 256 || lo.nthr <= hi.nthr)) return kGenRowSmaxLo;
+  return okh ? kGenStageMax : kGenRowSmaxLo;
+}
+
 bool gen_length_ok(int n) {
   bool ok = true;
   for (int k = kGenRows; k <= kGenComb && ok; ++k) {
     GenPlan a;
     const int e64 = k == kGenRows ? kGenRowE : gen_e<double>(), e32 = k == kGenRows ? kGenRowE : gen_e<float>();
     const int t64 = k == kGenRows ? 512 : gen_maxthr<double>(), t32 = k == kGenRows ? 512 : gen_maxthr<float>();
-    ok = make_gen_plan(n, e64, t64, &a, 0, 0, gen_smax<double>(k)) && make_gen_plan(n, e32, t32, &a, 0, 0, gen_smax<float>(k));
+    const int s64 = k == kGenRows ? gen_rows_smax(0, n) : gen_smax<double>(k);
+    const int s32 = k == kGenRows ? gen_rows_smax(1, n) : gen_smax<float>(k);
+    ok = make_gen_plan(n, e64, t64, &a, 0, 0, s64) && make_gen_plan(n, e32, t32, &a, 0, 0, s32);
   }
   return ok;
 }
@@ -1291,7 +1321,8 @@ int tune_candidates(int real_kind, int kind, int n, int S, int mode, int K, Pass
   const int E = kind == kTuneRows ? kGenRowE : (real_kind == 0 ? gen_e<double>() : gen_e<float>());
   const int maxthr = kind == kTuneRows ? 512 : (real_kind == 0 ? gen_maxthr<double>() : gen_maxthr<float>());
   const int gk = kind == kTuneRows ? kGenRows : kind == kTuneCols ? (mode == 1 ? kGenSym : kGenCols) : kGenComb;
-  const int smax = real_kind == 0 ? gen_smax<double>(gk) : gen_smax<float>(gk);
+  const int smax = kind == kTuneRows ? gen_rows_smax(real_kind, n)
+                                     : (real_kind == 0 ? gen_smax<double>(gk) : gen_smax<float>(gk));
   for (int order = 0; order < kGenOrders; ++order) {
     GenPlan g;
     if (!make_gen_plan(n, E, maxthr, &g, order, 0, smax)) continue;
@@ -1332,9 +1363,15 @@ template <typename R, typename TI>
 static hipError_t rows_fwd_gen(const GenPlan& gp, const void* in, void* out, int rows, size_t in_rs, size_t out_rs,
                                int nrhs, const void* tw, const int* skip, hipStream_t st, const hipEvent_t* tev) {
   const size_t lds = gen_line_slots(gp.n) * sizeof(cpx<R>);
-  allow_dynamic_lds(k_rows_fwd_gen<R, TI>, lds);
-  HP_PASS_LAUNCH(tev, (k_rows_fwd_gen<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
-                 (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
+  if (gp.smax <= kGenRowSmaxLo) {
+    allow_dynamic_lds(k_rows_fwd_gen3<R, TI>, lds);
+    HP_PASS_LAUNCH(tev, (k_rows_fwd_gen3<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
+                   (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
+  } else {
+    allow_dynamic_lds(k_rows_fwd_gen<R, TI>, lds);
+    HP_PASS_LAUNCH(tev, (k_rows_fwd_gen<R, TI>), dim3(rows, nrhs), dim3(gp.nthr), lds, st, (const cpx<TI>*)in,
+                   (cpx<R>*)out, in_rs, out_rs, gp, (const cpx<R>*)tw, skip);
+  }
   return hipGetLastError();
 }
 
@@ -1391,8 +1428,7 @@ hipError_t launch_rows_fwd(int real_kind, int in_kind, int n, const void* in, vo
                            const PassTune& tune, hipStream_t st, const hipEvent_t* tev) {
   if (!is_pow2_len(n)) {
     GenPlan gp;
-    if (!tuned_gen_plan(n, kGenRowE, 512, tune, &gp, real_kind == 0 ? gen_smax<double>(kGenRows) : gen_smax<float>(kGenRows)))
-      return hipErrorInvalidValue;
+    if (!tuned_gen_plan(n, kGenRowE, 512, tune, &gp, gen_rows_smax(real_kind, n))) return hipErrorInvalidValue;
     if (real_kind == 0) {
       if (in_kind != 0) return hipErrorInvalidValue;
       return rows_fwd_gen<double, double>(gp, in, out, rows, in_rs, out_rs, nrhs, tw, skip, st, tev);
