@@ -1249,14 +1249,14 @@ static bool tuned_gen_plan(int n, int E, int maxthr, const PassTune& t, GenPlan*
   return make_gen_plan(n, E, maxthr, gp, 0, 0, smax);
 }
 
-// Pass A's stage-radix cap for a mixed-radix row length: 12 (the kernel at three waves
-// per SIMD) unless that plan needs more threads than 256 and than the plan at 16 does
-// (the 5 of 2880 = 2^6 3^2 5 needs radix 10 and 288 threads under 12).
+// Pass A's stage-radix cap for a mixed-radix row length (either precision): 12 (the
+// kernel at three waves per SIMD) unless that plan needs more threads than 256 and than
+// the plan at 16 does (the 5 of 2880 = 2^6 3^2 5 needs radix 10 and 288 threads under 12).
 int gen_rows_smax(int real_kind, int n) {
+  (void)real_kind;
   GenPlan lo, hi;
   const bool okl = make_gen_plan(n, kGenRowE, 512, &lo, 0, 0, kGenRowSmaxLo);
   const bool okh = make_gen_plan(n, kGenRowE, 512, &hi, 0, 0, kGenStageMax);
-  if (real_kind != 0) return kGenRowSmaxLo;
   if (okl && (!okh || lo.nthr <= 256 || lo.nthr <= hi.nthr)) return kGenRowSmaxLo;
   return okh ? kGenStageMax : kGenRowSmaxLo;
 }
